@@ -1,0 +1,133 @@
+/*
+ * hyperion_mi355x.h -- C ABI of the MI355X (gfx950) sparse state-vector
+ * library: the exact Hamiltonian-times-state product and the steps of
+ * state-vector ADAPT-VQE that live on it.
+ *
+ * Paper: "High Performance Quantum Emulation for Chemistry Applications with
+ * Hyperion" (arXiv 2604.01176), section "Sparse State-Vector Emulation":
+ * the Hamiltonian is assembled from qubit-mapped fermionic operators, the
+ * state lives in the symmetry-restricted configuration space Omega_CIk, and
+ * the operations needed are the matrix-vector product, inner products and
+ * the application of exponentiated fermionic operators.  ADAPT-VQE operator
+ * selection by pool gradients is described in "Numerical performance".
+ *
+ * Conventions
+ *   n = 2M qubits (M <= 16 spatial orbitals).  Qubit q < M is orbital q with
+ *   spin alpha, qubit q >= M is orbital q-M with spin beta; bit set =
+ *   occupied (Jordan-Wigner, |1> = occupied).
+ *   A Pauli string is P(x, z) = tensor_q sigma(x_q, z_q) with sigma(0,0)=I,
+ *   (1,0)=X, (0,1)=Z, (1,1)=Y; P|b> = i^{n_Y} (-1)^{popc(z&b)} |b xor x>.
+ *   Sector (N_alpha, N_beta): all b with popc(alpha bits) = N_alpha and
+ *   popc(beta bits) = N_beta.  Sector index
+ *     idx(b) = rank(beta) * C(M, N_alpha) + rank(alpha),
+ *     rank(s) = sum_{i=1..k} C(o_i, i) over set bits o_1 < ... < o_k,
+ *   i.e. the position of b among all sector bitstrings in ascending order.
+ *   Excitation hyp_exc{cre, ann}: qubit masks with |cre| = |ann| in {1, 2},
+ *   disjoint.  tau = a+_{c1} a+_{c2} a_{a2} a_{a1} (c1 < c2, a1 < a2) or
+ *   a+_c a_a; the generator is A = tau - tau^dagger (real antisymmetric).
+ *
+ * Buffers and streams
+ *   State, gradient and scalar output buffers belong to the caller: device
+ *   memory, contiguous, 8-byte aligned, FP64 (HYP_F64) or FP32 (HYP_F32)
+ *   amplitudes of length hyp_sector_dim().  The library owns hyp_sector and
+ *   hyp_ham objects and their device tables and frees them in *_destroy; it
+ *   never frees caller memory.  `stream` is a hipStream_t (NULL = default).
+ *   Every call validates all arguments before enqueuing anything; on error it
+ *   has no side effects and leaves outputs untouched.  HYP_OK means
+ *   validated and enqueued (asynchronous).  Scalar results are written to
+ *   device memory.  Calls that use a sector's internal scratch (marked
+ *   "scratch") must not overlap with each other on different streams for the
+ *   same sector.  No C++ exception crosses this interface.
+ */
+#ifndef HYPERION_MI355X_H
+#define HYPERION_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HYP_OK = 0,
+  HYP_ERR_ARG = 1,          /* null pointer, bad dtype, mask bit >= n, |cre| != |ann|, overlap */
+  HYP_ERR_SECTOR = 2,       /* excitation changes N_alpha or N_beta, or M > 16 */
+  HYP_ERR_NONREAL = 3,      /* Pauli term with odd n_Y (imaginary for a real H) */
+  HYP_ERR_NOMEM = 4,
+  HYP_ERR_HIP = 5,          /* HIP runtime failure; text in hyp_last_error() */
+  HYP_ERR_UNSUPPORTED = 6
+} hyp_status;
+
+typedef enum { HYP_F64 = 0, HYP_F32 = 1 } hyp_dtype;
+
+typedef struct hyp_sector_s* hyp_sector;
+typedef struct hyp_ham_s* hyp_ham;
+typedef struct { uint32_t cre, ann; } hyp_exc;
+
+/* Thread-local text of the last non-OK status of this thread. */
+const char* hyp_last_error(void);
+
+/* Sector (N_alpha, N_beta) of M spatial orbitals, the symmetry-restricted
+ * configuration space Omega_CIk ("Sparse State-Vector Emulation", Table 1).
+ * 1 <= M <= 16, 0 <= N <= M.  Uploads string and rank tables to the current
+ * device.  *out owned by the library until hyp_sector_destroy. */
+hyp_status hyp_sector_create(int n_orb, int n_alpha, int n_beta, hyp_sector* out);
+hyp_status hyp_sector_destroy(hyp_sector s);
+/* C(M, N_alpha) * C(M, N_beta); -1 for a NULL sector. */
+int64_t hyp_sector_dim(hyp_sector s);
+
+/* Host-side, bit-exact: sector index of each bitstring (-1 if outside the
+ * sector), and its inverse (HYP_ERR_ARG for an index outside [0, dim)).
+ * Host arrays of n elements. */
+hyp_status hyp_sector_rank(hyp_sector s, const uint32_t* bits, int64_t n, int64_t* idx);
+hyp_status hyp_sector_unrank(hyp_sector s, const int64_t* idx, int64_t n, uint32_t* bits);
+
+/* Assemble the Hamiltonian H = sum_t c_t P(x_t, z_t) for this sector
+ * ("Sparse State-Vector Emulation": H is obtained by summing the qubit-mapped
+ * fermionic operators; here it stays matrix-free as an X-mask-grouped Pauli
+ * table).  Host arrays of n_terms elements.  Duplicate (x, z) are summed.
+ * HYP_ERR_NONREAL for a nonzero term with odd n_Y; HYP_ERR_ARG for a mask
+ * bit >= 2M or n_terms < 0.  Terms that cannot connect two sector states
+ * are dropped.  Two-body number-conserving Hamiltonians (every Jordan-Wigner
+ * molecular Hamiltonian) use the structured gfx950 kernel; any other real
+ * Pauli sum uses a generic term-by-term kernel.  Synchronous upload on
+ * `stream`.  *out owned by the library until hyp_ham_destroy. */
+hyp_status hyp_build_hamiltonian(hyp_sector s, const uint32_t* x_mask, const uint32_t* z_mask,
+                                 const double* coeff, int64_t n_terms, void* stream,
+                                 hyp_ham* out);
+hyp_status hyp_ham_destroy(hyp_ham h);
+/* 1 if the structured kernel serves this Hamiltonian, 0 if the generic one, -1 on NULL. */
+int hyp_ham_is_structured(hyp_ham h);
+
+/* sigma = P_S H P_S psi (the paper's sparse matrix-vector product, computed
+ * matrix-free as a pull gather: each output amplitude is written once, no
+ * atomics).  psi and sigma: device, dim amplitudes of dtype, must not alias.
+ * HYP_F32: FP32 storage, FP32 products, FP64 accumulation. */
+hyp_status hyp_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* sigma_dev,
+                       void* stream);
+
+/* *out_dev = <a|b> = sum_i a_i b_i with FP64 accumulation (the sparse inner
+ * product / expectation value of "General Framework for Variational
+ * Algorithms", E = <psi|H psi>).  out_dev: one device double.  Scratch. */
+hyp_status hyp_expectation(hyp_sector s, hyp_dtype dtype, const void* a_dev, const void* b_dev,
+                           double* out_dev, void* stream);
+
+/* grad_dev[k] = 2 <sigma| A_k psi> for the n_ops generators in ops_dev
+ * (device array of hyp_exc), with sigma = H psi given: the ADAPT-VQE pool
+ * gradient dE/dtheta at theta = 0 of appending exp(theta A_k).  FP64 output,
+ * FP64 accumulation.  Every excitation is validated (host copy) first. */
+hyp_status hyp_pool_gradients(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_dev,
+                              int64_t n_ops, const void* psi_dev, const void* sigma_dev,
+                              double* grad_dev, void* stream);
+
+/* psi <- exp(theta A) psi in place (the exponentiated fermionic operator):
+ * on every pair (D, D' = tau D, sign s) psi_D <- cos psi_D - s sin psi_D',
+ * psi_D' <- s sin psi_D + cos psi_D'; other amplitudes unchanged. */
+hyp_status hyp_apply_excitation(hyp_sector s, hyp_dtype dtype, hyp_exc op, double theta,
+                                void* psi_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYPERION_MI355X_H */

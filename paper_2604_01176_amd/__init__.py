@@ -1,0 +1,173 @@
+"""MI355X (gfx950) sparse state-vector ADAPT-VQE hot path.
+
+Thin Python binding over the C ABI of libhyperion_mi355x.so: argument
+marshalling only.  Device buffers are torch tensors on the current HIP device
+and every call is enqueued on torch's current stream; all arithmetic runs in
+the library's HIP kernels.  Importing this package needs the built library
+(there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import HYP_F32, HYP_F64, HypError, HypExc, check
+
+__all__ = ["Sector", "Hamiltonian", "hyp_expectation", "hyp_pool_gradients",
+           "hyp_apply_excitation", "HypError", "HYP_F64", "HYP_F32", "exc_tensor"]
+
+_lib.load()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return HYP_F64
+    if t.dtype == torch.float32:
+        return HYP_F32
+    raise TypeError(f"state buffers must be float64 or float32, got {t.dtype}")
+
+
+def _dev_ptr(t, n=None, what="buffer"):
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{what} has {t.numel()} elements, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Sector:
+    """hyp_sector: the (N_alpha, N_beta) configuration space of n_orb orbitals."""
+
+    def __init__(self, n_orb: int, n_alpha: int, n_beta: int):
+        h = ctypes.c_void_p()
+        check(_lib.load().hyp_sector_create(n_orb, n_alpha, n_beta, ctypes.byref(h)))
+        self._h = h
+        self.n_orb, self.n_alpha, self.n_beta = n_orb, n_alpha, n_beta
+        self.dim = int(_lib.load().hyp_sector_dim(h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def rank(self, bits) -> np.ndarray:
+        bits = np.ascontiguousarray(bits, dtype=np.uint32)
+        out = np.empty(bits.shape, dtype=np.int64)
+        check(_lib.load().hyp_sector_rank(self._h, bits.ctypes.data, bits.size, out.ctypes.data))
+        return out
+
+    def unrank(self, idx) -> np.ndarray:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        out = np.empty(idx.shape, dtype=np.uint32)
+        check(_lib.load().hyp_sector_unrank(self._h, idx.ctypes.data, idx.size, out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().hyp_sector_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hamiltonian:
+    """hyp_ham: X-grouped Pauli table uploaded for one sector."""
+
+    def __init__(self, sector: Sector, x, z, c):
+        x = np.ascontiguousarray(x, dtype=np.uint32)
+        z = np.ascontiguousarray(z, dtype=np.uint32)
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        if not (x.shape == z.shape == c.shape and x.ndim == 1):
+            raise ValueError("x, z, c must be 1-D arrays of equal length")
+        h = ctypes.c_void_p()
+        check(_lib.load().hyp_build_hamiltonian(sector.handle, x.ctypes.data, z.ctypes.data,
+                                                c.ctypes.data, x.size, _stream(), ctypes.byref(h)))
+        self._h = h
+        self.sector = sector
+        self.structured = bool(_lib.load().hyp_ham_is_structured(h))
+
+    def apply(self, psi, out=None):
+        """sigma = H psi (hyp_apply_h)."""
+        if out is None:
+            out = _torch().empty_like(psi)
+        hyp_apply_h(self, psi, out)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().hyp_ham_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hyp_apply_h(ham: Hamiltonian, psi, sigma):
+    n = ham.sector.dim
+    if psi.dtype != sigma.dtype:
+        raise TypeError("psi and sigma dtypes differ")
+    check(_lib.load().hyp_apply_h(ham._h, _dtype_code(psi), _dev_ptr(psi, n, "psi"),
+                                  _dev_ptr(sigma, n, "sigma"), _stream()))
+    return sigma
+
+
+def hyp_expectation(sector: Sector, a, b, out=None):
+    """<a|b> into a 1-element float64 device tensor."""
+    torch = _torch()
+    if a.dtype != b.dtype:
+        raise TypeError("a and b dtypes differ")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=a.device)
+    check(_lib.load().hyp_expectation(sector.handle, _dtype_code(a), _dev_ptr(a, sector.dim, "a"),
+                                      _dev_ptr(b, sector.dim, "b"), _dev_ptr(out, 1, "out"),
+                                      _stream()))
+    return out
+
+
+def exc_tensor(cre, ann, device="cuda"):
+    """Pack (cre, ann) masks into an int32 [n, 2] device tensor laid out as
+    the hyp_exc array."""
+    torch = _torch()
+    arr = np.stack([np.asarray(cre, dtype=np.uint32), np.asarray(ann, dtype=np.uint32)], axis=1)
+    return torch.from_numpy(arr.view(np.int32).copy()).to(device)
+
+
+def hyp_pool_gradients(sector: Sector, ops, psi, sigma, out=None):
+    torch = _torch()
+    if ops.dtype != torch.int32 or ops.dim() != 2 or ops.shape[1] != 2:
+        raise TypeError("ops must be an int32 [n, 2] tensor of (cre, ann) masks")
+    n = ops.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=psi.device)
+    check(_lib.load().hyp_pool_gradients(sector.handle, _dtype_code(psi), _dev_ptr(ops, None, "ops"), n,
+                                         _dev_ptr(psi, sector.dim, "psi"),
+                                         _dev_ptr(sigma, sector.dim, "sigma"),
+                                         _dev_ptr(out, n, "grad"), _stream()))
+    return out
+
+
+def hyp_apply_excitation(sector: Sector, cre: int, ann: int, theta: float, psi):
+    check(_lib.load().hyp_apply_excitation(sector.handle, _dtype_code(psi), HypExc(int(cre), int(ann)),
+                                           float(theta), _dev_ptr(psi, sector.dim, "psi"), _stream()))
+    return psi

@@ -1,0 +1,71 @@
+"""ctypes declarations of libhyperion_mi355x.so (the C ABI in
+include/hyperion_mi355x.h).  Loading fails loudly when the library is
+missing: there is no CPU fallback."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhyperion_mi355x.so")
+
+HYP_OK, HYP_ERR_ARG, HYP_ERR_SECTOR, HYP_ERR_NONREAL, HYP_ERR_NOMEM, HYP_ERR_HIP, HYP_ERR_UNSUPPORTED = range(7)
+HYP_F64, HYP_F32 = 0, 1
+STATUS_NAMES = {0: "HYP_OK", 1: "HYP_ERR_ARG", 2: "HYP_ERR_SECTOR", 3: "HYP_ERR_NONREAL",
+                4: "HYP_ERR_NOMEM", 5: "HYP_ERR_HIP", 6: "HYP_ERR_UNSUPPORTED"}
+
+
+class HypExc(ctypes.Structure):
+    _fields_ = [("cre", ctypes.c_uint32), ("ann", ctypes.c_uint32)]
+
+
+class HypError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_ci = ctypes.c_int
+_d = ctypes.c_double
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "hyp_last_error": (ctypes.c_char_p, []),
+    "hyp_sector_create": (_ci, [_ci, _ci, _ci, ctypes.POINTER(_vp)]),
+    "hyp_sector_destroy": (_ci, [_vp]),
+    "hyp_sector_dim": (_i64, [_vp]),
+    "hyp_sector_rank": (_ci, [_vp, _vp, _i64, _vp]),
+    "hyp_sector_unrank": (_ci, [_vp, _vp, _i64, _vp]),
+    "hyp_build_hamiltonian": (_ci, [_vp, _vp, _vp, _vp, _i64, _vp, ctypes.POINTER(_vp)]),
+    "hyp_ham_destroy": (_ci, [_vp]),
+    "hyp_ham_is_structured": (_ci, [_vp]),
+    "hyp_apply_h": (_ci, [_vp, _ci, _vp, _vp, _vp]),
+    "hyp_expectation": (_ci, [_vp, _ci, _vp, _vp, _vp, _vp]),
+    "hyp_pool_gradients": (_ci, [_vp, _ci, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "hyp_apply_excitation": (_ci, [_vp, _ci, HypExc, _d, _vp, _vp]),
+}
+
+_lib = None
+
+
+def load():
+    """Load the library (built by __graft_entry__.build / build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != HYP_OK:
+        raise HypError(status, load().hyp_last_error().decode(errors="replace"))

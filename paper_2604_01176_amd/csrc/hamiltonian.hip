@@ -1,0 +1,937 @@
+// Matrix-free sigma = P_S H P_S psi on gfx950 for a Pauli-sum Hamiltonian
+// grouped by X-mask (paper, "Sparse State-Vector Emulation": the sparse
+// Hamiltonian-state product that dominates ADAPT-VQE; here the CSR matrix is
+// never formed, each output amplitude pulls from its connected inputs).
+//
+// Build: the Pauli terms are grouped by x.  For an in-sector output d, a term
+// contributes c' (-1)^{popc(z & d)} psi[d xor x], c' = c (-1)^{n_Y/2}.  For a
+// two-body number-conserving Hamiltonian every group folds, exactly, into a
+// small closed form over d's occupations (HamDev in hyp_internal.h).  The
+// per-output work is then split by which spin the excitation touches:
+//   same-spin part  (diagonal in the other spin's string):  a sparse
+//       string-space matrix applied to whole rows -- kernel k_same_spin, run
+//       once on psi (beta rows) and once on psi^T (alpha rows);
+//   mixed part (alpha-beta doubles, the other-spin number dressing of singles,
+//       the alpha-beta diagonal): kernel k_mixed, one workgroup per beta row
+//       with the needed source rows staged through LDS.
+// Any real Pauli sum outside that class falls back to k_generic, a
+// term-by-term pull over X-groups.
+#include "hyp_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+
+namespace hyp {
+Sector* sector_of(hyp_sector h);
+
+// ---------------------------------------------------------------- helpers
+
+__host__ __device__ inline int pair_id(int p, int q) { return q * (q - 1) / 2 + p; }  // p < q
+
+__host__ __device__ inline int choose_small(int m, int k) {
+  // C(m, k) for m < 16, k <= 4 (quad ids)
+  if (k > m || m < 0) return 0;
+  int r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (m - k + i) / i;
+  return r;
+}
+
+__host__ __device__ inline int quad_id(int o0, int o1, int o2, int o3) {
+  return choose_small(o0, 1) + choose_small(o1, 2) + choose_small(o2, 3) + choose_small(o3, 4);
+}
+
+template <typename T>
+struct Acc;  // storage type -> product rules
+template <>
+struct Acc<double> {
+  __device__ static inline double prod(double c, double v) { return c * v; }
+  __device__ static inline double load(const double* p) { return *p; }
+};
+template <>
+struct Acc<float> {
+  // FP32 product, FP64 accumulation by the caller
+  __device__ static inline double prod(double c, float v) { return (double)((float)c * v); }
+  __device__ static inline double load(const float* p) { return (double)*p; }
+};
+
+__device__ inline double flip(double v, uint32_t odd) {
+  // multiply by (-1)^odd without a multiply: toggle the sign bit
+  uint64_t u = __double_as_longlong(v) ^ ((uint64_t)(odd & 1u) << 63);
+  return __longlong_as_double(u);
+}
+
+// ---------------------------------------------------------------- transpose
+
+template <typename T>
+__global__ void k_transpose(const T* __restrict__ in, T* __restrict__ out, int rows, int cols) {
+  // in[rows][cols] -> out[cols][rows], 64x64 tiles through LDS
+  __shared__ T tile[64][65];
+  int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 256 threads: 4 rows per pass
+  for (int r = ty; r < 64; r += 4) {
+    int rr = r0 + r, cc = c0 + tx;
+    if (rr < rows && cc < cols) tile[r][tx] = in[(int64_t)rr * cols + cc];
+  }
+  __syncthreads();
+  for (int c = ty; c < 64; c += 4) {
+    int cc = c0 + c, rr = r0 + tx;
+    if (rr < rows && cc < cols) out[(int64_t)cc * rows + rr] = tile[tx][c];
+  }
+}
+
+// ---------------------------------------------------------------- same-spin rows
+
+struct SameSpinArgs {
+  const void* in;         // [nrow][ncol] storage T
+  double* out;            // [nrow][ncol] FP64 partial
+  int nrow, ncol;
+  int M, nel;             // orbitals, electrons of the row spin
+  int spin;               // 0 alpha rows, 1 beta rows
+  const uint32_t* rstr;   // [nrow] row strings
+  const RankTables* rrank;
+  double constant;        // added to every diagonal (the identity term), once
+  HamDev H;
+};
+
+constexpr int kSameSpinMax = 1 + 64 + 784;  // self + singles + doubles for M <= 16
+constexpr int kSSThreads = 256;
+constexpr int kSSCols = 4;                  // columns per thread
+
+// out[r][c] = sum_{r'} Hs[r][r'] in[r'][c]: Hs = same-spin part of H in the
+// row spin (pure-spin diagonal, singles with same-spin number dressing,
+// same-spin doubles).  One workgroup per (row, column chunk).
+template <typename T>
+__global__ void __launch_bounds__(kSSThreads) k_same_spin(SameSpinArgs a) {
+  __shared__ int s_rank[kSameSpinMax];
+  __shared__ double s_coef[kSameSpinMax];
+  __shared__ int s_n;
+  const int row = blockIdx.y;
+  const uint32_t s = a.rstr[row];
+  const int off = a.spin * a.M;  // qubit offset of this spin
+  const uint32_t smask = (1u << a.M) - 1u;
+  if (threadIdx.x == 0) {
+    // self term
+    double e = a.constant;
+    uint32_t o1 = s;
+    while (o1) {
+      int k = __ffs(o1) - 1;
+      o1 &= o1 - 1;
+      e += a.H.dB[k + off];
+      uint32_t o2 = o1;
+      while (o2) {
+        int l = __ffs(o2) - 1;
+        o2 &= o2 - 1;
+        e += a.H.dC[(k + off) * 32 + (l + off)];
+      }
+    }
+    s_rank[0] = row;
+    s_coef[0] = e;
+    s_n = 1;
+  }
+  __syncthreads();
+  // singles: thread t handles pair (i occupied, a empty) number t
+  {
+    const int nemp = a.M - a.nel;
+    const int ns = a.nel * nemp;
+    for (int t = threadIdx.x; t < ns; t += blockDim.x) {
+      int io = t / nemp, ie = t % nemp;
+      // io-th occupied and ie-th empty orbital
+      uint32_t occ = s, emp = ~s & smask;
+      for (int j = 0; j < io; ++j) occ &= occ - 1;
+      for (int j = 0; j < ie; ++j) emp &= emp - 1;
+      int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
+      int p = min(i, e), q = max(i, e);
+      int pid = pair_id(p, q);
+      int O = (i == q) ? 1 : 0;
+      const int base = (a.spin * kMaxPairs + pid);
+      double v = a.H.sA[base * 2 + O];
+      const double* B = a.H.sB + (size_t)(base * 2 + O) * 32;
+      uint32_t oc = s;
+      while (oc) {
+        int k = __ffs(oc) - 1;
+        oc &= oc - 1;
+        v += B[k + off];
+      }
+      uint32_t J = a.H.sJ[base] >> off;
+      v = flip(v, __popc(J & s));
+      uint32_t t2 = s ^ (1u << i) ^ (1u << e);
+      s_rank[1 + t] = a.rrank->lo[t2 & 255u] + a.rrank->hi[(t2 >> 8) & 255u];
+      s_coef[1 + t] = v;
+    }
+    // doubles: (i<j occupied) x (a<b empty)
+    const int no2 = a.nel * (a.nel - 1) / 2, ne2 = nemp * (nemp - 1) / 2;
+    const int nd = no2 * ne2;
+    for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+      int po = t / ne2, pe = t % ne2;
+      // decode pair index po into (jo > io) among occupied list by colex
+      int jo = 1;
+      while ((jo + 1) * jo / 2 <= po) ++jo;
+      int io = po - jo * (jo - 1) / 2;
+      int je = 1;
+      while ((je + 1) * je / 2 <= pe) ++je;
+      int ie = pe - je * (je - 1) / 2;
+      uint32_t occ = s, emp = ~s & smask;
+      int oi = -1, oj = -1, ea = -1, eb = -1;
+      for (int c = 0; occ; ++c) {
+        int k = __ffs(occ) - 1;
+        occ &= occ - 1;
+        if (c == io) oi = k;
+        if (c == jo) oj = k;
+      }
+      for (int c = 0; emp; ++c) {
+        int k = __ffs(emp) - 1;
+        emp &= emp - 1;
+        if (c == ie) ea = k;
+        if (c == je) eb = k;
+      }
+      // sorted quad and occupied pattern
+      int q4[4] = {oi, oj, ea, eb};
+      for (int x = 1; x < 4; ++x)
+        for (int y = x; y > 0 && q4[y - 1] > q4[y]; --y) {
+          int tmp = q4[y];
+          q4[y] = q4[y - 1];
+          q4[y - 1] = tmp;
+        }
+      int O4 = 0;
+      for (int x = 0; x < 4; ++x)
+        if (q4[x] == oi || q4[x] == oj) O4 |= 1 << x;
+      int qid = quad_id(q4[0], q4[1], q4[2], q4[3]);
+      const int base = a.spin * kMaxQuads + qid;
+      double v = a.H.wF[(size_t)base * 16 + O4];
+      uint32_t J = a.H.wJ[base] >> off;
+      v = flip(v, __popc(J & s));
+      uint32_t t2 = s ^ (1u << oi) ^ (1u << oj) ^ (1u << ea) ^ (1u << eb);
+      s_rank[1 + ns + t] = a.rrank->lo[t2 & 255u] + a.rrank->hi[(t2 >> 8) & 255u];
+      s_coef[1 + ns + t] = v;
+    }
+    if (threadIdx.x == 0) s_n = 1 + ns + nd;
+  }
+  __syncthreads();
+  const int n = s_n;
+  const T* in = (const T*)a.in;
+  const int c0 = blockIdx.x * (kSSThreads * kSSCols) + threadIdx.x;
+  double acc[kSSCols];
+#pragma unroll
+  for (int k = 0; k < kSSCols; ++k) acc[k] = 0.0;
+  for (int e = 0; e < n; ++e) {
+    const T* src = in + (int64_t)s_rank[e] * a.ncol;
+    const double cf = s_coef[e];
+#pragma unroll
+    for (int k = 0; k < kSSCols; ++k) {
+      int c = c0 + k * kSSThreads;
+      if (c < a.ncol) acc[k] += Acc<T>::prod(cf, src[c]);
+    }
+  }
+  double* dst = a.out + (int64_t)row * a.ncol;
+#pragma unroll
+  for (int k = 0; k < kSSCols; ++k) {
+    int c = c0 + k * kSSThreads;
+    if (c < a.ncol) dst[c] = acc[k];
+  }
+}
+
+// ---------------------------------------------------------------- mixed rows
+
+struct MixedArgs {
+  const void* psi;        // [db][da] storage T
+  const double* pa_t;     // alpha same-spin partial, transposed [da][db]
+  const double* pb;       // beta same-spin partial [db][da]
+  void* sigma;            // [db][da] storage T
+  int M, na, nb, da, db;
+  const uint32_t* astr;
+  const uint32_t* bstr;
+  const RankTables* arank;
+  const RankTables* brank;
+  HamDev H;
+};
+
+// sigma[b][a] = pb[b][a] + pa_t[a][b] + (mixed alpha-beta part of H psi)[b][a]
+// One workgroup per beta row; EPT alpha columns per thread; the row's own
+// psi row and each beta-single source row are staged in LDS in turn.
+template <typename T, int EPT>
+__global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* s_row = (T*)smem;  // [da]
+  __shared__ int32_t s_lo[256], s_hi[256];
+  __shared__ uint32_t s_jsa[kMaxPairs], s_abja[kMaxPairs];
+  __shared__ double s_dmix[kMaxOrb];
+  __shared__ double s_srow[kMaxPairs * 2];
+  __shared__ double s_fab[kMaxPairs * 2];
+  __shared__ double s_bdress[kMaxOrb];
+  __shared__ int s_brank;
+  __shared__ double s_bscale;
+
+  const int brow = blockIdx.x;
+  const uint32_t bs = a.bstr[brow];
+  const int M = a.M;
+  const uint32_t amask = (1u << M) - 1u;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const HamDev& H = a.H;
+
+  for (int i = tid; i < 256; i += nt) {
+    s_lo[i] = a.arank->lo[i];
+    s_hi[i] = a.arank->hi[i];
+  }
+  for (int i = tid; i < kMaxPairs; i += nt) {
+    s_jsa[i] = H.sJ[i];  // alpha singles: J lies in alpha bits
+    s_abja[i] = H.abJa[i];
+  }
+  for (int k = tid; k < M; k += nt) {
+    // alpha orbital k couples to the occupied beta orbitals on the diagonal
+    double v = 0.0;
+    uint32_t o = bs;
+    while (o) {
+      int l = __ffs(o) - 1;
+      o &= o - 1;
+      v += H.dC[k * 32 + (l + M)];
+    }
+    s_dmix[k] = v;
+  }
+  for (int i = tid; i < kMaxPairs * 2; i += nt) {
+    // alpha singles: beta-occupation dressing (row constant)
+    const double* B = H.sB + (size_t)i * 32;
+    double v = 0.0;
+    uint32_t o = bs;
+    while (o) {
+      int l = __ffs(o) - 1;
+      o &= o - 1;
+      v += B[l + M];
+    }
+    s_srow[i] = v;
+  }
+  const T* psi = (const T*)a.psi;
+  const T* prow = psi + (int64_t)brow * a.da;
+  for (int i = tid; i < a.da; i += nt) s_row[i] = prow[i];
+  __syncthreads();
+
+  double acc[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) acc[k] = 0.0;
+
+  // (1) alpha-beta diagonal and alpha singles' beta dressing (source row = own row)
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int col = tid + k * nt;
+    if (col < a.da) {
+      const uint32_t s = a.astr[col];
+      double v = 0.0;
+      uint32_t o = s;
+      while (o) {
+        int i = __ffs(o) - 1;
+        o &= o - 1;
+        v += s_dmix[i];
+      }
+      double sum = Acc<T>::prod(v, s_row[col]);
+      uint32_t occ = s;
+      while (occ) {
+        int i = __ffs(occ) - 1;
+        occ &= occ - 1;
+        uint32_t emp = ~s & amask;
+        while (emp) {
+          int e = __ffs(emp) - 1;
+          emp &= emp - 1;
+          int p = min(i, e), q = max(i, e);
+          int pid = pair_id(p, q);
+          int O = (i == q) ? 1 : 0;
+          uint32_t t2 = s ^ (1u << i) ^ (1u << e);
+          int r2 = s_lo[t2 & 255u] + s_hi[(t2 >> 8) & 255u];
+          double cf = flip(s_srow[pid * 2 + O], __popc(s_jsa[pid] & s));
+          sum += Acc<T>::prod(cf, s_row[r2]);
+        }
+      }
+      acc[k] += sum;
+    }
+  }
+
+  // (2) beta singles: number dressing by alpha occupations + alpha-beta doubles
+  const int nbemp = M - a.nb;
+  const int nbs = a.nb * nbemp;
+  const uint32_t bmask = amask;
+  for (int jb = 0; jb < nbs; ++jb) {
+    __syncthreads();
+    // decode the jb-th beta single excitation (identical in every thread)
+    int io = jb / nbemp, ie = jb % nbemp;
+    uint32_t occ = bs, emp = ~bs & bmask;
+    for (int j = 0; j < io; ++j) occ &= occ - 1;
+    for (int j = 0; j < ie; ++j) emp &= emp - 1;
+    const int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
+    const int p = min(i, e), q = max(i, e);
+    const int pb = pair_id(p, q);
+    const int Ob = (i == q) ? 1 : 0;
+    const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
+    if (tid == 0) s_brank = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
+    // beta single: (-1)^{popc(J & beta)} (A + sum_{beta occ} B + sum_{alpha occ} B)
+    // the beta-only part is in the same-spin pass; here the alpha-occupation part
+    const int sbase = (kMaxPairs + pb) * 2 + Ob;
+    const uint32_t jsb = H.sJ[kMaxPairs + pb] >> M;
+    const double sgn_s = (__popc(jsb & bs) & 1) ? -1.0 : 1.0;
+    for (int k = tid; k < M; k += nt) s_bdress[k] = sgn_s * H.sB[(size_t)sbase * 32 + k];
+    // alpha-beta doubles with this beta excitation: F'[pa][Oa]
+    const double sgn_ab = (__popc((H.abJb[pb] >> M) & bs) & 1) ? -1.0 : 1.0;
+    for (int x = tid; x < kMaxPairs * 2; x += nt) {
+      int pa = x >> 1, Oa = x & 1;
+      s_fab[x] = sgn_ab * H.abF[((size_t)pa * kMaxPairs + pb) * 4 + Oa * 2 + Ob];
+    }
+    __syncthreads();
+    const T* src = psi + (int64_t)s_brank * a.da;
+    for (int c = tid; c < a.da; c += nt) s_row[c] = src[c];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int col = tid + k * nt;
+      if (col < a.da) {
+        const uint32_t s = a.astr[col];
+        double dr = 0.0;
+        uint32_t o = s;
+        while (o) {
+          int kk = __ffs(o) - 1;
+          o &= o - 1;
+          dr += s_bdress[kk];
+        }
+        double sum = Acc<T>::prod(dr, s_row[col]);
+        uint32_t occ2 = s;
+        while (occ2) {
+          int ii = __ffs(occ2) - 1;
+          occ2 &= occ2 - 1;
+          uint32_t emp2 = ~s & amask;
+          while (emp2) {
+            int ee = __ffs(emp2) - 1;
+            emp2 &= emp2 - 1;
+            int pp = min(ii, ee), qq = max(ii, ee);
+            int pa = pair_id(pp, qq);
+            int Oa = (ii == qq) ? 1 : 0;
+            uint32_t t2 = s ^ (1u << ii) ^ (1u << ee);
+            int r2 = s_lo[t2 & 255u] + s_hi[(t2 >> 8) & 255u];
+            double cf = flip(s_fab[pa * 2 + Oa], __popc(s_abja[pa] & s));
+            sum += Acc<T>::prod(cf, s_row[r2]);
+          }
+        }
+        acc[k] += sum;
+      }
+    }
+  }
+
+  // (3) combine with the two same-spin partials and store
+  T* out = (T*)a.sigma + (int64_t)brow * a.da;
+  const double* pbr = a.pb + (int64_t)brow * a.da;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int col = tid + k * nt;
+    if (col < a.da) {
+      double v = acc[k] + pbr[col] + a.pa_t[(int64_t)col * a.db + brow];
+      out[col] = (T)v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- generic
+
+struct GenericArgs {
+  const void* psi;
+  void* sigma;
+  int M, na, nb, da;
+  int64_t dim;
+  const uint32_t* astr;
+  const uint32_t* bstr;
+  const RankTables* arank;
+  const RankTables* brank;
+  int64_t ngroup;
+  const uint32_t* gx;
+  const int64_t* goff;
+  const uint32_t* tz;
+  const double* tc;
+};
+
+// One thread per output amplitude, every X-group in turn (any real Pauli sum).
+template <typename T>
+__global__ void k_generic(GenericArgs a) {
+  int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= a.dim) return;
+  const uint32_t amask = (1u << a.M) - 1u;
+  const uint32_t bd = a.astr[d % a.da] | (a.bstr[d / a.da] << a.M);
+  const T* psi = (const T*)a.psi;
+  double acc = 0.0;
+  for (int64_t g = 0; g < a.ngroup; ++g) {
+    const uint32_t b = bd ^ a.gx[g];
+    const uint32_t ba = b & amask, bb = b >> a.M;
+    if (__popc(ba) != a.na || __popc(bb) != a.nb) continue;
+    const int64_t src = (int64_t)(a.brank->lo[bb & 255u] + a.brank->hi[(bb >> 8) & 255u]) * a.da +
+                        (a.arank->lo[ba & 255u] + a.arank->hi[(ba >> 8) & 255u]);
+    double cf = 0.0;
+    for (int64_t t = a.goff[g]; t < a.goff[g + 1]; ++t) cf += flip(a.tc[t], __popc(a.tz[t] & bd));
+    acc += Acc<T>::prod(cf, psi[src]);
+  }
+  ((T*)a.sigma)[d] = (T)acc;
+}
+
+// ---------------------------------------------------------------- launch
+
+struct HamWork {
+  void* psi_t = nullptr;      // transposed psi, storage size of the largest dtype (8 B)
+  double* part_a = nullptr;   // [da][db]
+  double* part_b = nullptr;   // [db][da]
+};
+
+static int pick_ept(int da, int* threads) {
+  static const int opts[5] = {1, 2, 4, 8, 16};
+  for (int e : opts) {
+    int nt = ((da + e - 1) / e + 63) / 64 * 64;
+    if (nt <= 1024) {
+      *threads = std::max(nt, 64);
+      return e;
+    }
+  }
+  *threads = 1024;
+  return 16;
+}
+
+template <typename T>
+static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sigma,
+                                 hipStream_t st) {
+  Sector* S = Hm->sec;
+  const int da = (int)S->da, db = (int)S->db;
+  // psi^T for the alpha-row pass
+  dim3 tg((da + 63) / 64, (db + 63) / 64);
+  hipLaunchKernelGGL(k_transpose<T>, tg, dim3(256), 0, st, (const T*)psi, (T*)W->psi_t, db, da);
+  SameSpinArgs sa;
+  sa.H = Hm->dev;
+  sa.M = S->M;
+  // alpha rows (over psi^T): rows = alpha strings, columns = beta strings
+  sa.in = W->psi_t;
+  sa.out = W->part_a;
+  sa.nrow = da;
+  sa.ncol = db;
+  sa.nel = S->na;
+  sa.spin = 0;
+  sa.rstr = S->d_astr;
+  sa.rrank = S->d_arank;
+  sa.constant = 0.0;
+  dim3 ga((db + kSSThreads * kSSCols - 1) / (kSSThreads * kSSCols), da);
+  hipLaunchKernelGGL(k_same_spin<T>, ga, dim3(kSSThreads), 0, st, sa);
+  // beta rows (over psi), carrying the constant (identity) term once
+  sa.in = psi;
+  sa.out = W->part_b;
+  sa.nrow = db;
+  sa.ncol = da;
+  sa.nel = S->nb;
+  sa.spin = 1;
+  sa.rstr = S->d_bstr;
+  sa.rrank = S->d_brank;
+  sa.constant = Hm->dev.dA;
+  dim3 gb((da + kSSThreads * kSSCols - 1) / (kSSThreads * kSSCols), db);
+  hipLaunchKernelGGL(k_same_spin<T>, gb, dim3(kSSThreads), 0, st, sa);
+  MixedArgs ma;
+  ma.psi = psi;
+  ma.pa_t = W->part_a;
+  ma.pb = W->part_b;
+  ma.sigma = sigma;
+  ma.M = S->M;
+  ma.na = S->na;
+  ma.nb = S->nb;
+  ma.da = da;
+  ma.db = db;
+  ma.astr = S->d_astr;
+  ma.bstr = S->d_bstr;
+  ma.arank = S->d_arank;
+  ma.brank = S->d_brank;
+  ma.H = Hm->dev;
+  int nt = Hm->threads, ept = Hm->ept;
+  size_t shm = (size_t)da * sizeof(T);
+  switch (ept) {
+#define HYP_MIXED(E)                                                                         \
+  case E:                                                                                    \
+    if (shm > 48 * 1024)                                                                     \
+      HYP_HIP(hipFuncSetAttribute((const void*)k_mixed<T, E>,                                \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));    \
+    hipLaunchKernelGGL((k_mixed<T, E>), dim3(db), dim3(nt), shm, st, ma);                    \
+    break;
+    HYP_MIXED(1)
+    HYP_MIXED(2)
+    HYP_MIXED(4)
+    HYP_MIXED(8)
+    HYP_MIXED(16)
+#undef HYP_MIXED
+    default:
+      return fail(HYP_ERR_UNSUPPORTED, "k_mixed: no instantiation for this shape");
+  }
+  HYP_HIP(hipGetLastError());
+  return HYP_OK;
+}
+
+template <typename T>
+static hyp_status run_generic(Ham* Hm, const void* psi, void* sigma, hipStream_t st) {
+  Sector* S = Hm->sec;
+  GenericArgs g;
+  g.psi = psi;
+  g.sigma = sigma;
+  g.M = S->M;
+  g.na = S->na;
+  g.nb = S->nb;
+  g.da = (int)S->da;
+  g.dim = S->dim;
+  g.astr = S->d_astr;
+  g.bstr = S->d_bstr;
+  g.arank = S->d_arank;
+  g.brank = S->d_brank;
+  g.ngroup = Hm->n_groups;
+  g.gx = Hm->d_gx;
+  g.goff = Hm->d_goff;
+  g.tz = Hm->d_tz;
+  g.tc = Hm->d_tc;
+  int64_t blocks = (S->dim + 255) / 256;
+  hipLaunchKernelGGL(k_generic<T>, dim3((unsigned)blocks), dim3(256), 0, st, g);
+  HYP_HIP(hipGetLastError());
+  return HYP_OK;
+}
+
+}  // namespace hyp
+
+using namespace hyp;
+
+struct hyp_ham_s {
+  Ham h;
+  HamWork w;
+};
+
+namespace {
+
+struct TermIn {
+  uint32_t x, z;
+  double c;
+};
+
+inline int popc(uint32_t v) { return __builtin_popcount(v); }
+
+// Fold the X-groups into the structured tables.  Returns false if some group
+// does not have the two-body closed form (then the generic kernel is used).
+bool fold_structured(int M, const std::vector<TermIn>& t, const std::vector<int64_t>& goff,
+                     std::vector<double>& dB, std::vector<double>& dC, double& dA,
+                     std::vector<uint32_t>& sJ, std::vector<double>& sA, std::vector<double>& sB,
+                     std::vector<uint32_t>& wJ, std::vector<double>& wF,
+                     std::vector<uint32_t>& abJa, std::vector<uint32_t>& abJb,
+                     std::vector<double>& abF, std::string& why) {
+  const int n = 2 * M;
+  const uint32_t amask = (1u << M) - 1u;
+  const uint32_t bmask_q = amask << M;
+  dA = 0.0;
+  dB.assign(32, 0.0);
+  dC.assign(32 * 32, 0.0);
+  sJ.assign(2 * kMaxPairs, 0u);
+  sA.assign(2 * kMaxPairs * 2, 0.0);
+  sB.assign(2 * kMaxPairs * 2 * 32, 0.0);
+  wJ.assign(2 * kMaxQuads, 0u);
+  wF.assign((size_t)2 * kMaxQuads * 16, 0.0);
+  abJa.assign(kMaxPairs, 0u);
+  abJb.assign(kMaxPairs, 0u);
+  abF.assign((size_t)kMaxPairs * kMaxPairs * 4, 0.0);
+  std::vector<char> haveA(kMaxPairs, 0), haveB(kMaxPairs, 0);
+  const size_t G = goff.size() - 1;
+  for (size_t g = 0; g < G; ++g) {
+    const uint32_t x = t[goff[g]].x;
+    const uint32_t xa = x & amask, xb = (x >> M) & amask;
+    const int ka = popc(xa), kb = popc(xb);
+    if (ka == 0 && kb == 0) {
+      for (int64_t i = goff[g]; i < goff[g + 1]; ++i) {
+        const uint32_t z = t[i].z;
+        const double c = t[i].c;
+        const int w = popc(z);
+        if (w > 2) {
+          why = "diagonal term with more than two Z";
+          return false;
+        }
+        // (-1)^{n_k} = 1 - 2 n_k ; (-1)^{n_k + n_l} = 1 - 2n_k - 2n_l + 4 n_k n_l
+        dA += c;
+        if (w >= 1) {
+          int k = __builtin_ctz(z);
+          dB[k] -= 2.0 * c;
+          if (w == 2) {
+            int l = 31 - __builtin_clz(z);
+            dB[l] -= 2.0 * c;
+            dC[k * 32 + l] += 4.0 * c;
+          }
+        }
+      }
+    } else if ((ka == 2 && kb == 0) || (ka == 0 && kb == 2)) {
+      const int spin = ka ? 0 : 1;
+      const uint32_t xs = ka ? xa : xb;
+      const int p = __builtin_ctz(xs), q = 31 - __builtin_clz(xs);
+      const int pid = pair_id(p, q);
+      const uint32_t spin_q = spin ? bmask_q : amask;
+      // find J with every z_out in {J} or {J xor e_k}
+      const uint32_t z0 = t[goff[g]].z & ~x;
+      uint32_t J = 0;
+      bool found = false;
+      for (int cand = -1; cand < n && !found; ++cand) {
+        uint32_t Jc = cand < 0 ? z0 : (z0 ^ (1u << cand));
+        if (Jc & x) continue;
+        bool ok = true;
+        for (int64_t i = goff[g]; i < goff[g + 1] && ok; ++i)
+          if (popc((t[i].z & ~x) ^ Jc) > 1) ok = false;
+        if (ok) {
+          J = Jc;
+          found = true;
+        }
+      }
+      if (!found || (J & ~spin_q)) {
+        why = "single-excitation group without a number-dressed form";
+        return false;
+      }
+      sJ[spin * kMaxPairs + pid] = J;
+      for (int O = 0; O < 2; ++O) {
+        const uint32_t Om = (O ? (1u << q) : (1u << p)) << (spin * M);
+        double F0 = 0.0;
+        double Fk[32] = {0};
+        for (int64_t i = goff[g]; i < goff[g + 1]; ++i) {
+          const double v = (popc(t[i].z & Om) & 1) ? -t[i].c : t[i].c;
+          const uint32_t r = (t[i].z & ~x) ^ J;
+          if (r == 0)
+            F0 += v;
+          else
+            Fk[__builtin_ctz(r)] += v;
+        }
+        double a0 = F0;
+        for (int k = 0; k < n; ++k) a0 += Fk[k];
+        sA[(spin * kMaxPairs + pid) * 2 + O] = a0;
+        for (int k = 0; k < n; ++k) sB[((size_t)(spin * kMaxPairs + pid) * 2 + O) * 32 + k] = -2.0 * Fk[k];
+      }
+    } else if ((ka == 4 && kb == 0) || (ka == 0 && kb == 4)) {
+      const int spin = ka ? 0 : 1;
+      const uint32_t xs = ka ? xa : xb;
+      int o[4], c = 0;
+      for (int k = 0; k < M; ++k)
+        if (xs & (1u << k)) o[c++] = k;
+      const int qid = quad_id(o[0], o[1], o[2], o[3]);
+      const uint32_t zo = t[goff[g]].z & ~x;
+      const uint32_t spin_q = spin ? bmask_q : amask;
+      for (int64_t i = goff[g]; i < goff[g + 1]; ++i)
+        if ((t[i].z & ~x) != zo) {
+          why = "same-spin double group with several Z strings";
+          return false;
+        }
+      if (zo & ~spin_q) {
+        why = "same-spin double group with a Z string on the other spin";
+        return false;
+      }
+      wJ[spin * kMaxQuads + qid] = zo;
+      for (int O4 = 0; O4 < 16; ++O4) {
+        if (popc(O4) != 2) continue;
+        uint32_t Om = 0;
+        for (int k = 0; k < 4; ++k)
+          if (O4 & (1 << k)) Om |= 1u << o[k];
+        Om <<= spin * M;
+        double v = 0.0;
+        for (int64_t i = goff[g]; i < goff[g + 1]; ++i)
+          v += (popc(t[i].z & Om) & 1) ? -t[i].c : t[i].c;
+        wF[((size_t)spin * kMaxQuads + qid) * 16 + O4] = v;
+      }
+    } else if (ka == 2 && kb == 2) {
+      const int pa_lo = __builtin_ctz(xa), pa_hi = 31 - __builtin_clz(xa);
+      const int pb_lo = __builtin_ctz(xb), pb_hi = 31 - __builtin_clz(xb);
+      const int pa = pair_id(pa_lo, pa_hi), pb = pair_id(pb_lo, pb_hi);
+      const uint32_t zo = t[goff[g]].z & ~x;
+      for (int64_t i = goff[g]; i < goff[g + 1]; ++i)
+        if ((t[i].z & ~x) != zo) {
+          why = "alpha-beta group with several Z strings";
+          return false;
+        }
+      const uint32_t za = zo & amask, zb = zo & bmask_q;
+      if ((haveA[pa] && abJa[pa] != za) || (haveB[pb] && abJb[pb] != zb)) {
+        why = "alpha-beta Z strings do not factor by spin";
+        return false;
+      }
+      haveA[pa] = haveB[pb] = 1;
+      abJa[pa] = za;
+      abJb[pb] = zb;
+      for (int Oa = 0; Oa < 2; ++Oa)
+        for (int Ob = 0; Ob < 2; ++Ob) {
+          const uint32_t Om = (Oa ? (1u << pa_hi) : (1u << pa_lo)) |
+                              ((Ob ? (1u << pb_hi) : (1u << pb_lo)) << M);
+          double v = 0.0;
+          for (int64_t i = goff[g]; i < goff[g + 1]; ++i)
+            v += (popc(t[i].z & Om) & 1) ? -t[i].c : t[i].c;
+          abF[((size_t)pa * kMaxPairs + pb) * 4 + Oa * 2 + Ob] = v;
+        }
+    } else {
+      why = "X-mask outside the two-body classes";
+      return false;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+hyp_status hyp_build_hamiltonian(hyp_sector sh, const uint32_t* x_mask, const uint32_t* z_mask,
+                                 const double* coeff, int64_t n_terms, void* stream,
+                                 hyp_ham* out) {
+  Sector* S = sector_of(sh);
+  if (!S || !out) return fail(HYP_ERR_ARG, "hyp_build_hamiltonian: NULL sector or out");
+  if (n_terms < 0) return fail(HYP_ERR_ARG, "hyp_build_hamiltonian: n_terms < 0");
+  if (n_terms > 0 && (!x_mask || !z_mask || !coeff))
+    return fail(HYP_ERR_ARG, "hyp_build_hamiltonian: NULL term array");
+  const int M = S->M, n = 2 * M;
+  const uint32_t all = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
+  const uint32_t amask = (1u << M) - 1u;
+  std::vector<TermIn> t;
+  t.reserve((size_t)n_terms);
+  for (int64_t i = 0; i < n_terms; ++i) {
+    if ((x_mask[i] & ~all) || (z_mask[i] & ~all))
+      return fail(HYP_ERR_ARG, "hyp_build_hamiltonian: mask bit >= 2*n_orb");
+    if (!std::isfinite(coeff[i])) return fail(HYP_ERR_ARG, "hyp_build_hamiltonian: non-finite coefficient");
+    if ((popc(x_mask[i] & z_mask[i]) & 1) && coeff[i] != 0.0)
+      return fail(HYP_ERR_NONREAL, "hyp_build_hamiltonian: odd number of Y (imaginary coefficient)");
+    t.push_back({x_mask[i], z_mask[i], coeff[i]});
+  }
+  std::stable_sort(t.begin(), t.end(), [](const TermIn& a, const TermIn& b) {
+    return a.x != b.x ? a.x < b.x : a.z < b.z;
+  });
+  // merge duplicates, c' = c (-1)^{n_Y/2}, drop exact zeros and groups that
+  // cannot connect two states of this sector
+  std::vector<TermIn> m;
+  for (size_t i = 0; i < t.size();) {
+    size_t j = i;
+    double c = 0.0;
+    while (j < t.size() && t[j].x == t[i].x && t[j].z == t[i].z) c += t[j++].c;
+    const uint32_t x = t[i].x, xa = x & amask, xb = (x >> M) & amask;
+    const int ka = popc(xa), kb = popc(xb);
+    bool connects = !(ka & 1) && !(kb & 1) && ka / 2 <= std::min(S->na, M - S->na) &&
+                    kb / 2 <= std::min(S->nb, M - S->nb);
+    if (c != 0.0 && connects) {
+      if ((popc(x & t[i].z) / 2) & 1) c = -c;
+      m.push_back({x, t[i].z, c});
+    }
+    i = j;
+  }
+  std::vector<int64_t> goff;
+  for (size_t i = 0; i < m.size(); ++i)
+    if (i == 0 || m[i].x != m[i - 1].x) goff.push_back((int64_t)i);
+  goff.push_back((int64_t)m.size());
+  if (m.empty()) goff.assign(1, 0);
+
+  hyp_ham_s* hh = new (std::nothrow) hyp_ham_s();
+  if (!hh) return fail(HYP_ERR_NOMEM, "hyp_build_hamiltonian: host allocation");
+  Ham& H = hh->h;
+  H.sec = S;
+  H.n_terms = (int64_t)m.size();
+  H.n_groups = (int64_t)goff.size() - 1;
+  hipStream_t st = (hipStream_t)stream;
+
+  std::vector<double> dB, dC, sA, sB, wF, abF;
+  std::vector<uint32_t> sJ, wJ, abJa, abJb;
+  double dA = 0.0;
+  std::string why;
+  H.structured = fold_structured(M, m, goff, dB, dC, dA, sJ, sA, sB, wJ, wF, abJa, abJb, abF, why);
+
+  std::vector<uint32_t> gx(H.n_groups), tz(m.size());
+  std::vector<double> tc(m.size());
+  for (int64_t g = 0; g < H.n_groups; ++g) gx[g] = m[goff[g]].x;
+  for (size_t i = 0; i < m.size(); ++i) {
+    tz[i] = m[i].z;
+    tc[i] = m[i].c;
+  }
+  auto cleanup_fail = [&](hipError_t e, const char* what) {
+    hyp_ham_destroy(hh);
+    return hip_fail(e, what);
+  };
+  hipError_t e = hipSuccess;
+  e = hipMalloc(&H.d_gx, std::max<size_t>(1, gx.size()) * 4);
+  if (e == hipSuccess) e = hipMalloc(&H.d_goff, goff.size() * 8);
+  if (e == hipSuccess) e = hipMalloc(&H.d_tz, std::max<size_t>(1, tz.size()) * 4);
+  if (e == hipSuccess) e = hipMalloc(&H.d_tc, std::max<size_t>(1, tc.size()) * 8);
+  if (e == hipSuccess && !gx.empty()) e = hipMemcpyAsync(H.d_gx, gx.data(), gx.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(H.d_goff, goff.data(), goff.size() * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !tz.empty()) e = hipMemcpyAsync(H.d_tz, tz.data(), tz.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !tc.empty()) e = hipMemcpyAsync(H.d_tc, tc.data(), tc.size() * 8, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return cleanup_fail(e, "hyp_build_hamiltonian: generic table upload");
+
+  if (H.structured) {
+    // one blob: doubles first, then u32 tables
+    size_t nd = dB.size() + dC.size() + sA.size() + sB.size() + wF.size() + abF.size();
+    size_t nu = sJ.size() + wJ.size() + abJa.size() + abJb.size();
+    std::vector<unsigned char> blob(nd * 8 + nu * 4);
+    size_t off = 0;
+    auto putd = [&](const std::vector<double>& v) {
+      size_t o = off;
+      std::memcpy(blob.data() + off, v.data(), v.size() * 8);
+      off += v.size() * 8;
+      return o;
+    };
+    auto putu = [&](const std::vector<uint32_t>& v) {
+      size_t o = off;
+      std::memcpy(blob.data() + off, v.data(), v.size() * 4);
+      off += v.size() * 4;
+      return o;
+    };
+    size_t o_dB = putd(dB), o_dC = putd(dC), o_sA = putd(sA), o_sB = putd(sB), o_wF = putd(wF),
+           o_abF = putd(abF);
+    size_t o_sJ = putu(sJ), o_wJ = putu(wJ), o_abJa = putu(abJa), o_abJb = putu(abJb);
+    e = hipMalloc(&H.d_blob, blob.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(H.d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return cleanup_fail(e, "hyp_build_hamiltonian: structured table upload");
+    unsigned char* b = (unsigned char*)H.d_blob;
+    H.dev.dA = dA;
+    H.dev.dB = (const double*)(b + o_dB);
+    H.dev.dC = (const double*)(b + o_dC);
+    H.dev.sA = (const double*)(b + o_sA);
+    H.dev.sB = (const double*)(b + o_sB);
+    H.dev.wF = (const double*)(b + o_wF);
+    H.dev.abF = (const double*)(b + o_abF);
+    H.dev.sJ = (const uint32_t*)(b + o_sJ);
+    H.dev.wJ = (const uint32_t*)(b + o_wJ);
+    H.dev.abJa = (const uint32_t*)(b + o_abJa);
+    H.dev.abJb = (const uint32_t*)(b + o_abJb);
+    H.ept = pick_ept((int)S->da, &H.threads);
+    // workspace: psi^T and the two same-spin partials
+    e = hipMalloc(&hh->w.psi_t, (size_t)S->dim * 8);
+    if (e == hipSuccess) e = hipMalloc(&hh->w.part_a, (size_t)S->dim * 8);
+    if (e == hipSuccess) e = hipMalloc(&hh->w.part_b, (size_t)S->dim * 8);
+    if (e != hipSuccess) return cleanup_fail(e, "hyp_build_hamiltonian: workspace");
+  }
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return cleanup_fail(e, "hyp_build_hamiltonian: upload sync");
+  if (!H.structured) set_error(std::string("generic kernel: ") + why);
+  *out = hh;
+  return HYP_OK;
+}
+
+hyp_status hyp_ham_destroy(hyp_ham hh) {
+  if (!hh) return HYP_OK;
+  Ham& H = hh->h;
+  (void)hipFree(H.d_gx);
+  (void)hipFree(H.d_goff);
+  (void)hipFree(H.d_tz);
+  (void)hipFree(H.d_tc);
+  (void)hipFree(H.d_blob);
+  (void)hipFree(hh->w.psi_t);
+  (void)hipFree(hh->w.part_a);
+  (void)hipFree(hh->w.part_b);
+  delete hh;
+  return HYP_OK;
+}
+
+int hyp_ham_is_structured(hyp_ham hh) { return hh ? (hh->h.structured ? 1 : 0) : -1; }
+
+hyp_status hyp_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* sigma, void* stream) {
+  if (!hh || !psi || !sigma) return fail(HYP_ERR_ARG, "hyp_apply_h: NULL argument");
+  if (dtype != HYP_F64 && dtype != HYP_F32) return fail(HYP_ERR_ARG, "hyp_apply_h: bad dtype");
+  if (psi == sigma) return fail(HYP_ERR_ARG, "hyp_apply_h: psi and sigma alias");
+  Ham* H = &hh->h;
+  hipStream_t st = (hipStream_t)stream;
+  if (H->structured) {
+    if (dtype == HYP_F64) return run_structured<double>(H, &hh->w, psi, sigma, st);
+    return run_structured<float>(H, &hh->w, psi, sigma, st);
+  }
+  if (dtype == HYP_F64) return run_generic<double>(H, psi, sigma, st);
+  return run_generic<float>(H, psi, sigma, st);
+}
+
+}  // extern "C"
+
+namespace hyp {
+Ham* ham_of(hyp_ham h) { return h ? &h->h : nullptr; }
+}  // namespace hyp

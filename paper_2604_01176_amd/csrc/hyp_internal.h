@@ -1,0 +1,126 @@
+// Internal declarations of the gfx950 state-vector library (not part of the
+// public C ABI).  Host objects, device table layouts and launch helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hyperion_mi355x.h"
+
+namespace hyp {
+
+constexpr int kMaxOrb = 16;           // n <= 32 qubits
+constexpr int kMaxPairs = 120;        // C(16,2)
+constexpr int kMaxQuads = 1820;       // C(16,4)
+
+// Thread-local error text behind hyp_last_error().
+void set_error(const std::string& msg);
+hyp_status fail(hyp_status st, const std::string& msg);
+hyp_status hip_fail(hipError_t e, const char* what);
+
+#define HYP_HIP(call)                                            \
+  do {                                                           \
+    hipError_t e_ = (call);                                      \
+    if (e_ != hipSuccess) return ::hyp::hip_fail(e_, #call);     \
+  } while (0)
+
+// Split colex rank: for a k-subset s of {0..M-1},
+//   rank(s) = lo[s & 255] + hi[s >> 8]
+// because the position of every high bit among the set bits depends only on
+// how many bits the low byte holds, which is k - popc(s >> 8).
+struct RankTables {
+  int32_t lo[256];
+  int32_t hi[256];
+};
+
+// Device-side description of a sector (passed by value to kernels).
+struct SectorDev {
+  int M, na, nb;
+  int da, db;             // C(M,na), C(M,nb)
+  int64_t dim;
+  const uint32_t* astr;   // [da] alpha string of each alpha rank
+  const uint32_t* bstr;   // [db]
+  const RankTables* arank;  // device copies
+  const RankTables* brank;
+};
+
+struct Sector {
+  int M = 0, na = 0, nb = 0;
+  int64_t da = 0, db = 0, dim = 0;
+  std::vector<uint32_t> h_astr, h_bstr;
+  RankTables h_arank{}, h_brank{};
+  uint32_t* d_astr = nullptr;
+  uint32_t* d_bstr = nullptr;
+  RankTables* d_arank = nullptr;
+  RankTables* d_brank = nullptr;
+  double* d_scratch = nullptr;      // reduction partials (kScratch doubles)
+  double* d_pair = nullptr;         // chunk partials of the pair kernels (grow-only)
+  size_t pair_cap = 0;
+  int device = 0;
+  SectorDev dev() const {
+    SectorDev s;
+    s.M = M; s.na = na; s.nb = nb; s.da = (int)da; s.db = (int)db; s.dim = dim;
+    s.astr = d_astr; s.bstr = d_bstr; s.arank = d_arank; s.brank = d_brank;
+    return s;
+  }
+};
+constexpr int kScratch = 8192;
+constexpr int kDotBlocks = 1024;
+
+// ---------------------------------------------------------------------------
+// X-grouped Hamiltonian, structured form.
+//
+// Every Pauli term (x, z, c) with even n_Y becomes, on in-sector outputs d,
+// c' (-1)^{popc(z & d)} with c' = c (-1)^{n_Y/2}.  Terms are grouped by x;
+// each group is folded at build time into a closed evaluation over the
+// occupation pattern of d (see hamiltonian.hip).  The classes of x that can
+// connect two states of one (N_a, N_b) sector under a two-body Hamiltonian:
+//   diag     x = 0
+//   single   2 bits of one spin       (index: spin, pair id)
+//   double   4 bits of one spin       (index: spin, quad id)
+//   ab       2 alpha + 2 beta bits    (index: alpha pair id, beta pair id)
+// ---------------------------------------------------------------------------
+struct HamDev {
+  // diagonal: E(d) = dA + sum_{k in occ} dB[k] + sum_{k<l in occ} dC[k][l]
+  double dA;
+  const double* dB;        // [32]
+  const double* dC;        // [32*32] (upper triangle used)
+  // singles, per spin s and pair id p (p = q(q-1)/2 + lo, lo < q):
+  //   v(d) = (-1)^{popc(sJ & d)} (sA[O] + sum_{k in occ(d), k not in x} sB[O][k])
+  //   O = 1 if the upper orbital of the pair is occupied in d, else 0
+  const uint32_t* sJ;      // [2][120]
+  const double* sA;        // [2][120][2]
+  const double* sB;        // [2][120][2][32]
+  // same-spin doubles, per spin and quad id (colex rank of the 4-subset):
+  //   v(d) = (-1)^{popc(wJ & d)} wF[O4], O4 = 4-bit mask of which sorted
+  //   orbitals of the quad are occupied in d
+  const uint32_t* wJ;      // [2][1820]
+  const double* wF;        // [2][1820][16]
+  // alpha-beta doubles: v(d) = (-1)^{popc(abJa[pa] & d)} (-1)^{popc(abJb[pb] & d)}
+  //   abF[pa][pb][Oa*2+Ob]
+  const uint32_t* abJa;    // [120]
+  const uint32_t* abJb;    // [120]
+  const double* abF;       // [120][120][4]
+};
+
+struct Ham {
+  Sector* sec = nullptr;
+  bool structured = false;
+  // structured tables (one device allocation)
+  void* d_blob = nullptr;
+  HamDev dev{};
+  // generic form: groups sorted by x
+  int64_t n_terms = 0, n_groups = 0;
+  uint32_t* d_gx = nullptr;        // [G] x mask
+  int64_t* d_goff = nullptr;       // [G+1] term offsets
+  uint32_t* d_tz = nullptr;        // [T] z mask
+  double* d_tc = nullptr;          // [T] c' = c (-1)^{n_Y/2}
+  // launch tuning for the structured kernel
+  int threads = 0, ept = 0;
+};
+
+hyp_status launch_dot(Sector* S, hyp_dtype dt, const void* a, const void* b, double* out,
+                      hipStream_t st);
+
+}  // namespace hyp
