@@ -1,0 +1,187 @@
+"""Benchmark of the state-vector ADAPT-VQE hot path on one MI355X.
+
+One step = one pass of the whole hot path over the resident synthetic state:
+sigma = H psi (FP64), the energy <psi|sigma>, the full pool-gradient sweep
+g_k = 2 <sigma|A_k psi>, and one exponentiated-operator rotation of psi.
+Prints one JSON line.  The headline value is the H psi rate in GB/s under the
+gather model (every structural nonzero's source amplitude read once, the
+output written once, plus the Pauli table), measured with HIP events on the
+stream the kernels run on.  The oracle leg times the plain CPU oracle on a
+bounded sample of output rows of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_VECTOR_TFLOPS = 78.6    # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz
+
+
+def model(M, na, nb, T, pool):
+    """Closed-form sizes of the workload (per H psi / per sweep)."""
+    da, db = math.comb(M, na), math.comb(M, nb)
+    dim = da * db
+    sa, sb = na * (M - na), nb * (M - nb)
+    dda = math.comb(na, 2) * math.comb(M - na, 2)
+    ddb = math.comb(nb, 2) * math.comb(M - nb, 2)
+    conn = 1 + sa + sb + dda + ddb + sa * sb
+    nnz = dim * conn
+    pairs = (nnz - dim) // 2
+    return dict(dim=dim, da=da, db=db, conn=conn, nnz=nnz, pairs=pairs, sa=sa, sb=sb,
+                dda=dda, ddb=ddb, T=T, pool=pool)
+
+
+def hpsi_gather_bytes(m, S=8):
+    return (m["nnz"] + m["dim"]) * S + 16 * m["T"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="h16_32q")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="approximate CPU time budget of the oracle leg (0 disables it)")
+    ap.add_argument("--no-sweep", action="store_true", help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the row-partitioned design is described, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2604_01176_amd as hyp
+
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    M, na, nb = w.n_orb, w.n_alpha, w.n_beta
+    t0 = time.time()
+    x, z, c, _, _ = synth.hamiltonian(w)
+    cre, ann, cls = synth.canonical_pool(M)
+    m = model(M, na, nb, len(c), len(cre))
+    print(f"[bench] {w.name}: dim {m['dim']}, {m['T']} Pauli terms, pool {m['pool']}, "
+          f"inputs built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    S = hyp.Sector(M, na, nb)
+    H = hyp.Hamiltonian(S, x, z, c)
+    assert H.structured
+    psi_h = synth.random_state(S.dim, 7)
+    psi = torch.from_numpy(psi_h).cuda()
+    sig = torch.empty_like(psi)
+    ops = hyp.exc_tensor(cre, ann)
+    grad = torch.empty(len(cre), dtype=torch.float64, device="cuda")
+    e_dev = torch.empty(1, dtype=torch.float64, device="cuda")
+    k_rot = int(np.nonzero(cls == 4)[0][0])
+
+    def step():
+        hyp.hyp_apply_h(H, psi, sig)
+        hyp.hyp_expectation(S, psi, sig, e_dev)
+        if not args.no_sweep:
+            hyp.hyp_pool_gradients(S, ops, psi, sig, grad)
+        hyp.hyp_apply_excitation(S, int(cre[k_rot]), int(ann[k_rot]), 1e-3, psi)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    hyp.profile_reset()
+    hyp.profile_enable(True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for i in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    hyp.profile_enable(False)
+    step_ms = ev0.elapsed_time(ev1) / args.steps
+    prof = hyp.profile_read()
+    print(f"[bench] timed {args.steps} steps: {step_ms:.2f} ms/step", file=sys.stderr, flush=True)
+    for k_, (ms, n) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
+        print(f"[bench]   {k_:20s} {ms / max(n, 1):10.3f} ms/launch x {n}", file=sys.stderr)
+
+    hpsi_kernels = ("k_transpose", "k_same_spin", "k_mixed")
+    hpsi_ms = sum(prof.get(k, (0.0, 0))[0] for k in hpsi_kernels) / args.steps
+    hpsi_bytes = hpsi_gather_bytes(m)
+    value = hpsi_bytes / (hpsi_ms * 1e-3) / 1e9
+    sweep_ms = sum(prof.get(k, (0.0, 0))[0] for k in ("k_pool_grad", "k_sum_chunks")) / args.steps
+
+    # dominant kernel of the step and its roofline
+    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    dom_ms = prof[dom][0] / prof[dom][1]
+    if dom == "k_mixed":
+        # alpha-beta doubles + the beta-single dressing and the alpha-beta diagonal:
+        # one FMA per structural nonzero handled by this kernel
+        flops = 2.0 * m["dim"] * (m["sa"] * m["sb"] + m["sa"] + m["sb"] + 1)
+    elif dom == "k_same_spin":
+        flops = 2.0 * m["dim"] * (1 + (m["sa"] + m["dda"] + m["sb"] + m["ddb"]) / 2)
+    elif dom == "k_pool_grad":
+        flops = 4.0 * m["pairs"]
+    else:
+        flops = 2.0 * m["nnz"]
+    achieved = flops / (dom_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
+            "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_VECTOR_TFLOPS, 4), "traffic": None,
+            "ms_per_launch": round(dom_ms, 3)}
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        import oracle
+        rng = np.random.default_rng(0)
+        sig_h = None
+        n_try = 64
+        t = time.time()
+        oracle.apply_h(M, na, nb, x, z, c, psi_h, out_idx=rng.integers(0, S.dim, n_try))
+        dt = time.time() - t
+        n_rows = int(max(n_try, min(5_000_000, n_try * args.cpu_seconds / max(dt, 1e-6))))
+        idx = rng.integers(0, S.dim, n_rows)
+        t = time.time()
+        oracle.apply_h(M, na, nb, x, z, c, psi_h, out_idx=idx)
+        dt = time.time() - t
+        row_bytes = (m["conn"] + 1) * 8
+        cpu = {"value": round(n_rows * row_bytes / dt / 1e9, 4), "unit": "GB/s",
+               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+               "kind": "oracle",
+               "sample": f"{n_rows} random output rows of H psi ({dt:.1f} s), gather-model bytes"}
+        del sig_h
+
+    out = {
+        "metric": "H psi GB/s (gather model) + pool-grad evals/s",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {2 * M} qubits, sector ({na},{nb}), dim {m['dim']}, "
+                               f"{m['T']} Pauli terms, pool {m['pool']}",
+                   "parallelism": "1 GPU"},
+        "hpsi_ms": round(hpsi_ms, 3),
+        "hpsi_frac_hbm_gather_model": round(value / HBM_PEAK_GBS, 4),
+        "pool_grad_evals_per_s": round(m["pool"] / (sweep_ms * 1e-3), 1) if sweep_ms > 0 else None,
+        "sweep_ms": round(sweep_ms, 3),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

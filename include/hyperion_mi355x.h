@@ -126,6 +126,17 @@ hyp_status hyp_pool_gradients(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_
 hyp_status hyp_apply_excitation(hyp_sector s, hyp_dtype dtype, hyp_exc op, double theta,
                                 void* psi_dev, void* stream);
 
+/* Kernel timing (tracing).  While enabled, every kernel the library launches
+ * is bracketed by HIP events on its stream; hyp_profile_count() waits for
+ * the recorded events and returns the number of distinct kernel names, and
+ * hyp_profile_get(i, ...) returns the i-th name (NUL-terminated, truncated
+ * to name_len), its summed device time in ms and its launch count.
+ * Intended for measurement runs; enable before the calls to be timed. */
+hyp_status hyp_profile_enable(int on);
+hyp_status hyp_profile_reset(void);
+int hyp_profile_count(void);
+hyp_status hyp_profile_get(int i, char* name, int name_len, double* total_ms, int64_t* calls);
+
 #ifdef __cplusplus
 }
 #endif

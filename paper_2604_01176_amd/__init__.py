@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import HYP_F32, HYP_F64, HypError, HypExc, check
 
-__all__ = ["Sector", "Hamiltonian", "hyp_expectation", "hyp_pool_gradients",
+__all__ = ["profile_enable", "profile_reset", "profile_read", "Sector", "Hamiltonian", "hyp_expectation", "hyp_pool_gradients",
            "hyp_apply_excitation", "HypError", "HYP_F64", "HYP_F32", "exc_tensor"]
 
 _lib.load()
@@ -171,3 +171,24 @@ def hyp_apply_excitation(sector: Sector, cre: int, ann: int, theta: float, psi):
     check(_lib.load().hyp_apply_excitation(sector.handle, _dtype_code(psi), HypExc(int(cre), int(ann)),
                                            float(theta), _dev_ptr(psi, sector.dim, "psi"), _stream()))
     return psi
+
+
+def profile_enable(on: bool = True):
+    check(_lib.load().hyp_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    check(_lib.load().hyp_profile_reset())
+
+
+def profile_read() -> dict:
+    """{kernel name: (total device ms, launches)} of the events recorded so far."""
+    L = _lib.load()
+    out = {}
+    for i in range(L.hyp_profile_count()):
+        buf = ctypes.create_string_buffer(128)
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(L.hyp_profile_get(i, buf, 128, ctypes.byref(ms), ctypes.byref(n)))
+        out[buf.value.decode()] = (ms.value, n.value)
+    return out

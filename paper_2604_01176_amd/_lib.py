@@ -45,6 +45,10 @@ SIGNATURES = {
     "hyp_expectation": (_ci, [_vp, _ci, _vp, _vp, _vp, _vp]),
     "hyp_pool_gradients": (_ci, [_vp, _ci, _vp, _i64, _vp, _vp, _vp, _vp]),
     "hyp_apply_excitation": (_ci, [_vp, _ci, HypExc, _d, _vp, _vp]),
+    "hyp_profile_enable": (_ci, [_ci]),
+    "hyp_profile_reset": (_ci, []),
+    "hyp_profile_count": (_ci, []),
+    "hyp_profile_get": (_ci, [_ci, ctypes.c_char_p, _ci, ctypes.POINTER(_d), ctypes.POINTER(_i64)]),
 }
 
 _lib = None

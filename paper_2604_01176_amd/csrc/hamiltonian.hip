@@ -495,7 +495,7 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   const int da = (int)S->da, db = (int)S->db;
   // psi^T for the alpha-row pass
   dim3 tg((da + 63) / 64, (db + 63) / 64);
-  hipLaunchKernelGGL(k_transpose<T>, tg, dim3(256), 0, st, (const T*)psi, (T*)W->psi_t, db, da);
+  HYP_LAUNCH("k_transpose", k_transpose<T>, tg, dim3(256), 0, st, (const T*)psi, (T*)W->psi_t, db, da);
   SameSpinArgs sa;
   sa.H = Hm->dev;
   sa.M = S->M;
@@ -510,7 +510,7 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   sa.rrank = S->d_arank;
   sa.constant = 0.0;
   dim3 ga((db + kSSThreads * kSSCols - 1) / (kSSThreads * kSSCols), da);
-  hipLaunchKernelGGL(k_same_spin<T>, ga, dim3(kSSThreads), 0, st, sa);
+  HYP_LAUNCH("k_same_spin", k_same_spin<T>, ga, dim3(kSSThreads), 0, st, sa);
   // beta rows (over psi), carrying the constant (identity) term once
   sa.in = psi;
   sa.out = W->part_b;
@@ -522,7 +522,7 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   sa.rrank = S->d_brank;
   sa.constant = Hm->dev.dA;
   dim3 gb((da + kSSThreads * kSSCols - 1) / (kSSThreads * kSSCols), db);
-  hipLaunchKernelGGL(k_same_spin<T>, gb, dim3(kSSThreads), 0, st, sa);
+  HYP_LAUNCH("k_same_spin", k_same_spin<T>, gb, dim3(kSSThreads), 0, st, sa);
   MixedArgs ma;
   ma.psi = psi;
   ma.pa_t = W->part_a;
@@ -546,7 +546,7 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
     if (shm > 48 * 1024)                                                                     \
       HYP_HIP(hipFuncSetAttribute((const void*)k_mixed<T, E>,                                \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));    \
-    hipLaunchKernelGGL((k_mixed<T, E>), dim3(db), dim3(nt), shm, st, ma);                    \
+    HYP_LAUNCH("k_mixed", (k_mixed<T, E>), dim3(db), dim3(nt), shm, st, ma);                    \
     break;
     HYP_MIXED(1)
     HYP_MIXED(2)
@@ -582,7 +582,7 @@ static hyp_status run_generic(Ham* Hm, const void* psi, void* sigma, hipStream_t
   g.tz = Hm->d_tz;
   g.tc = Hm->d_tc;
   int64_t blocks = (S->dim + 255) / 256;
-  hipLaunchKernelGGL(k_generic<T>, dim3((unsigned)blocks), dim3(256), 0, st, g);
+  HYP_LAUNCH("k_generic", k_generic<T>, dim3((unsigned)blocks), dim3(256), 0, st, g);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
 }

@@ -19,6 +19,23 @@ void set_error(const std::string& msg);
 hyp_status fail(hyp_status st, const std::string& msg);
 hyp_status hip_fail(hipError_t e, const char* what);
 
+// Event bracket around one launch (active only while profiling is enabled).
+class ProfScope {
+ public:
+  ProfScope(const char* name, hipStream_t st);
+  ~ProfScope();
+ private:
+  const char* name_;
+  hipStream_t st_;
+  void* a_ = nullptr;
+};
+
+#define HYP_LAUNCH(name, kernel, grid, block, shm, st, ...)              \
+  do {                                                                   \
+    ::hyp::ProfScope ps_(name, st);                                      \
+    hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);       \
+  } while (0)
+
 #define HYP_HIP(call)                                            \
   do {                                                           \
     hipError_t e_ = (call);                                      \

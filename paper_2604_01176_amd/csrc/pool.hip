@@ -359,9 +359,9 @@ static hyp_status launch_pool_grad(Sector* S, const hyp_exc* ops, int64_t n_ops,
   hyp_status r = pair_scratch(S, (size_t)n_ops * kPairChunks, &part);
   if (r != HYP_OK) return r;
   // grid.x is limited to 2^31-1, n_ops <= 40k here
-  hipLaunchKernelGGL(k_pool_grad<T>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0, st,
+  HYP_LAUNCH("k_pool_grad", k_pool_grad<T>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0, st,
                      S->dev(), ops, (const T*)psi, (const T*)sig, part);
-  hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((n_ops + 255) / 256)), dim3(256), 0, st, part,
+  HYP_LAUNCH("k_sum_chunks", k_sum_chunks, dim3((unsigned)((n_ops + 255) / 256)), dim3(256), 0, st, part,
                      n_ops, 2.0, grad);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
@@ -391,10 +391,10 @@ hyp_status launch_rotate(Sector* S, hyp_dtype dt, hyp_exc op, double theta, void
   int nch = rot_chunks(S, op);
   double co = std::cos(theta), sn = std::sin(theta);
   if (dt == HYP_F64)
-    hipLaunchKernelGGL(k_rotate<double>, dim3(nch), dim3(kPairThreads), 0, st, S->dev(), op, co, sn,
+    HYP_LAUNCH("k_rotate", k_rotate<double>, dim3(nch), dim3(kPairThreads), 0, st, S->dev(), op, co, sn,
                        (double*)psi, nch);
   else
-    hipLaunchKernelGGL(k_rotate<float>, dim3(nch), dim3(kPairThreads), 0, st, S->dev(), op, co, sn,
+    HYP_LAUNCH("k_rotate", k_rotate<float>, dim3(nch), dim3(kPairThreads), 0, st, S->dev(), op, co, sn,
                        (float*)psi, nch);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
@@ -407,12 +407,12 @@ hyp_status launch_adjoint_step(Sector* S, hyp_dtype dt, hyp_exc op, const double
                                hipStream_t st) {
   int nch = rot_chunks(S, op);
   if (dt == HYP_F64)
-    hipLaunchKernelGGL(k_adjoint_step<double>, dim3(nch), dim3(kPairThreads), 0, st, S->dev(), op,
+    HYP_LAUNCH("k_adjoint_step", k_adjoint_step<double>, dim3(nch), dim3(kPairThreads), 0, st, S->dev(), op,
                        theta_dev, (double*)phi, (double*)lam, part, nch);
   else
-    hipLaunchKernelGGL(k_adjoint_step<float>, dim3(nch), dim3(kPairThreads), 0, st, S->dev(), op,
+    HYP_LAUNCH("k_adjoint_step", k_adjoint_step<float>, dim3(nch), dim3(kPairThreads), 0, st, S->dev(), op,
                        theta_dev, (float*)phi, (float*)lam, part, nch);
-  hipLaunchKernelGGL(k_sum_n, dim3(1), dim3(64), 0, st, part, nch, 2.0, grad_out);
+  HYP_LAUNCH("k_sum_n", k_sum_n, dim3(1), dim3(64), 0, st, part, nch, 2.0, grad_out);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
 }

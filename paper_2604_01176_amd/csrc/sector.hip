@@ -110,12 +110,12 @@ hyp_status launch_dot(Sector* S, hyp_dtype dt, const void* a, const void* b, dou
   int blocks = (int)std::min<int64_t>(kDotBlocks, (n + 255) / 256);
   if (blocks < 1) blocks = 1;
   if (dt == HYP_F64)
-    hipLaunchKernelGGL(k_dot_partial_f64, dim3(blocks), dim3(256), 0, st, (const double*)a,
+    HYP_LAUNCH("k_dot_partial_f64", k_dot_partial_f64, dim3(blocks), dim3(256), 0, st, (const double*)a,
                        (const double*)b, n, S->d_scratch);
   else
-    hipLaunchKernelGGL(k_dot_partial_f32, dim3(blocks), dim3(256), 0, st, (const float*)a,
+    HYP_LAUNCH("k_dot_partial_f32", k_dot_partial_f32, dim3(blocks), dim3(256), 0, st, (const float*)a,
                        (const float*)b, n, S->d_scratch);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, S->d_scratch, blocks, out);
+  HYP_LAUNCH("k_sum_partials", k_sum_partials, dim3(1), dim3(256), 0, st, S->d_scratch, blocks, out);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
 }
