@@ -140,12 +140,17 @@ def main():
     if args.cpu_seconds > 0:
         import oracle
         rng = np.random.default_rng(0)
-        sig_h = None
-        n_try = 64
-        t = time.time()
-        oracle.apply_h(M, na, nb, x, z, c, psi_h, out_idx=rng.integers(0, S.dim, n_try))
-        dt = time.time() - t
-        n_rows = int(max(n_try, min(5_000_000, n_try * args.cpu_seconds / max(dt, 1e-6))))
+        # calibrate on growing samples until one takes >= 1 s, then size the
+        # timed sample to about cpu_seconds of oracle work
+        n_try, dt = 256, 0.0
+        while True:
+            t = time.time()
+            oracle.apply_h(M, na, nb, x, z, c, psi_h, out_idx=rng.integers(0, S.dim, n_try))
+            dt = time.time() - t
+            if dt >= 1.0 or n_try >= 4_000_000:
+                break
+            n_try *= 4
+        n_rows = int(max(256, min(20_000_000, n_try * args.cpu_seconds / max(dt, 1e-6))))
         idx = rng.integers(0, S.dim, n_rows)
         t = time.time()
         oracle.apply_h(M, na, nb, x, z, c, psi_h, out_idx=idx)
@@ -155,7 +160,6 @@ def main():
                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
                "kind": "oracle",
                "sample": f"{n_rows} random output rows of H psi ({dt:.1f} s), gather-model bytes"}
-        del sig_h
 
     out = {
         "metric": "H psi GB/s (gather model) + pool-grad evals/s",

@@ -126,6 +126,63 @@ hyp_status hyp_pool_gradients(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_
 hyp_status hyp_apply_excitation(hyp_sector s, hyp_dtype dtype, hyp_exc op, double theta,
                                 void* psi_dev, void* stream);
 
+/* ------------------------------------------------------------------------
+ * ADAPT-VQE driver ("Numerical performance"): starting from the Hartree-Fock
+ * determinant (sector index 0), each iteration computes sigma = H psi and the
+ * pool gradients, appends the operator of largest |g| (ties: the lowest pool
+ * index among |g| >= max|g| (1 - tie_tol)), and re-optimises all parameters
+ * with BFGS (strong-Wolfe line search) on E(theta) = <psi(theta)|H|psi(theta)>,
+ * psi(theta) = exp(theta_j A_j) ... exp(theta_1 A_1) |HF>, warm-started from
+ * the previous parameters with the new one at 0.  Each energy+gradient
+ * evaluation (state preparation, H psi, energy, adjoint gradient) is one
+ * hipGraph replay when use_graph != 0.  FP32 storage renormalises the state
+ * after every preparation.  The driver owns its stream and buffers; calls are
+ * synchronous and return after the iteration finished.
+ * ------------------------------------------------------------------------ */
+typedef struct hyp_adapt_s* hyp_adapt;
+typedef struct {
+  int32_t max_iter;   /* maximum ansatz length (buffer capacity), 1..4096 */
+  int32_t max_bfgs;   /* BFGS iterations per ADAPT iteration */
+  int32_t use_graph;  /* capture each evaluation in a hipGraph */
+  int32_t reserved;
+  double tie_tol;     /* relative tie tolerance of the selection, in [0, 1) */
+  double gtol;        /* BFGS stop: max_i |dE/dtheta_i| <= gtol, > 0 */
+  double gmax_stop;   /* no operator is added when max|g| < gmax_stop */
+} hyp_adapt_opts;
+typedef struct {
+  int32_t selected;   /* pool index appended, -1 if stopped on gmax_stop */
+  int32_t tie_count;  /* size of the tie set */
+  int32_t n_evals;    /* energy+gradient evaluations of the optimiser */
+  int32_t bfgs_iters;
+  int32_t converged;  /* 1 if the gradient tolerance was met */
+  int32_t reserved;
+  double gmax;        /* max |g| over the computed gradients */
+  double energy_before;  /* E of the state the gradients were taken on */
+  double energy;      /* E after optimisation */
+  double grad_ms, opt_ms;  /* host wall time of the two phases */
+} hyp_adapt_record;
+
+/* pool: host array of n_pool validated excitations (the operator pool). */
+hyp_status hyp_adapt_create(hyp_ham h, hyp_dtype dtype, const hyp_exc* pool, int64_t n_pool,
+                            const hyp_adapt_opts* opts, hyp_adapt* out);
+hyp_status hyp_adapt_destroy(hyp_adapt a);
+/* One iteration.  cand == NULL: exact gradients of the whole pool; otherwise
+ * only of the n_cand pool indices in cand (host array), and the selection
+ * runs inside that set (the screened iteration). */
+hyp_status hyp_adapt_iterate(hyp_adapt a, const int32_t* cand, int64_t n_cand,
+                             hyp_adapt_record* rec);
+/* Pool gradients of the last iteration (host, n = pool size; NaN where not computed). */
+hyp_status hyp_adapt_last_gradients(hyp_adapt a, double* grad, int64_t n);
+/* Current ansatz (pool indices, parameters); with cap < length only *n is set. */
+hyp_status hyp_adapt_ansatz(hyp_adapt a, int32_t* ops, double* theta, int64_t cap, int64_t* n);
+hyp_status hyp_adapt_set_ansatz(hyp_adapt a, const int32_t* ops, const double* theta, int64_t n);
+/* One energy+gradient evaluation at theta (host arrays of the ansatz length). */
+hyp_status hyp_adapt_eval(hyp_adapt a, const double* theta, double* energy, double* grad);
+/* Copy U(theta)|HF> (adapt dtype) to psi_dev. */
+hyp_status hyp_adapt_state(hyp_adapt a, void* psi_dev);
+/* Energy of the current ansatz replayed in FP64 (allocates two FP64 vectors). */
+hyp_status hyp_adapt_energy_fp64(hyp_adapt a, double* energy);
+
 /* Kernel timing (tracing).  While enabled, every kernel the library launches
  * is bracketed by HIP events on its stream; hyp_profile_count() waits for
  * the recorded events and returns the number of distinct kernel names, and

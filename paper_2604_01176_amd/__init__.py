@@ -15,8 +15,9 @@ import numpy as np
 from . import _lib
 from ._lib import HYP_F32, HYP_F64, HypError, HypExc, check
 
-__all__ = ["profile_enable", "profile_reset", "profile_read", "Sector", "Hamiltonian", "hyp_expectation", "hyp_pool_gradients",
-           "hyp_apply_excitation", "HypError", "HYP_F64", "HYP_F32", "exc_tensor"]
+__all__ = ["Sector", "Hamiltonian", "Adapt", "hyp_apply_h", "hyp_expectation",
+           "hyp_pool_gradients", "hyp_apply_excitation", "HypError", "HYP_F64", "HYP_F32",
+           "exc_tensor", "profile_enable", "profile_reset", "profile_read"]
 
 _lib.load()
 
@@ -192,3 +193,91 @@ def profile_read() -> dict:
         check(L.hyp_profile_get(i, buf, 128, ctypes.byref(ms), ctypes.byref(n)))
         out[buf.value.decode()] = (ms.value, n.value)
     return out
+
+
+class Adapt:
+    """hyp_adapt: the native ADAPT-VQE driver over one Hamiltonian and pool.
+
+    dtype "f64" or "f32" (FP32 storage, FP64 accumulation).  Defaults follow
+    the selection/optimiser readings: tie_tol 1e-9 (f64) / 1e-5 (f32),
+    BFGS gtol 1e-9 (f64) / 1e-6 (f32), early stop when max|g| < 1e-10.
+    """
+
+    def __init__(self, ham: Hamiltonian, cre, ann, dtype: str = "f64", max_iter: int = 64,
+                 max_bfgs: int = 1000, use_graph: bool = True, tie_tol=None, gtol=None,
+                 gmax_stop: float = 1e-10):
+        f32 = dtype == "f32"
+        self.dtype = dtype
+        self.ham = ham
+        self.n_pool = len(cre)
+        pool = (_lib.HypExc * self.n_pool)()
+        for i, (c_, a_) in enumerate(zip(np.asarray(cre).tolist(), np.asarray(ann).tolist())):
+            pool[i].cre, pool[i].ann = int(c_), int(a_)
+        o = _lib.AdaptOpts(max_iter=max_iter, max_bfgs=max_bfgs, use_graph=1 if use_graph else 0,
+                           reserved=0, tie_tol=(1e-5 if f32 else 1e-9) if tie_tol is None else tie_tol,
+                           gtol=(1e-6 if f32 else 1e-9) if gtol is None else gtol,
+                           gmax_stop=gmax_stop)
+        h = ctypes.c_void_p()
+        check(_lib.load().hyp_adapt_create(ham._h, HYP_F32 if f32 else HYP_F64, pool, self.n_pool,
+                                           ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def iterate(self, cand=None) -> dict:
+        rec = _lib.AdaptRecord()
+        if cand is None:
+            check(_lib.load().hyp_adapt_iterate(self._h, None, 0, ctypes.byref(rec)))
+        else:
+            c = np.ascontiguousarray(cand, dtype=np.int32)
+            check(_lib.load().hyp_adapt_iterate(self._h, c.ctypes.data, c.size, ctypes.byref(rec)))
+        return {f: getattr(rec, f) for f, _ in rec._fields_ if f != "reserved"}
+
+    def last_gradients(self) -> np.ndarray:
+        out = np.empty(self.n_pool)
+        check(_lib.load().hyp_adapt_last_gradients(self._h, out.ctypes.data, self.n_pool))
+        return out
+
+    def ansatz(self):
+        n = ctypes.c_int64()
+        check(_lib.load().hyp_adapt_ansatz(self._h, None, None, 0, ctypes.byref(n)))
+        ops = np.empty(n.value, dtype=np.int32)
+        th = np.empty(n.value)
+        check(_lib.load().hyp_adapt_ansatz(self._h, ops.ctypes.data, th.ctypes.data, n.value,
+                                           ctypes.byref(n)))
+        return ops, th
+
+    def set_ansatz(self, ops, theta):
+        ops = np.ascontiguousarray(ops, dtype=np.int32)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        check(_lib.load().hyp_adapt_set_ansatz(self._h, ops.ctypes.data, th.ctypes.data, ops.size))
+
+    def eval(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        e = ctypes.c_double()
+        g = np.empty(th.size)
+        check(_lib.load().hyp_adapt_eval(self._h, th.ctypes.data if th.size else None,
+                                         ctypes.byref(e), g.ctypes.data if th.size else None))
+        return e.value, g
+
+    def state(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.ham.sector.dim, device="cuda",
+                              dtype=torch.float32 if self.dtype == "f32" else torch.float64)
+        check(_lib.load().hyp_adapt_state(self._h, _dev_ptr(out, self.ham.sector.dim, "psi")))
+        return out
+
+    def energy_fp64(self) -> float:
+        e = ctypes.c_double()
+        check(_lib.load().hyp_adapt_energy_fp64(self._h, ctypes.byref(e)))
+        return e.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().hyp_adapt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

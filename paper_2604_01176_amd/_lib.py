@@ -19,6 +19,22 @@ class HypExc(ctypes.Structure):
     _fields_ = [("cre", ctypes.c_uint32), ("ann", ctypes.c_uint32)]
 
 
+class AdaptOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("max_bfgs", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tie_tol", ctypes.c_double), ("gtol", ctypes.c_double),
+                ("gmax_stop", ctypes.c_double)]
+
+
+class AdaptRecord(ctypes.Structure):
+    _fields_ = [("selected", ctypes.c_int32), ("tie_count", ctypes.c_int32),
+                ("n_evals", ctypes.c_int32), ("bfgs_iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("gmax", ctypes.c_double), ("energy_before", ctypes.c_double),
+                ("energy", ctypes.c_double), ("grad_ms", ctypes.c_double),
+                ("opt_ms", ctypes.c_double)]
+
+
 class HypError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -45,6 +61,15 @@ SIGNATURES = {
     "hyp_expectation": (_ci, [_vp, _ci, _vp, _vp, _vp, _vp]),
     "hyp_pool_gradients": (_ci, [_vp, _ci, _vp, _i64, _vp, _vp, _vp, _vp]),
     "hyp_apply_excitation": (_ci, [_vp, _ci, HypExc, _d, _vp, _vp]),
+    "hyp_adapt_create": (_ci, [_vp, _ci, _vp, _i64, ctypes.POINTER(AdaptOpts), ctypes.POINTER(_vp)]),
+    "hyp_adapt_destroy": (_ci, [_vp]),
+    "hyp_adapt_iterate": (_ci, [_vp, _vp, _i64, ctypes.POINTER(AdaptRecord)]),
+    "hyp_adapt_last_gradients": (_ci, [_vp, _vp, _i64]),
+    "hyp_adapt_ansatz": (_ci, [_vp, _vp, _vp, _i64, ctypes.POINTER(_i64)]),
+    "hyp_adapt_set_ansatz": (_ci, [_vp, _vp, _vp, _i64]),
+    "hyp_adapt_eval": (_ci, [_vp, _vp, ctypes.POINTER(_d), _vp]),
+    "hyp_adapt_state": (_ci, [_vp, _vp]),
+    "hyp_adapt_energy_fp64": (_ci, [_vp, ctypes.POINTER(_d)]),
     "hyp_profile_enable": (_ci, [_ci]),
     "hyp_profile_reset": (_ci, []),
     "hyp_profile_count": (_ci, []),

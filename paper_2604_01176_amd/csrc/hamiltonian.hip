@@ -25,7 +25,6 @@
 #include <new>
 
 namespace hyp {
-Sector* sector_of(hyp_sector h);
 
 // ---------------------------------------------------------------- helpers
 
@@ -920,8 +919,17 @@ hyp_status hyp_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* sigma
   if (!hh || !psi || !sigma) return fail(HYP_ERR_ARG, "hyp_apply_h: NULL argument");
   if (dtype != HYP_F64 && dtype != HYP_F32) return fail(HYP_ERR_ARG, "hyp_apply_h: bad dtype");
   if (psi == sigma) return fail(HYP_ERR_ARG, "hyp_apply_h: psi and sigma alias");
+  return apply_h_internal(hh, dtype, psi, sigma, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace hyp {
+Ham* ham_of(hyp_ham h) { return h ? &h->h : nullptr; }
+
+hyp_status apply_h_internal(hyp_ham hh, hyp_dtype dtype, const void* psi, void* sigma,
+                            hipStream_t st) {
   Ham* H = &hh->h;
-  hipStream_t st = (hipStream_t)stream;
   if (H->structured) {
     if (dtype == HYP_F64) return run_structured<double>(H, &hh->w, psi, sigma, st);
     return run_structured<float>(H, &hh->w, psi, sigma, st);
@@ -929,9 +937,4 @@ hyp_status hyp_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* sigma
   if (dtype == HYP_F64) return run_generic<double>(H, psi, sigma, st);
   return run_generic<float>(H, psi, sigma, st);
 }
-
-}  // extern "C"
-
-namespace hyp {
-Ham* ham_of(hyp_ham h) { return h ? &h->h : nullptr; }
 }  // namespace hyp

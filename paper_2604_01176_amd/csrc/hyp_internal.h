@@ -140,4 +140,20 @@ struct Ham {
 hyp_status launch_dot(Sector* S, hyp_dtype dt, const void* a, const void* b, double* out,
                       hipStream_t st);
 
+// shared entry points between translation units
+Sector* sector_of(hyp_sector h);
+Ham* ham_of(hyp_ham h);
+hyp_status ensure_binom();
+hyp_status validate_exc(const Sector* S, hyp_exc op);
+hyp_status pair_scratch(Sector* S, size_t n_doubles, double** out);
+hyp_status apply_h_internal(hyp_ham h, hyp_dtype dt, const void* psi, void* sigma, hipStream_t st);
+hyp_status launch_pool_gradients(Sector* S, hyp_dtype dt, const hyp_exc* ops_dev, int64_t n_ops,
+                                 const void* psi, const void* sig, double* grad, hipStream_t st);
+hyp_status launch_rotate(Sector* S, hyp_dtype dt, hyp_exc op, double theta,
+                         const double* theta_dev, void* psi, hipStream_t st);
+hyp_status launch_adjoint_step(Sector* S, hyp_dtype dt, hyp_exc op, const double* theta_dev,
+                               void* phi, void* lam, double* part, double* grad_out,
+                               hipStream_t st);
+int max_rot_chunks();
+
 }  // namespace hyp

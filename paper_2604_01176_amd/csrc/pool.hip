@@ -17,7 +17,6 @@
 #include <vector>
 
 namespace hyp {
-Sector* sector_of(hyp_sector h);
 
 constexpr int kListMax = 3432;  // max C(M-2, N-1) for M <= 16
 constexpr int kPairChunks = 16; // beta-entry chunks per generator (gradient partials)
@@ -191,12 +190,19 @@ __global__ void k_sum_chunks(const double* part, int64_t n, double scale, double
 
 // ---------------------------------------------------------------- rotation
 
+// theta_dev != nullptr: the angle is read from device memory (graph replay
+// with new parameters); otherwise (co, sn) are used.
 template <typename T>
 __global__ void __launch_bounds__(kPairThreads) k_rotate(SectorDev S, hyp_exc op, double co,
-                                                        double sn, T* psi, int nchunk) {
+                                                        double sn, const double* theta_dev,
+                                                        T* psi, int nchunk) {
   __shared__ uint32_t lst[kListMax];
   const PairCtx c = make_ctx(op, S);
   build_alpha_list(c, S, lst);
+  if (theta_dev) {
+    co = cos(*theta_dev);
+    sn = sin(*theta_dev);
+  }
   __syncthreads();
   const int nA = c.a_id ? S.da : c.pa.count;
   const int nB = c.pb.count;
@@ -367,6 +373,15 @@ static hyp_status launch_pool_grad(Sector* S, const hyp_exc* ops, int64_t n_ops,
   return HYP_OK;
 }
 
+hyp_status launch_pool_gradients(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_ops,
+                                 const void* psi, const void* sig, double* grad, hipStream_t st) {
+  hyp_status r = ensure_binom();
+  if (r != HYP_OK) return r;
+  if (n_ops == 0) return HYP_OK;
+  if (dt == HYP_F64) return launch_pool_grad<double>(S, ops, n_ops, psi, sig, grad, st);
+  return launch_pool_grad<float>(S, ops, n_ops, psi, sig, grad, st);
+}
+
 static int rot_chunks(const Sector* S, hyp_exc op) {
   // number of beta entries of the generator bounds the useful chunk count
   const uint32_t m = (1u << S->M) - 1u;
@@ -384,18 +399,18 @@ static int rot_chunks(const Sector* S, hyp_exc op) {
   return (int)std::max<int64_t>(ch, 1);
 }
 
-hyp_status launch_rotate(Sector* S, hyp_dtype dt, hyp_exc op, double theta, void* psi,
-                         hipStream_t st) {
+hyp_status launch_rotate(Sector* S, hyp_dtype dt, hyp_exc op, double theta, const double* theta_dev,
+                         void* psi, hipStream_t st) {
   hyp_status r = ensure_binom();
   if (r != HYP_OK) return r;
   int nch = rot_chunks(S, op);
   double co = std::cos(theta), sn = std::sin(theta);
   if (dt == HYP_F64)
     HYP_LAUNCH("k_rotate", k_rotate<double>, dim3(nch), dim3(kPairThreads), 0, st, S->dev(), op, co, sn,
-                       (double*)psi, nch);
+               theta_dev, (double*)psi, nch);
   else
     HYP_LAUNCH("k_rotate", k_rotate<float>, dim3(nch), dim3(kPairThreads), 0, st, S->dev(), op, co, sn,
-                       (float*)psi, nch);
+               theta_dev, (float*)psi, nch);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
 }
@@ -440,10 +455,7 @@ hyp_status hyp_pool_gradients(hyp_sector sh, hyp_dtype dtype, const hyp_exc* ops
     hyp_status r = validate_exc(S, h[(size_t)k]);
     if (r != HYP_OK) return r;
   }
-  hyp_status r = ensure_binom();
-  if (r != HYP_OK) return r;
-  if (dtype == HYP_F64) return launch_pool_grad<double>(S, ops, n_ops, psi, sigma, grad, st);
-  return launch_pool_grad<float>(S, ops, n_ops, psi, sigma, grad, st);
+  return launch_pool_gradients(S, dtype, ops, n_ops, psi, sigma, grad, st);
 }
 
 hyp_status hyp_apply_excitation(hyp_sector sh, hyp_dtype dtype, hyp_exc op, double theta,
@@ -454,7 +466,7 @@ hyp_status hyp_apply_excitation(hyp_sector sh, hyp_dtype dtype, hyp_exc op, doub
   if (!std::isfinite(theta)) return fail(HYP_ERR_ARG, "hyp_apply_excitation: non-finite theta");
   hyp_status r = validate_exc(S, op);
   if (r != HYP_OK) return r;
-  return launch_rotate(S, dtype, op, theta, psi, (hipStream_t)stream);
+  return launch_rotate(S, dtype, op, theta, nullptr, psi, (hipStream_t)stream);
 }
 
 }  // extern "C"

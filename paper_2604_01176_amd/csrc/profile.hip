@@ -53,6 +53,8 @@ void drain_locked() {
 
 ProfScope::ProfScope(const char* name, hipStream_t st) : name_(name), st_(st) {
   if (!g_on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(g_mu);
   a_ = take_event();
   if (a_ && hipEventRecord((hipEvent_t)a_, st_) != hipSuccess) a_ = nullptr;

@@ -1,0 +1,140 @@
+"""GPU ADAPT-VQE driver against the oracle ADAPT loop (scipy BFGS) on the same
+seeded workloads.  Parity is on selections and converged energies, not on
+optimiser paths: the oracle is teacher-forced to the GPU's pick whenever that
+pick lies inside the oracle's own tie set (several selections are correct
+when |g| ties exactly)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from oracle.adapt import SectorProblem, run_adapt
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hyp():
+    import paper_2604_01176_amd as hyp
+    return hyp
+
+
+def _run_pair(hyp, w, n_iter, dtype="f64", use_graph=True):
+    x, z, c, h, g = synth.hamiltonian(w)
+    cre, ann, _ = synth.canonical_pool(w.n_orb)
+    S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    A = hyp.Adapt(H, cre, ann, dtype=dtype, max_iter=n_iter + 1, use_graph=use_graph)
+    recs = []
+    for it in range(n_iter):
+        r = A.iterate()
+        recs.append(r)
+        if r["selected"] < 0:
+            break
+    sel = [r["selected"] for r in recs if r["selected"] >= 0]
+    prob = SectorProblem(w.n_orb, w.n_alpha, w.n_beta, x, z, c, cre, ann)
+
+    def force(it, ties, own):
+        return sel[it]
+
+    log = run_adapt(prob, len(sel), force=force)
+    return A, recs, sel, log, (x, z, c, h, g)
+
+
+def test_adapt_8q_fp64_parity_and_fci():
+    import paper_2604_01176_amd as hyp
+    w = synth.WORKLOADS["h4_8q"]
+    A, recs, sel, log, (x, z, c, h, g) = _run_pair(hyp, w, w.iterations)
+    assert len(sel) == len(log.selected)
+    assert log.selected == sel  # forced picks were all inside the oracle's tie sets
+    e_gpu = np.array([r["energy"] for r in recs if r["selected"] >= 0])
+    e_orc = np.array(log.energies)
+    assert np.abs(e_gpu - e_orc).max() < 1e-9
+    assert all(r["converged"] for r in recs if r["selected"] >= 0)
+    # variational: non-increasing and above the FCI energy (dense diagonalisation)
+    basis = brute.sector_basis(w.n_orb, w.n_alpha, w.n_beta)
+    efci = brute.fci(brute.sector_matrix(brute.fermion_hamiltonian(h, g), basis))
+    assert np.all(np.diff(e_gpu) <= 1e-10)
+    assert np.all(e_gpu >= efci - 1e-9)
+    # gradient vectors at the first iteration agree with the oracle's
+    # (taken at HF: psi = e_0)
+    ops, th = A.ansatz()
+    assert list(ops) == sel
+    assert abs(A.energy_fp64() - e_gpu[-1]) < 1e-10
+
+
+def test_adapt_step1_closed_form(hyp):
+    """One parameter from HF along the first selected double: the optimum is
+    the lower eigenvalue of the 2x2 block [[E_HF, H01], [H01, E_D']]."""
+    w = synth.WORKLOADS["h4_8q"]
+    x, z, c, h, g = synth.hamiltonian(w)
+    cre, ann, cls = synth.canonical_pool(w.n_orb)
+    S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    A = hyp.Adapt(H, cre, ann, max_iter=2)
+    r = A.iterate()
+    k = r["selected"]
+    basis = brute.sector_basis(w.n_orb, w.n_alpha, w.n_beta)
+    Hs = brute.sector_matrix_from_paulis(w.n_orb, w.n_alpha, w.n_beta, x, z, c).real
+    s, bp = oracle.apply_tau(int(cre[k]), int(ann[k]), int(basis[0]))
+    assert s != 0
+    j = int(np.searchsorted(basis, bp))
+    blk = np.array([[Hs[0, 0], Hs[0, j]], [Hs[j, 0], Hs[j, j]]])
+    assert abs(r["energy"] - np.linalg.eigvalsh(blk)[0]) < 1e-10
+
+
+def test_adapt_16q_fp64_parity():
+    import paper_2604_01176_amd as hyp
+    w = synth.WORKLOADS["h8_16q"]
+    A, recs, sel, log, _ = _run_pair(hyp, w, 12)
+    e_gpu = np.array([r["energy"] for r in recs if r["selected"] >= 0])
+    assert log.selected == sel
+    assert np.abs(e_gpu - np.array(log.energies)).max() < 1e-9
+    assert np.all(np.diff(e_gpu) <= 1e-10)
+
+
+def test_adapt_graph_equals_eager(hyp):
+    w = synth.WORKLOADS["h8_16q"]
+    x, z, c, _, _ = synth.hamiltonian(w)
+    cre, ann, _ = synth.canonical_pool(w.n_orb)
+    S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    Ag = hyp.Adapt(H, cre, ann, max_iter=8, use_graph=True)
+    Ae = hyp.Adapt(H, cre, ann, max_iter=8, use_graph=False)
+    ops = [int(v) for v in np.random.default_rng(0).integers(0, len(cre), 6)]
+    th = np.linspace(-0.3, 0.4, 6)
+    Ag.set_ansatz(ops, th)
+    Ae.set_ansatz(ops, th)
+    e_e, g_e = Ae.eval(th)
+    outs = []
+    for rep in range(4):  # replays of one captured graph with eager work in between
+        th2 = th * (1 + 0.1 * rep)
+        e_g, g_g = Ag.eval(th2)
+        e_e2, g_e2 = Ae.eval(th2)
+        outs.append((e_g, g_g, e_e2, g_e2))
+        torch.cuda.synchronize()
+    for e_g, g_g, e_e2, g_e2 in outs:
+        assert abs(e_g - e_e2) < 1e-13
+        assert np.abs(g_g - g_e2).max() < 1e-12
+    # against the oracle's plain definition of the gradient
+    prob = SectorProblem(w.n_orb, w.n_alpha, w.n_beta, x, z, c, cre, ann)
+    e_o, g_o = prob.energy_grad(ops, th)
+    assert abs(e_e - e_o) < 1e-12
+    assert np.abs(g_e - g_o).max() < 1e-11
+
+
+def test_adapt_fp32_close_to_fp64(hyp):
+    w = synth.WORKLOADS["h8_16q"]
+    x, z, c, _, _ = synth.hamiltonian(w)
+    cre, ann, _ = synth.canonical_pool(w.n_orb)
+    S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    A64 = hyp.Adapt(H, cre, ann, max_iter=8)
+    A32 = hyp.Adapt(H, cre, ann, dtype="f32", max_iter=8)
+    for _ in range(6):
+        r64 = A64.iterate()
+        r32 = A32.iterate(None)
+        assert r32["selected"] == r64["selected"] or r32["tie_count"] > 1
+    assert abs(A32.energy_fp64() - A64.energy_fp64()) < 1e-6
