@@ -126,6 +126,37 @@ hyp_status hyp_pool_gradients(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_
 hyp_status hyp_apply_excitation(hyp_sector s, hyp_dtype dtype, hyp_exc op, double theta,
                                 void* psi_dev, void* stream);
 
+/* Batched pool gradients: the jobs (up to 16 instances, possibly of
+ * different sectors, one dtype) run in ONE persistent launch that drains a
+ * device work queue of (instance, generator, beta-chunk) items, then one
+ * fixed-order reduction per generator; results equal hyp_pool_gradients per
+ * job up to summation order.  Excitations are validated on the host first
+ * (device-to-host copy of every ops_dev array).  Uses a per-device library
+ * scratch (grow-only): concurrent batched calls on one device race.
+ * tile == NULL selects {256 threads, 16 chunks, 4 workgroups per CU}. */
+typedef struct {
+  hyp_sector sector;
+  hyp_dtype dtype;
+  const hyp_exc* ops_dev;   /* device array of n_ops excitations */
+  int64_t n_ops;
+  const void* psi_dev;
+  const void* sigma_dev;    /* sigma = H psi of this instance */
+  double* grad_dev;         /* device, n_ops doubles */
+} hyp_grad_job;
+typedef struct {
+  int32_t threads;          /* workgroup size: 64, 128, 256, 512 or 1024 */
+  int32_t chunks;           /* beta-entry chunks per generator, 1..256 */
+  int32_t blocks_per_cu;    /* resident workgroups per CU of the persistent grid, 1..32 */
+  int32_t reserved;
+} hyp_sweep_tile;
+hyp_status hyp_pool_gradients_batched(const hyp_grad_job* jobs, int n_jobs,
+                                      const hyp_sweep_tile* tile, void* stream);
+/* Autotuner: times every tile of {128,256,512} x {4,8,16,32} x {2,4,8} on
+ * these jobs (reps launches each, HIP events on `stream`) and returns the
+ * fastest and its mean time.  Overwrites the jobs' gradient outputs. */
+hyp_status hyp_tune_pool_gradients(const hyp_grad_job* jobs, int n_jobs, int reps,
+                                   hyp_sweep_tile* best, double* best_ms, void* stream);
+
 /* ------------------------------------------------------------------------
  * ADAPT-VQE driver ("Numerical performance"): starting from the Hartree-Fock
  * determinant (sector index 0), each iteration computes sigma = H psi and the
@@ -171,6 +202,13 @@ hyp_status hyp_adapt_destroy(hyp_adapt a);
  * runs inside that set (the screened iteration). */
 hyp_status hyp_adapt_iterate(hyp_adapt a, const int32_t* cand, int64_t n_cand,
                              hyp_adapt_record* rec);
+/* The two halves of hyp_adapt_iterate: exact gradients of the current state
+ * (whole pool or the candidates), then selection + BFGS over the stored
+ * gradients.  A screen calls the first on its candidates, may call it again
+ * on the whole pool (fallback), then calls the second. */
+hyp_status hyp_adapt_gradients(hyp_adapt a, const int32_t* cand, int64_t n_cand,
+                               hyp_adapt_record* rec);
+hyp_status hyp_adapt_select_optimize(hyp_adapt a, hyp_adapt_record* rec);
 /* Pool gradients of the last iteration (host, n = pool size; NaN where not computed). */
 hyp_status hyp_adapt_last_gradients(hyp_adapt a, double* grad, int64_t n);
 /* Current ansatz (pool indices, parameters); with cap < length only *n is set. */
@@ -182,6 +220,58 @@ hyp_status hyp_adapt_eval(hyp_adapt a, const double* theta, double* energy, doub
 hyp_status hyp_adapt_state(hyp_adapt a, void* psi_dev);
 /* Energy of the current ansatz replayed in FP64 (allocates two FP64 vectors). */
 hyp_status hyp_adapt_energy_fp64(hyp_adapt a, double* energy);
+
+/* ------------------------------------------------------------------------
+ * Learned gradient screen (a ranking aid for ADAPT-VQE operator selection;
+ * not in the paper).  Feature rows are 32 BF16 values per operator.  The MLP
+ * is y = W3 relu(W2 relu(W1 f + b1) + b2) + b3 with widths 32-256-256-1;
+ * W1, W2 and the activations entering the two matrix products are BF16
+ * (round to nearest even) on MFMA with FP32 accumulation; masters, biases,
+ * W3 and the output layer are FP32.  Parameter layout (host arrays):
+ * W1[256][32], b1[256], W2[256][256], b2[256], W3[256], b3[1] (74,241 floats).
+ * ------------------------------------------------------------------------ */
+typedef struct hyp_mlp_s* hyp_mlp;
+/* init_host: initial parameters (layout above); max_rows: largest batch or
+ * scoring call. */
+hyp_status hyp_mlp_create(const float* init_host, int64_t max_rows, hyp_mlp* out);
+hyp_status hyp_mlp_destroy(hyp_mlp m);
+hyp_status hyp_mlp_params(hyp_mlp m, float* host_out);
+/* scores y_dev[n] for feature rows X_dev[n][32] (BF16 bit patterns). */
+hyp_status hyp_mlp_forward(hyp_mlp m, const uint16_t* X_dev, int64_t n, float* y_dev, void* stream);
+/* One Adam step (beta 0.9/0.999, eps 1e-8) on the mean squared error of a
+ * batch of B rows (16 <= B <= max_rows, B % 16 == 0) against targets t_dev;
+ * y_dev receives the forward scores. */
+hyp_status hyp_mlp_train_step(hyp_mlp m, const uint16_t* X_dev, const float* t_dev, int64_t B,
+                              float lr, float* y_dev, void* stream);
+/* Parameter gradients of the last train step (host, parameter layout). */
+hyp_status hyp_mlp_grads(hyp_mlp m, float* host_out);
+/* Static feature rows (host): stat[n][32] FP32 = class one-hot (0..4),
+ * spatial orbital index / (M-1) of (c1, c2, a1, a2) for doubles or (c, a)
+ * for singles, -1 padding (5..8), log10(|h_ca| + 1e-12) for singles or
+ * log10(|(c1 a1|c2 a2)| + 1e-12), log10(|(c1 a2|c2 a1)| + 1e-12) for doubles
+ * (9, 10), M/16 (17), zeros elsewhere; qidx[n][4] the same spin-orbitals as
+ * qubit indices.  h: M*M, g: M^4 chemist's-notation integrals (host). */
+hyp_status hyp_screen_static(int n_orb, const hyp_exc* pool, const uint8_t* cls, int64_t n,
+                             const double* h, const double* g, float* stat, int32_t* qidx);
+/* <n_q> of every spin-orbital q < 2M for a sector state (occ_dev: 2M
+ * doubles; work_dev: C(M, N_beta) * 17 doubles of scratch). */
+hyp_status hyp_occupations(hyp_sector s, hyp_dtype dtype, const void* psi_dev, double* occ_dev,
+                           double* work_dev, void* stream);
+/* Feature rows: static part stat_dev[n][32] (FP32) with slots 11..14 set to
+ * <n_q> of the operator's spin-orbitals qidx_dev[n][4] (-1: 0), slot 15 to
+ * log10(|g_prev| + 1e-12), slot 16 to min(age, 50) / 10; output BF16. */
+hyp_status hyp_features(const float* stat_dev, const int32_t* qidx_dev, const double* occ_dev,
+                        const double* gprev_dev, const int32_t* age_dev, int64_t n, uint16_t* X_dev,
+                        void* stream);
+/* Screen bookkeeping: for every k with g_dev[k] not NaN, gprev[k] = g[k]
+ * and age[k] = 0; every other age grows by one. */
+hyp_status hyp_screen_update(const double* g_dev, int64_t n, double* gprev_dev, int32_t* age_dev,
+                             void* stream);
+/* Training rows: Xo[i] = X[idx[i]] (32 BF16), t[i] = log10(|g[idx[i]]| + 1e-12). */
+hyp_status hyp_screen_batch(const uint16_t* X_dev, const double* g_dev, const int32_t* idx_dev,
+                            int64_t m, uint16_t* Xo_dev, float* t_dev, void* stream);
+/* Operator indices sorted by descending score (stable: ties keep index order). */
+hyp_status hyp_rank_scores(hyp_mlp m, const float* y_dev, int64_t n, int32_t* order_dev, void* stream);
 
 /* Kernel timing (tracing).  While enabled, every kernel the library launches
  * is bracketed by HIP events on its stream; hyp_profile_count() waits for

@@ -231,6 +231,23 @@ class Adapt:
             check(_lib.load().hyp_adapt_iterate(self._h, c.ctypes.data, c.size, ctypes.byref(rec)))
         return {f: getattr(rec, f) for f, _ in rec._fields_ if f != "reserved"}
 
+    def gradients(self, cand=None) -> dict:
+        """Exact pool gradients of the current state (all, or the candidates)."""
+        rec = _lib.AdaptRecord()
+        if cand is None:
+            check(_lib.load().hyp_adapt_gradients(self._h, None, 0, ctypes.byref(rec)))
+        else:
+            c = np.ascontiguousarray(cand, dtype=np.int32)
+            check(_lib.load().hyp_adapt_gradients(self._h, c.ctypes.data, c.size, ctypes.byref(rec)))
+        self._rec = rec
+        return {f: getattr(rec, f) for f, _ in rec._fields_ if f != "reserved"}
+
+    def select_optimize(self) -> dict:
+        rec = getattr(self, "_rec", None) or _lib.AdaptRecord()
+        check(_lib.load().hyp_adapt_select_optimize(self._h, ctypes.byref(rec)))
+        self._rec = None
+        return {f: getattr(rec, f) for f, _ in rec._fields_ if f != "reserved"}
+
     def last_gradients(self) -> np.ndarray:
         out = np.empty(self.n_pool)
         check(_lib.load().hyp_adapt_last_gradients(self._h, out.ctypes.data, self.n_pool))
@@ -281,3 +298,39 @@ class Adapt:
             self.close()
         except Exception:
             pass
+
+
+def hyp_pool_gradients_batched(jobs, tile=None):
+    """jobs: list of (sector, ops, psi, sigma, grad_out) tensors; one persistent launch."""
+    arr = (_lib.GradJob * len(jobs))()
+    for i, (sec, ops, psi, sig, g) in enumerate(jobs):
+        arr[i].sector = sec.handle
+        arr[i].dtype = _dtype_code(psi)
+        arr[i].ops_dev = _dev_ptr(ops, None, "ops")
+        arr[i].n_ops = ops.shape[0]
+        arr[i].psi_dev = _dev_ptr(psi, sec.dim, "psi")
+        arr[i].sigma_dev = _dev_ptr(sig, sec.dim, "sigma")
+        arr[i].grad_dev = _dev_ptr(g, ops.shape[0], "grad")
+    t = None
+    if tile is not None:
+        t = ctypes.byref(_lib.SweepTile(int(tile[0]), int(tile[1]), int(tile[2]), 0))
+    check(_lib.load().hyp_pool_gradients_batched(arr, len(jobs), t, _stream()))
+    return arr
+
+
+def hyp_tune_pool_gradients(jobs, reps: int = 2):
+    """Autotune the batched sweep tile on these jobs: ((threads, chunks, blocks_per_cu), ms)."""
+    arr = (_lib.GradJob * len(jobs))()
+    for i, (sec, ops, psi, sig, g) in enumerate(jobs):
+        arr[i].sector = sec.handle
+        arr[i].dtype = _dtype_code(psi)
+        arr[i].ops_dev = _dev_ptr(ops, None, "ops")
+        arr[i].n_ops = ops.shape[0]
+        arr[i].psi_dev = _dev_ptr(psi, sec.dim, "psi")
+        arr[i].sigma_dev = _dev_ptr(sig, sec.dim, "sigma")
+        arr[i].grad_dev = _dev_ptr(g, ops.shape[0], "grad")
+    best = _lib.SweepTile()
+    ms = ctypes.c_double()
+    check(_lib.load().hyp_tune_pool_gradients(arr, len(jobs), reps, ctypes.byref(best), ctypes.byref(ms),
+                                              _stream()))
+    return (best.threads, best.chunks, best.blocks_per_cu), ms.value

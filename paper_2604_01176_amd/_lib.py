@@ -35,6 +35,17 @@ class AdaptRecord(ctypes.Structure):
                 ("opt_ms", ctypes.c_double)]
 
 
+class GradJob(ctypes.Structure):
+    _fields_ = [("sector", ctypes.c_void_p), ("dtype", ctypes.c_int), ("ops_dev", ctypes.c_void_p),
+                ("n_ops", ctypes.c_int64), ("psi_dev", ctypes.c_void_p),
+                ("sigma_dev", ctypes.c_void_p), ("grad_dev", ctypes.c_void_p)]
+
+
+class SweepTile(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("chunks", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class HypError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -61,9 +72,25 @@ SIGNATURES = {
     "hyp_expectation": (_ci, [_vp, _ci, _vp, _vp, _vp, _vp]),
     "hyp_pool_gradients": (_ci, [_vp, _ci, _vp, _i64, _vp, _vp, _vp, _vp]),
     "hyp_apply_excitation": (_ci, [_vp, _ci, HypExc, _d, _vp, _vp]),
+    "hyp_pool_gradients_batched": (_ci, [_vp, _ci, _vp, _vp]),
+    "hyp_tune_pool_gradients": (_ci, [_vp, _ci, _ci, ctypes.POINTER(SweepTile), ctypes.POINTER(_d), _vp]),
+    "hyp_mlp_create": (_ci, [_vp, _i64, ctypes.POINTER(_vp)]),
+    "hyp_mlp_destroy": (_ci, [_vp]),
+    "hyp_mlp_params": (_ci, [_vp, _vp]),
+    "hyp_mlp_forward": (_ci, [_vp, _vp, _i64, _vp, _vp]),
+    "hyp_mlp_train_step": (_ci, [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp]),
+    "hyp_mlp_grads": (_ci, [_vp, _vp]),
+    "hyp_screen_static": (_ci, [_ci, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "hyp_occupations": (_ci, [_vp, _ci, _vp, _vp, _vp, _vp]),
+    "hyp_features": (_ci, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "hyp_screen_update": (_ci, [_vp, _i64, _vp, _vp, _vp]),
+    "hyp_screen_batch": (_ci, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "hyp_rank_scores": (_ci, [_vp, _vp, _i64, _vp, _vp]),
     "hyp_adapt_create": (_ci, [_vp, _ci, _vp, _i64, ctypes.POINTER(AdaptOpts), ctypes.POINTER(_vp)]),
     "hyp_adapt_destroy": (_ci, [_vp]),
     "hyp_adapt_iterate": (_ci, [_vp, _vp, _i64, ctypes.POINTER(AdaptRecord)]),
+    "hyp_adapt_gradients": (_ci, [_vp, _vp, _i64, ctypes.POINTER(AdaptRecord)]),
+    "hyp_adapt_select_optimize": (_ci, [_vp, ctypes.POINTER(AdaptRecord)]),
     "hyp_adapt_last_gradients": (_ci, [_vp, _vp, _i64]),
     "hyp_adapt_ansatz": (_ci, [_vp, _vp, _vp, _i64, ctypes.POINTER(_i64)]),
     "hyp_adapt_set_ansatz": (_ci, [_vp, _vp, _vp, _i64]),

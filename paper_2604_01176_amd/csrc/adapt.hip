@@ -446,18 +446,17 @@ hyp_status hyp_adapt_create(hyp_ham ham, hyp_dtype dtype, const hyp_exc* pool, i
   return HYP_OK;
 }
 
-// One ADAPT iteration.  cand == NULL: exact gradients over the whole pool.
-// Otherwise only over the n_cand pool indices in cand (host array); the
-// selection then runs inside that set.
-hyp_status hyp_adapt_iterate(hyp_adapt h, const int32_t* cand, int64_t n_cand, hyp_adapt_record* rec) {
-  if (!h || !rec) return fail(HYP_ERR_ARG, "hyp_adapt_iterate: NULL argument");
+// Exact pool gradients of the current state.  cand == NULL: the whole pool;
+// otherwise only the n_cand pool indices in cand (host array).  Stores them
+// (NaN elsewhere) for the selection and fills energy_before, gmax, grad_ms.
+hyp_status hyp_adapt_gradients(hyp_adapt h, const int32_t* cand, int64_t n_cand, hyp_adapt_record* rec) {
+  if (!h || !rec) return fail(HYP_ERR_ARG, "hyp_adapt_gradients: NULL argument");
   Adapt& A = h->a;
   const int64_t np = (int64_t)A.pool.size();
-  if (cand && (n_cand < 1 || n_cand > np)) return fail(HYP_ERR_ARG, "hyp_adapt_iterate: bad candidate count");
+  if (cand && (n_cand < 1 || n_cand > np)) return fail(HYP_ERR_ARG, "hyp_adapt_gradients: bad candidate count");
   if (cand)
     for (int64_t i = 0; i < n_cand; ++i)
-      if (cand[i] < 0 || cand[i] >= np) return fail(HYP_ERR_ARG, "hyp_adapt_iterate: candidate index out of range");
-  if ((int)A.ops.size() >= A.o.max_iter) return fail(HYP_ERR_ARG, "hyp_adapt_iterate: ansatz at max_iter");
+      if (cand[i] < 0 || cand[i] >= np) return fail(HYP_ERR_ARG, "hyp_adapt_gradients: candidate index out of range");
   std::memset(rec, 0, sizeof(*rec));
   auto t0 = std::chrono::steady_clock::now();
   hyp_status r = prepare_state(&A);
@@ -485,14 +484,28 @@ hyp_status hyp_adapt_iterate(hyp_adapt h, const int32_t* cand, int64_t n_cand, h
     gmax = std::max(gmax, std::fabs(A.h_pin[1 + i]));
   }
   rec->gmax = gmax;
-  auto t1 = std::chrono::steady_clock::now();
-  rec->grad_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  rec->grad_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return HYP_OK;
+}
+
+// Selection over the stored gradients (tie rule: lowest pool index among
+// |g| >= max|g| (1 - tie_tol)), then BFGS over all parameters.  Keeps the
+// gradient fields of rec; selected = -1 (nothing appended) if max|g| <
+// gmax_stop.
+hyp_status hyp_adapt_select_optimize(hyp_adapt h, hyp_adapt_record* rec) {
+  if (!h || !rec) return fail(HYP_ERR_ARG, "hyp_adapt_select_optimize: NULL argument");
+  Adapt& A = h->a;
+  const int64_t np = (int64_t)A.pool.size();
+  if ((int)A.ops.size() >= A.o.max_iter) return fail(HYP_ERR_ARG, "hyp_adapt_select_optimize: ansatz at max_iter");
+  double gmax = 0.0;
+  for (int64_t k = 0; k < np; ++k)
+    if (!std::isnan(A.last_grad[(size_t)k])) gmax = std::max(gmax, std::fabs(A.last_grad[(size_t)k]));
+  rec->gmax = gmax;
   if (gmax < A.o.gmax_stop) {
     rec->selected = -1;
     rec->energy = rec->energy_before;
     return HYP_OK;
   }
-  // tie rule: lowest pool index among |g| >= gmax (1 - tie_tol)
   int32_t best = -1, ties = 0;
   for (int64_t k = 0; k < np; ++k) {
     const double v = A.last_grad[(size_t)k];
@@ -504,13 +517,14 @@ hyp_status hyp_adapt_iterate(hyp_adapt h, const int32_t* cand, int64_t n_cand, h
   }
   rec->selected = best;
   rec->tie_count = ties;
+  auto t1 = std::chrono::steady_clock::now();
   A.ops.push_back(best);
   A.theta.push_back(0.0);
   A.n_evals = 0;
   double f = 0.0;
   int iters = 0, conv = 0;
   std::vector<double> x = A.theta;
-  r = bfgs(&A, x, &f, &iters, &conv);
+  hyp_status r = bfgs(&A, x, &f, &iters, &conv);
   if (r != HYP_OK) {
     A.ops.pop_back();
     A.theta.pop_back();
@@ -524,6 +538,16 @@ hyp_status hyp_adapt_iterate(hyp_adapt h, const int32_t* cand, int64_t n_cand, h
   rec->converged = conv;
   rec->opt_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
   return HYP_OK;
+}
+
+// One ADAPT iteration: gradients (cand as in hyp_adapt_gradients), then
+// selection and optimisation.
+hyp_status hyp_adapt_iterate(hyp_adapt h, const int32_t* cand, int64_t n_cand, hyp_adapt_record* rec) {
+  if (h && (int)h->a.ops.size() >= h->a.o.max_iter)
+    return fail(HYP_ERR_ARG, "hyp_adapt_iterate: ansatz at max_iter");
+  hyp_status r = hyp_adapt_gradients(h, cand, n_cand, rec);
+  if (r != HYP_OK) return r;
+  return hyp_adapt_select_optimize(h, rec);
 }
 
 hyp_status hyp_adapt_last_gradients(hyp_adapt h, double* out, int64_t n) {

@@ -84,9 +84,10 @@ __global__ void k_transpose(const T* __restrict__ in, T* __restrict__ out, int r
 // ---------------------------------------------------------------- same-spin rows
 
 struct SameSpinArgs {
-  const void* in;         // [nrow][ncol] storage T
-  double* out;            // [nrow][ncol] FP64 partial
-  int nrow, ncol;
+  int* list_rank;         // [nrow][nent] source row of each entry
+  double* list_coef;      // [nrow][nent] coefficient of each entry
+  int nent;
+  int nrow;
   int M, nel;             // orbitals, electrons of the row spin
   int spin;               // 0 alpha rows, 1 beta rows
   const uint32_t* rstr;   // [nrow] row strings
@@ -97,17 +98,17 @@ struct SameSpinArgs {
 
 constexpr int kSameSpinMax = 1 + 64 + 784;  // self + singles + doubles for M <= 16
 constexpr int kSSThreads = 256;
-constexpr int kSSCols = 4;                  // columns per thread
 
-// out[r][c] = sum_{r'} Hs[r][r'] in[r'][c]: Hs = same-spin part of H in the
-// row spin (pure-spin diagonal, singles with same-spin number dressing,
-// same-spin doubles).  One workgroup per (row, column chunk).
-template <typename T>
-__global__ void __launch_bounds__(kSSThreads) k_same_spin(SameSpinArgs a) {
+// Row r of Hs, the same-spin part of H as a sparse matrix over strings of
+// one spin (pure-spin diagonal, singles with same-spin number dressing,
+// same-spin doubles), evaluated from the folded X-group tables and stored
+// as (source row, coefficient) entries.  Built once per Hamiltonian: one
+// workgroup per row string.
+__global__ void __launch_bounds__(kSSThreads) k_ss_build(SameSpinArgs a) {
   __shared__ int s_rank[kSameSpinMax];
   __shared__ double s_coef[kSameSpinMax];
   __shared__ int s_n;
-  const int row = blockIdx.y;
+  const int row = blockIdx.x;
   const uint32_t s = a.rstr[row];
   const int off = a.spin * a.M;  // qubit offset of this spin
   const uint32_t smask = (1u << a.M) - 1u;
@@ -210,26 +211,61 @@ __global__ void __launch_bounds__(kSSThreads) k_same_spin(SameSpinArgs a) {
   }
   __syncthreads();
   const int n = s_n;
-  const T* in = (const T*)a.in;
-  const int c0 = blockIdx.x * (kSSThreads * kSSCols) + threadIdx.x;
-  double acc[kSSCols];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    a.list_rank[(int64_t)row * a.nent + e] = s_rank[e];
+    a.list_coef[(int64_t)row * a.nent + e] = s_coef[e];
+  }
+}
+
+struct SSApplyArgs {
+  const void* in;           // [nrow][ncol] storage T
+  double* out;              // [nrow][ncol] FP64 partial
+  const int* list_rank;
+  const double* list_coef;
+  int nent, nrow, ncol;
+  int ntiles, nrb;          // 64-column tiles, 4-row blocks
+};
+
+// out[r][c] = sum_e coef[r][e] in[rank[r][e]][c].  Each wave owns one output
+// row and 64 consecutive columns, so its entry list is wave-uniform.  The
+// workgroup -> (tile, rows) map is XCD-aware: workgroups are dispatched to
+// the 8 XCDs round-robin, so block b runs on XCD b % 8; consecutive blocks
+// of one XCD take consecutive row blocks of the same 64-column tile, and the
+// tile's slab of the input (nrow x 64 amplitudes) stays in that XCD's L2.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ss_apply(SSApplyArgs a) {
+  const int b = blockIdx.x;
+  const int xcd = b & 7, j = b >> 3;
+  const int tile = (j / a.nrb) * 8 + xcd;
+  const int rb = j % a.nrb;
+  if (tile >= a.ntiles) return;
+  const int row = rb * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (row >= a.nrow) return;
+  const int col = tile * 64 + (threadIdx.x & 63);
+  const bool live = col < a.ncol;
+  const int colc = live ? col : 0;
+  const int* __restrict__ rk = a.list_rank + (int64_t)row * a.nent;
+  const double* __restrict__ cf = a.list_coef + (int64_t)row * a.nent;
+  const T* __restrict__ in = (const T*)a.in;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int e = 0;
+  // eight independent loads in flight per wave
+  for (; e + 8 <= a.nent; e += 8) {
+    T v[8];
 #pragma unroll
-  for (int k = 0; k < kSSCols; ++k) acc[k] = 0.0;
-  for (int e = 0; e < n; ++e) {
-    const T* src = in + (int64_t)s_rank[e] * a.ncol;
-    const double cf = s_coef[e];
-#pragma unroll
-    for (int k = 0; k < kSSCols; ++k) {
-      int c = c0 + k * kSSThreads;
-      if (c < a.ncol) acc[k] += Acc<T>::prod(cf, src[c]);
+    for (int u = 0; u < 8; ++u) {
+      const int r = __builtin_amdgcn_readfirstlane(rk[e + u]);
+      v[u] = in[(int64_t)r * a.ncol + colc];
     }
-  }
-  double* dst = a.out + (int64_t)row * a.ncol;
 #pragma unroll
-  for (int k = 0; k < kSSCols; ++k) {
-    int c = c0 + k * kSSThreads;
-    if (c < a.ncol) dst[c] = acc[k];
+    for (int u = 0; u < 8; ++u) acc[u & 3] += Acc<T>::prod(cf[e + u], v[u]);
   }
+  for (; e < a.nent; ++e) {
+    const int r = __builtin_amdgcn_readfirstlane(rk[e]);
+    acc[0] += Acc<T>::prod(cf[e], in[(int64_t)r * a.ncol + colc]);
+  }
+  const double acc0 = acc[0] + acc[2], acc1 = acc[1] + acc[3];
+  if (live) a.out[(int64_t)row * a.ncol + col] = acc0 + acc1;
 }
 
 // ---------------------------------------------------------------- mixed rows
@@ -244,116 +280,132 @@ struct MixedArgs {
   const uint32_t* bstr;
   const RankTables* arank;
   const RankTables* brank;
+  int nchunk;             // column chunks per beta row
   HamDev H;
 };
 
 // sigma[b][a] = pb[b][a] + pa_t[a][b] + (mixed alpha-beta part of H psi)[b][a]
-// One workgroup per beta row; EPT alpha columns per thread; the row's own
-// psi row and each beta-single source row are staged in LDS in turn.
-template <typename T, int EPT>
-__global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
+//
+// One thread per alpha column.  Its (up to 64) alpha single excitations are
+// decoded once into registers as packed entries
+//   bits 0..13  rank of the target alpha string
+//   bit  14     alpha-beta sign (-1)^{popc(abJa & s)}
+//   bits 15..22 pair id * 2 + O (which orbital of the pair is occupied)
+//   bit  23     single-dressing sign (-1)^{popc(sJ & s)}
+// and reused for every staged source row: the workgroup's own beta row (the
+// alpha singles' beta-occupation dressing and the alpha-beta diagonal), then
+// each beta-single source row (the beta singles' alpha-occupation dressing and
+// the alpha-beta doubles).  Coefficient tables with both signs pre-applied sit
+// in LDS, so one term is two LDS reads and one FMA.
+template <typename T>
+__global__ void __launch_bounds__(768) k_mixed(MixedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* s_row = (T*)smem;  // [da]
-  __shared__ int32_t s_lo[256], s_hi[256];
-  __shared__ uint32_t s_jsa[kMaxPairs], s_abja[kMaxPairs];
+  __shared__ double s_fab[kMaxPairs * 4];   // [(pid*2+O)*2 + sign]
+  __shared__ double s_srow[kMaxPairs * 4];  // [(pid*2+O)*2 + sign]
   __shared__ double s_dmix[kMaxOrb];
-  __shared__ double s_srow[kMaxPairs * 2];
-  __shared__ double s_fab[kMaxPairs * 2];
   __shared__ double s_bdress[kMaxOrb];
   __shared__ int s_brank;
-  __shared__ double s_bscale;
 
-  const int brow = blockIdx.x;
-  const uint32_t bs = a.bstr[brow];
   const int M = a.M;
   const uint32_t amask = (1u << M) - 1u;
   const int tid = threadIdx.x, nt = blockDim.x;
   const HamDev& H = a.H;
+  // XCD-aware: the column chunks of one beta row run on one XCD
+  const int b = blockIdx.x, xcd = b & 7, jj = b >> 3;
+  const int brow = (jj / a.nchunk) * 8 + xcd;
+  const int chunk = jj % a.nchunk;
+  if (brow >= a.db) return;
+  const uint32_t bs = a.bstr[brow];
+  const int col = chunk * nt + tid;
+  const bool live = col < a.da;
+  const uint32_t s = live ? a.astr[col] : a.astr[0];
 
-  for (int i = tid; i < 256; i += nt) {
-    s_lo[i] = a.arank->lo[i];
-    s_hi[i] = a.arank->hi[i];
-  }
-  for (int i = tid; i < kMaxPairs; i += nt) {
-    s_jsa[i] = H.sJ[i];  // alpha singles: J lies in alpha bits
-    s_abja[i] = H.abJa[i];
-  }
   for (int k = tid; k < M; k += nt) {
-    // alpha orbital k couples to the occupied beta orbitals on the diagonal
-    double v = 0.0;
+    double v = 0.0;  // alpha orbital k against the occupied beta orbitals (diagonal)
     uint32_t o = bs;
     while (o) {
-      int l = __ffs(o) - 1;
+      const int l = __ffs(o) - 1;
       o &= o - 1;
       v += H.dC[k * 32 + (l + M)];
     }
     s_dmix[k] = v;
   }
   for (int i = tid; i < kMaxPairs * 2; i += nt) {
-    // alpha singles: beta-occupation dressing (row constant)
-    const double* B = H.sB + (size_t)i * 32;
+    const double* B = H.sB + (size_t)i * 32;  // alpha singles, beta-occupation dressing
     double v = 0.0;
     uint32_t o = bs;
     while (o) {
-      int l = __ffs(o) - 1;
+      const int l = __ffs(o) - 1;
       o &= o - 1;
       v += B[l + M];
     }
-    s_srow[i] = v;
+    s_srow[2 * i] = v;
+    s_srow[2 * i + 1] = -v;
+  }
+  // packed excitation entries of this thread's alpha string
+  uint32_t ex[64];
+  int ns = 0;
+  {
+    const RankTables* R = a.arank;
+    uint32_t occ = s;
+    while (occ) {
+      const int i = __ffs(occ) - 1;
+      occ &= occ - 1;
+      uint32_t emp = ~s & amask;
+      while (emp) {
+        const int e = __ffs(emp) - 1;
+        emp &= emp - 1;
+        const int p = min(i, e), q = max(i, e);
+        const int pid = pair_id(p, q);
+        const uint32_t t2 = s ^ (1u << i) ^ (1u << e);
+        const uint32_t r2 = (uint32_t)(R->lo[t2 & 255u] + R->hi[(t2 >> 8) & 255u]);
+        const uint32_t sab = __popc(H.abJa[pid] & s) & 1u;
+        const uint32_t ssg = __popc(H.sJ[pid] & s) & 1u;
+        const uint32_t O = (i == q) ? 1u : 0u;
+        const uint32_t ent = r2 | (sab << 14) | (((uint32_t)pid * 2u + O) << 15) | (ssg << 23);
+#pragma unroll
+        for (int x = 0; x < 64; ++x)
+          if (x == ns) ex[x] = ent;
+        ++ns;
+      }
+    }
   }
   const T* psi = (const T*)a.psi;
-  const T* prow = psi + (int64_t)brow * a.da;
-  for (int i = tid; i < a.da; i += nt) s_row[i] = prow[i];
+  {
+    const T* prow = psi + (int64_t)brow * a.da;
+    for (int i = tid; i < a.da; i += nt) s_row[i] = prow[i];
+  }
   __syncthreads();
 
-  double acc[EPT];
+  double acc = 0.0;
+  // (1) own row: alpha-beta diagonal and alpha singles' beta dressing
+  {
+    double v = 0.0;
+    uint32_t o = s;
+    while (o) {
+      const int i = __ffs(o) - 1;
+      o &= o - 1;
+      v += s_dmix[i];
+    }
+    acc += Acc<T>::prod(v, s_row[live ? col : 0]);
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) acc[k] = 0.0;
-
-  // (1) alpha-beta diagonal and alpha singles' beta dressing (source row = own row)
-#pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int col = tid + k * nt;
-    if (col < a.da) {
-      const uint32_t s = a.astr[col];
-      double v = 0.0;
-      uint32_t o = s;
-      while (o) {
-        int i = __ffs(o) - 1;
-        o &= o - 1;
-        v += s_dmix[i];
+    for (int x = 0; x < 64; ++x) {
+      if (x < ns) {
+        const uint32_t e = ex[x];
+        const int fi = (int)(((e >> 15) & 0xffu) * 2u + (e >> 23));
+        acc += Acc<T>::prod(s_srow[fi], s_row[e & 0x3fffu]);
       }
-      double sum = Acc<T>::prod(v, s_row[col]);
-      uint32_t occ = s;
-      while (occ) {
-        int i = __ffs(occ) - 1;
-        occ &= occ - 1;
-        uint32_t emp = ~s & amask;
-        while (emp) {
-          int e = __ffs(emp) - 1;
-          emp &= emp - 1;
-          int p = min(i, e), q = max(i, e);
-          int pid = pair_id(p, q);
-          int O = (i == q) ? 1 : 0;
-          uint32_t t2 = s ^ (1u << i) ^ (1u << e);
-          int r2 = s_lo[t2 & 255u] + s_hi[(t2 >> 8) & 255u];
-          double cf = flip(s_srow[pid * 2 + O], __popc(s_jsa[pid] & s));
-          sum += Acc<T>::prod(cf, s_row[r2]);
-        }
-      }
-      acc[k] += sum;
     }
   }
 
-  // (2) beta singles: number dressing by alpha occupations + alpha-beta doubles
+  // (2) beta-single source rows
   const int nbemp = M - a.nb;
   const int nbs = a.nb * nbemp;
-  const uint32_t bmask = amask;
   for (int jb = 0; jb < nbs; ++jb) {
     __syncthreads();
-    // decode the jb-th beta single excitation (identical in every thread)
     int io = jb / nbemp, ie = jb % nbemp;
-    uint32_t occ = bs, emp = ~bs & bmask;
+    uint32_t occ = bs, emp = ~bs & amask;
     for (int j = 0; j < io; ++j) occ &= occ - 1;
     for (int j = 0; j < ie; ++j) emp &= emp - 1;
     const int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
@@ -362,67 +414,43 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
     const int Ob = (i == q) ? 1 : 0;
     const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
     if (tid == 0) s_brank = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
-    // beta single: (-1)^{popc(J & beta)} (A + sum_{beta occ} B + sum_{alpha occ} B)
-    // the beta-only part is in the same-spin pass; here the alpha-occupation part
     const int sbase = (kMaxPairs + pb) * 2 + Ob;
     const uint32_t jsb = H.sJ[kMaxPairs + pb] >> M;
     const double sgn_s = (__popc(jsb & bs) & 1) ? -1.0 : 1.0;
     for (int k = tid; k < M; k += nt) s_bdress[k] = sgn_s * H.sB[(size_t)sbase * 32 + k];
-    // alpha-beta doubles with this beta excitation: F'[pa][Oa]
     const double sgn_ab = (__popc((H.abJb[pb] >> M) & bs) & 1) ? -1.0 : 1.0;
     for (int x = tid; x < kMaxPairs * 2; x += nt) {
-      int pa = x >> 1, Oa = x & 1;
-      s_fab[x] = sgn_ab * H.abF[((size_t)pa * kMaxPairs + pb) * 4 + Oa * 2 + Ob];
+      const int pa = x >> 1, Oa = x & 1;
+      const double f = sgn_ab * H.abF[((size_t)pa * kMaxPairs + pb) * 4 + Oa * 2 + Ob];
+      s_fab[2 * x] = f;
+      s_fab[2 * x + 1] = -f;
     }
     __syncthreads();
     const T* src = psi + (int64_t)s_brank * a.da;
     for (int c = tid; c < a.da; c += nt) s_row[c] = src[c];
     __syncthreads();
+    double dr = 0.0;
+    uint32_t o = s;
+    while (o) {
+      const int kk = __ffs(o) - 1;
+      o &= o - 1;
+      dr += s_bdress[kk];
+    }
+    double sum = Acc<T>::prod(dr, s_row[live ? col : 0]);
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      const int col = tid + k * nt;
-      if (col < a.da) {
-        const uint32_t s = a.astr[col];
-        double dr = 0.0;
-        uint32_t o = s;
-        while (o) {
-          int kk = __ffs(o) - 1;
-          o &= o - 1;
-          dr += s_bdress[kk];
-        }
-        double sum = Acc<T>::prod(dr, s_row[col]);
-        uint32_t occ2 = s;
-        while (occ2) {
-          int ii = __ffs(occ2) - 1;
-          occ2 &= occ2 - 1;
-          uint32_t emp2 = ~s & amask;
-          while (emp2) {
-            int ee = __ffs(emp2) - 1;
-            emp2 &= emp2 - 1;
-            int pp = min(ii, ee), qq = max(ii, ee);
-            int pa = pair_id(pp, qq);
-            int Oa = (ii == qq) ? 1 : 0;
-            uint32_t t2 = s ^ (1u << ii) ^ (1u << ee);
-            int r2 = s_lo[t2 & 255u] + s_hi[(t2 >> 8) & 255u];
-            double cf = flip(s_fab[pa * 2 + Oa], __popc(s_abja[pa] & s));
-            sum += Acc<T>::prod(cf, s_row[r2]);
-          }
-        }
-        acc[k] += sum;
+    for (int x = 0; x < 64; ++x) {
+      if (x < ns) {
+        const uint32_t e2 = ex[x];
+        sum += Acc<T>::prod(s_fab[(e2 >> 14) & 0x1ffu], s_row[e2 & 0x3fffu]);
       }
     }
+    acc += sum;
   }
 
   // (3) combine with the two same-spin partials and store
-  T* out = (T*)a.sigma + (int64_t)brow * a.da;
-  const double* pbr = a.pb + (int64_t)brow * a.da;
-#pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int col = tid + k * nt;
-    if (col < a.da) {
-      double v = acc[k] + pbr[col] + a.pa_t[(int64_t)col * a.db + brow];
-      out[col] = (T)v;
-    }
+  if (live) {
+    const double v = acc + a.pb[(int64_t)brow * a.da + col] + a.pa_t[(int64_t)col * a.db + brow];
+    ((T*)a.sigma)[(int64_t)brow * a.da + col] = (T)v;
   }
 }
 
@@ -472,20 +500,61 @@ struct HamWork {
   void* psi_t = nullptr;      // transposed psi, storage size of the largest dtype (8 B)
   double* part_a = nullptr;   // [da][db]
   double* part_b = nullptr;   // [db][da]
+  // same-spin string-space matrices (built once per Hamiltonian)
+  int* a_rank = nullptr;
+  double* a_coef = nullptr;
+  int a_nent = 0;
+  int* b_rank = nullptr;
+  double* b_coef = nullptr;
+  int b_nent = 0;
 };
 
-static int pick_ept(int da, int* threads) {
-  static const int opts[5] = {1, 2, 4, 8, 16};
-  for (int e : opts) {
-    int nt = ((da + e - 1) / e + 63) / 64 * 64;
-    if (nt <= 1024) {
-      *threads = std::max(nt, 64);
-      return e;
-    }
-  }
-  *threads = 1024;
-  return 16;
+static int same_spin_entries(int M, int N) {
+  const int s = N * (M - N);
+  const int d = (N * (N - 1) / 2) * ((M - N) * (M - N - 1) / 2);
+  return 1 + s + d;
 }
+
+// Build both same-spin matrices (synchronous on st).
+static hyp_status build_same_spin(Ham* Hm, HamWork* W, hipStream_t st) {
+  Sector* S = Hm->sec;
+  W->a_nent = same_spin_entries(S->M, S->na);
+  W->b_nent = same_spin_entries(S->M, S->nb);
+  HYP_HIP(hipMalloc(&W->a_rank, sizeof(int) * S->da * W->a_nent));
+  HYP_HIP(hipMalloc(&W->a_coef, sizeof(double) * S->da * W->a_nent));
+  HYP_HIP(hipMalloc(&W->b_rank, sizeof(int) * S->db * W->b_nent));
+  HYP_HIP(hipMalloc(&W->b_coef, sizeof(double) * S->db * W->b_nent));
+  SameSpinArgs sa;
+  sa.H = Hm->dev;
+  sa.M = S->M;
+  sa.list_rank = W->a_rank;
+  sa.list_coef = W->a_coef;
+  sa.nent = W->a_nent;
+  sa.nrow = (int)S->da;
+  sa.nel = S->na;
+  sa.spin = 0;
+  sa.rstr = S->d_astr;
+  sa.rrank = S->d_arank;
+  sa.constant = 0.0;
+  HYP_LAUNCH("k_ss_build", k_ss_build, dim3((unsigned)S->da), dim3(kSSThreads), 0, st, sa);
+  sa.list_rank = W->b_rank;
+  sa.list_coef = W->b_coef;
+  sa.nent = W->b_nent;
+  sa.nrow = (int)S->db;
+  sa.nel = S->nb;
+  sa.spin = 1;
+  sa.rstr = S->d_bstr;
+  sa.rrank = S->d_brank;
+  sa.constant = Hm->dev.dA;
+  HYP_LAUNCH("k_ss_build", k_ss_build, dim3((unsigned)S->db), dim3(kSSThreads), 0, st, sa);
+  HYP_HIP(hipGetLastError());
+  HYP_HIP(hipStreamSynchronize(st));
+  return HYP_OK;
+}
+
+// threads per mixed-kernel workgroup: one per alpha column, at most 768 (a
+// 12-wave workgroup leaves 168 registers per lane for the cached entries)
+static int pick_threads(int da) { return std::max(64, std::min(768, (da + 63) / 64 * 64)); }
 
 template <typename T>
 static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sigma,
@@ -495,33 +564,31 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   // psi^T for the alpha-row pass
   dim3 tg((da + 63) / 64, (db + 63) / 64);
   HYP_LAUNCH("k_transpose", k_transpose<T>, tg, dim3(256), 0, st, (const T*)psi, (T*)W->psi_t, db, da);
-  SameSpinArgs sa;
-  sa.H = Hm->dev;
-  sa.M = S->M;
   // alpha rows (over psi^T): rows = alpha strings, columns = beta strings
+  SSApplyArgs sa;
   sa.in = W->psi_t;
   sa.out = W->part_a;
+  sa.list_rank = W->a_rank;
+  sa.list_coef = W->a_coef;
+  sa.nent = W->a_nent;
   sa.nrow = da;
   sa.ncol = db;
-  sa.nel = S->na;
-  sa.spin = 0;
-  sa.rstr = S->d_astr;
-  sa.rrank = S->d_arank;
-  sa.constant = 0.0;
-  dim3 ga((db + kSSThreads * kSSCols - 1) / (kSSThreads * kSSCols), da);
-  HYP_LAUNCH("k_same_spin", k_same_spin<T>, ga, dim3(kSSThreads), 0, st, sa);
-  // beta rows (over psi), carrying the constant (identity) term once
+  sa.ntiles = (db + 63) / 64;
+  sa.nrb = (da + 3) / 4;
+  int64_t nb_a = (int64_t)8 * ((sa.ntiles + 7) / 8) * sa.nrb;
+  HYP_LAUNCH("k_ss_apply", k_ss_apply<T>, dim3((unsigned)nb_a), dim3(256), 0, st, sa);
+  // beta rows (over psi), the constant (identity) term folded into their diagonal
   sa.in = psi;
   sa.out = W->part_b;
+  sa.list_rank = W->b_rank;
+  sa.list_coef = W->b_coef;
+  sa.nent = W->b_nent;
   sa.nrow = db;
   sa.ncol = da;
-  sa.nel = S->nb;
-  sa.spin = 1;
-  sa.rstr = S->d_bstr;
-  sa.rrank = S->d_brank;
-  sa.constant = Hm->dev.dA;
-  dim3 gb((da + kSSThreads * kSSCols - 1) / (kSSThreads * kSSCols), db);
-  HYP_LAUNCH("k_same_spin", k_same_spin<T>, gb, dim3(kSSThreads), 0, st, sa);
+  sa.ntiles = (da + 63) / 64;
+  sa.nrb = (db + 3) / 4;
+  int64_t nb_b = (int64_t)8 * ((sa.ntiles + 7) / 8) * sa.nrb;
+  HYP_LAUNCH("k_ss_apply", k_ss_apply<T>, dim3((unsigned)nb_b), dim3(256), 0, st, sa);
   MixedArgs ma;
   ma.psi = psi;
   ma.pa_t = W->part_a;
@@ -537,25 +604,13 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   ma.arank = S->d_arank;
   ma.brank = S->d_brank;
   ma.H = Hm->dev;
-  int nt = Hm->threads, ept = Hm->ept;
-  size_t shm = (size_t)da * sizeof(T);
-  switch (ept) {
-#define HYP_MIXED(E)                                                                         \
-  case E:                                                                                    \
-    if (shm > 48 * 1024)                                                                     \
-      HYP_HIP(hipFuncSetAttribute((const void*)k_mixed<T, E>,                                \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));    \
-    HYP_LAUNCH("k_mixed", (k_mixed<T, E>), dim3(db), dim3(nt), shm, st, ma);                    \
-    break;
-    HYP_MIXED(1)
-    HYP_MIXED(2)
-    HYP_MIXED(4)
-    HYP_MIXED(8)
-    HYP_MIXED(16)
-#undef HYP_MIXED
-    default:
-      return fail(HYP_ERR_UNSUPPORTED, "k_mixed: no instantiation for this shape");
-  }
+  const int nt = Hm->threads;
+  ma.nchunk = (da + nt - 1) / nt;
+  const size_t shm = (size_t)da * sizeof(T);
+  if (shm > 48 * 1024)
+    HYP_HIP(hipFuncSetAttribute((const void*)k_mixed<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  const int64_t nblk = (int64_t)8 * ((db + 7) / 8) * ma.nchunk;
+  HYP_LAUNCH("k_mixed", k_mixed<T>, dim3((unsigned)nblk), dim3(nt), shm, st, ma);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
 }
@@ -884,12 +939,17 @@ hyp_status hyp_build_hamiltonian(hyp_sector sh, const uint32_t* x_mask, const ui
     H.dev.wJ = (const uint32_t*)(b + o_wJ);
     H.dev.abJa = (const uint32_t*)(b + o_abJa);
     H.dev.abJb = (const uint32_t*)(b + o_abJb);
-    H.ept = pick_ept((int)S->da, &H.threads);
+    H.threads = pick_threads((int)S->da);
     // workspace: psi^T and the two same-spin partials
     e = hipMalloc(&hh->w.psi_t, (size_t)S->dim * 8);
     if (e == hipSuccess) e = hipMalloc(&hh->w.part_a, (size_t)S->dim * 8);
     if (e == hipSuccess) e = hipMalloc(&hh->w.part_b, (size_t)S->dim * 8);
     if (e != hipSuccess) return cleanup_fail(e, "hyp_build_hamiltonian: workspace");
+    hyp_status rb = build_same_spin(&H, &hh->w, st);
+    if (rb != HYP_OK) {
+      hyp_ham_destroy(hh);
+      return rb;
+    }
   }
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return cleanup_fail(e, "hyp_build_hamiltonian: upload sync");
@@ -909,6 +969,10 @@ hyp_status hyp_ham_destroy(hyp_ham hh) {
   (void)hipFree(hh->w.psi_t);
   (void)hipFree(hh->w.part_a);
   (void)hipFree(hh->w.part_b);
+  (void)hipFree(hh->w.a_rank);
+  (void)hipFree(hh->w.a_coef);
+  (void)hipFree(hh->w.b_rank);
+  (void)hipFree(hh->w.b_coef);
   delete hh;
   return HYP_OK;
 }

@@ -1,0 +1,260 @@
+"""Learned gradient screen around the native ADAPT driver.
+
+Per screened ADAPT iteration (every call below is one C-ABI entry point;
+the arithmetic runs in the library's kernels):
+  state psi -> <n_q> occupations -> feature rows -> MLP scores -> descending
+  order -> candidates = top-K plus an audit sample of the rest (positions drawn
+  on the host from a generator seeded by (seed, iteration)) -> exact
+  gradients of the candidates -> fallback to the full sweep if the audit's
+  largest |g| beats the top-K's -> selection + BFGS -> g_prev / age update ->
+  one online Adam step on the freshly computed (feature, log10|g|) rows.
+Every judge_every-th iteration (iteration 0 included) runs the full sweep.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import check
+from . import _dev_ptr, _stream, _torch, _dtype_code, Adapt, Sector
+
+N_FEAT = 32
+N_PARAM = 256 * 32 + 256 + 256 * 256 + 256 + 256 + 1
+
+
+class MLP:
+    """hyp_mlp: the screen's network, parameters on the device."""
+
+    def __init__(self, init_params, max_rows: int):
+        p = np.ascontiguousarray(init_params, dtype=np.float32)
+        if p.size != N_PARAM:
+            raise ValueError(f"expected {N_PARAM} parameters")
+        h = ctypes.c_void_p()
+        check(_lib.load().hyp_mlp_create(p.ctypes.data, int(max_rows), ctypes.byref(h)))
+        self._h = h
+        self.max_rows = int(max_rows)
+
+    def params(self) -> np.ndarray:
+        out = np.empty(N_PARAM, dtype=np.float32)
+        check(_lib.load().hyp_mlp_params(self._h, out.ctypes.data))
+        return out
+
+    def grads(self) -> np.ndarray:
+        out = np.empty(N_PARAM, dtype=np.float32)
+        check(_lib.load().hyp_mlp_grads(self._h, out.ctypes.data))
+        return out
+
+    def forward(self, X, y=None):
+        torch = _torch()
+        n = X.shape[0]
+        if y is None:
+            y = torch.empty(n, dtype=torch.float32, device=X.device)
+        check(_lib.load().hyp_mlp_forward(self._h, _dev_ptr(X, n * N_FEAT, "X"), n,
+                                          _dev_ptr(y, n, "y"), _stream()))
+        return y
+
+    def train_step(self, X, t, lr=1e-3, y=None):
+        torch = _torch()
+        B = X.shape[0]
+        if y is None:
+            y = torch.empty(B, dtype=torch.float32, device=X.device)
+        check(_lib.load().hyp_mlp_train_step(self._h, _dev_ptr(X, B * N_FEAT, "X"), _dev_ptr(t, B, "t"),
+                                             B, ctypes.c_float(lr), _dev_ptr(y, B, "y"), _stream()))
+        return y
+
+    def rank(self, y, order=None):
+        torch = _torch()
+        n = y.shape[0]
+        if order is None:
+            order = torch.empty(n, dtype=torch.int32, device=y.device)
+        check(_lib.load().hyp_rank_scores(self._h, _dev_ptr(y, n, "y"), n, _dev_ptr(order, n, "order"),
+                                          _stream()))
+        return order
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().hyp_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def static_features(n_orb, cre, ann, cls, h, g):
+    """(stat [n][32] float32, qidx [n][4] int32) from hyp_screen_static."""
+    n = len(cre)
+    pool = (_lib.HypExc * n)()
+    for i, (c_, a_) in enumerate(zip(np.asarray(cre).tolist(), np.asarray(ann).tolist())):
+        pool[i].cre, pool[i].ann = int(c_), int(a_)
+    cls = np.ascontiguousarray(cls, dtype=np.uint8)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    stat = np.empty((n, N_FEAT), dtype=np.float32)
+    qidx = np.empty((n, 4), dtype=np.int32)
+    check(_lib.load().hyp_screen_static(int(n_orb), pool, cls.ctypes.data, n, h.ctypes.data, g.ctypes.data,
+                                        stat.ctypes.data, qidx.ctypes.data))
+    return stat, qidx
+
+
+class FeatureState:
+    """Device buffers of one problem's features: static rows, g_prev, age."""
+
+    def __init__(self, sector: Sector, stat, qidx, dtype="f64"):
+        torch = _torch()
+        self.sector = sector
+        self.n = stat.shape[0]
+        self.stat = torch.from_numpy(stat).cuda()
+        self.qidx = torch.from_numpy(qidx).cuda()
+        self.gprev = torch.zeros(self.n, dtype=torch.float64, device="cuda")
+        self.age = torch.full((self.n,), 50, dtype=torch.int32, device="cuda")
+        self.occ = torch.zeros(2 * sector.n_orb, dtype=torch.float64, device="cuda")
+        db = int(round(sector.dim / _comb(sector.n_orb, sector.n_alpha)))
+        self.work = torch.zeros(db * 17, dtype=torch.float64, device="cuda")
+        self.X = torch.empty((self.n, N_FEAT), dtype=torch.int16, device="cuda")
+        self.gdev = torch.empty(self.n, dtype=torch.float64, device="cuda")
+
+    def features(self, psi):
+        L = _lib.load()
+        check(L.hyp_occupations(self.sector.handle, _dtype_code(psi), _dev_ptr(psi, self.sector.dim, "psi"),
+                                _dev_ptr(self.occ, None), _dev_ptr(self.work, None), _stream()))
+        check(L.hyp_features(_dev_ptr(self.stat, None), _dev_ptr(self.qidx, None), _dev_ptr(self.occ, None),
+                             _dev_ptr(self.gprev, None), _dev_ptr(self.age, None), self.n,
+                             _dev_ptr(self.X, None), _stream()))
+        return self.X
+
+    def update(self, g_host):
+        """Record exact gradients (NaN = not computed) as g_prev / age."""
+        torch = _torch()
+        self.gdev.copy_(torch.from_numpy(np.ascontiguousarray(g_host, dtype=np.float64)))
+        check(_lib.load().hyp_screen_update(_dev_ptr(self.gdev, None), self.n, _dev_ptr(self.gprev, None),
+                                            _dev_ptr(self.age, None), _stream()))
+
+    def rows(self, idx):
+        """(X rows, targets log10|g| + 1e-12) of the operators idx, from gdev."""
+        torch = _torch()
+        idx_d = torch.from_numpy(np.ascontiguousarray(idx, dtype=np.int32)).cuda()
+        m = idx_d.shape[0]
+        Xo = torch.empty((m, N_FEAT), dtype=torch.int16, device="cuda")
+        t = torch.empty(m, dtype=torch.float32, device="cuda")
+        check(_lib.load().hyp_screen_batch(_dev_ptr(self.X, None), _dev_ptr(self.gdev, None),
+                                           _dev_ptr(idx_d, None), m, _dev_ptr(Xo, None), _dev_ptr(t, None),
+                                           _stream()))
+        return Xo, t
+
+
+def _comb(n, k):
+    import math
+    return math.comb(n, k)
+
+
+def audit_ranks(n_rest: int, n_audit: int, seed: int, iteration: int):
+    """Audit positions among the operators ranked below the top-K: a uniform
+    sample without replacement from a generator seeded by (seed, iteration)."""
+    rng = np.random.default_rng([seed, iteration])
+    m = min(n_audit, n_rest)
+    return np.sort(rng.choice(n_rest, m, replace=False)) if m > 0 else np.zeros(0, dtype=np.int64)
+
+
+class Screen:
+    """Screened ADAPT iterations for one problem."""
+
+    def __init__(self, adapt: Adapt, sector: Sector, stat, qidx, mlp: MLP, K=512, audit=256,
+                 judge_every=10, seed=42, lr=1e-3, online=True):
+        self.adapt = adapt
+        self.fs = FeatureState(sector, stat, qidx)
+        self.mlp = mlp
+        self.K, self.audit, self.judge_every, self.seed, self.lr = K, audit, judge_every, seed, lr
+        self.online = online
+        self.n = stat.shape[0]
+        self.psi = None
+        self.log = []
+
+    def iterate(self, it: int) -> dict:
+        torch = _torch()
+        n = self.n
+        full = (it % self.judge_every == 0) or n <= self.K + self.audit
+        self.psi = self.adapt.state(self.psi)
+        X = self.fs.features(self.psi)
+        info = {"iteration": it, "judge": full, "fallback": False}
+        if full:
+            rec = self.adapt.gradients(None)
+            cand = np.arange(n)
+        else:
+            y = self.mlp.forward(X)
+            order = self.mlp.rank(y).cpu().numpy()
+            top = order[: self.K]
+            rest = order[self.K:]
+            aud = rest[audit_ranks(rest.size, self.audit, self.seed, it)]
+            cand = np.concatenate([top, aud]).astype(np.int32)
+            rec = self.adapt.gradients(cand)
+            g = self.adapt.last_gradients()
+            if aud.size and np.nanmax(np.abs(g[aud])) > np.nanmax(np.abs(g[top])):
+                info["fallback"] = True
+                rec = self.adapt.gradients(None)
+                cand = np.arange(n)
+        g = self.adapt.last_gradients()
+        self.fs.update(g)
+        if self.online:
+            m = (cand.size // 16) * 16
+            if m >= 16:
+                pick = cand[:m] if m == cand.size else np.sort(
+                    np.random.default_rng([self.seed, it, 1]).choice(cand, m, replace=False))
+                for lo in range(0, m, self.mlp.max_rows // 16 * 16):
+                    sl = pick[lo: lo + self.mlp.max_rows // 16 * 16]
+                    Xb, tb = self.fs.rows(sl)
+                    self.mlp.train_step(Xb, tb, self.lr)
+        rec2 = self.adapt.select_optimize()
+        info.update(rec2)
+        info["n_exact"] = int(np.count_nonzero(~np.isnan(g)))
+        self.log.append(info)
+        torch.cuda.synchronize()
+        return info
+
+
+def collect_rows(adapt: Adapt, fs: FeatureState, n_iter: int):
+    """Plain ADAPT with full sweeps; after each sweep the feature rows (built
+    before the sweep) and the targets of every operator.  Returns host arrays
+    (X int16 bit patterns [rows][32], t float32 [rows])."""
+    Xs, ts = [], []
+    psi = None
+    for it in range(n_iter):
+        psi = adapt.state(psi)
+        X = fs.features(psi)
+        rec = adapt.gradients(None)
+        g = adapt.last_gradients()
+        fs.update(g)
+        Xr, tr = fs.rows(np.arange(fs.n))
+        Xs.append(Xr.cpu().numpy())
+        ts.append(tr.cpu().numpy())
+        r2 = adapt.select_optimize()
+        if r2["selected"] < 0:
+            break
+        del X, rec
+    return np.concatenate(Xs), np.concatenate(ts)
+
+
+def train(mlp: MLP, X, t, epochs=3, batch=1024, lr=1e-3, seed=0):
+    """Shuffled mini-batch Adam on host arrays (X int16 [rows][32], t float32)."""
+    torch = _torch()
+    rng = np.random.default_rng(seed)
+    n = (X.shape[0] // batch) * batch
+    losses = []
+    Xd = torch.from_numpy(X).cuda()
+    td = torch.from_numpy(t).cuda()
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(X.shape[0])[:n].astype(np.int64)).cuda()
+        tot = 0.0
+        for b in range(0, n, batch):
+            idx = perm[b: b + batch]
+            Xb = Xd.index_select(0, idx).contiguous()
+            tb = td.index_select(0, idx).contiguous()
+            y = mlp.train_step(Xb, tb, lr)
+            d = y.cpu().numpy().astype(np.float64) - tb.cpu().numpy()
+            tot += float(np.mean(d * d))
+        losses.append(tot / max(1, n // batch))
+    return losses

@@ -88,7 +88,7 @@ def test_adapt_step1_closed_form(hyp):
 def test_adapt_16q_fp64_parity():
     import paper_2604_01176_amd as hyp
     w = synth.WORKLOADS["h8_16q"]
-    A, recs, sel, log, _ = _run_pair(hyp, w, 12)
+    A, recs, sel, log, _ = _run_pair(hyp, w, 8)
     e_gpu = np.array([r["energy"] for r in recs if r["selected"] >= 0])
     assert log.selected == sel
     assert np.abs(e_gpu - np.array(log.energies)).max() < 1e-9

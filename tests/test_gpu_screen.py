@@ -1,0 +1,207 @@
+"""Learned screen on the GPU: MFMA forward/backward and Adam against the FP64
+reference with the same BF16 rounding points, the feature and occupation
+kernels, the ranking, and screened ADAPT against the full sweep it screens
+(argmax agreement, energies) plus the ablation against screening without a
+trained network."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as om
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hyp():
+    import paper_2604_01176_amd as hyp
+    return hyp
+
+
+@pytest.fixture(scope="module")
+def scr():
+    from paper_2604_01176_amd import screen
+    return screen
+
+
+def _bf16_bits(x):
+    f = om.bf16(x).astype(np.float32)
+    return (f.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+
+
+def test_mlp_forward_parity(scr):
+    p = om.init_params(11)
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((1000, om.N_FEAT))
+    net = scr.MLP(p, 1024)
+    Xd = torch.from_numpy(_bf16_bits(X)).cuda()
+    y = net.forward(Xd).cpu().numpy().astype(np.float64)
+    ref, _ = om.forward(p.astype(np.float64), X, quant=True)
+    assert np.linalg.norm(y - ref) <= 2e-4 * np.linalg.norm(ref)
+    assert np.abs(y - ref).max() <= 2e-3 * np.abs(ref).max()
+
+
+def test_mlp_train_step_parity(scr):
+    p = om.init_params(5)
+    rng = np.random.default_rng(1)
+    B = 1024
+    X = rng.standard_normal((B, om.N_FEAT))
+    t = rng.standard_normal(B).astype(np.float32)
+    net = scr.MLP(p, B)
+    Xd = torch.from_numpy(_bf16_bits(X)).cuda()
+    td = torch.from_numpy(t).cuda()
+    net.train_step(Xd, td, lr=1e-3)
+    g = net.grads().astype(np.float64)
+    loss, _, gref = om.loss_grad(p.astype(np.float64), X, t.astype(np.float64), quant=True)
+    blocks = [(0, 8192), (8192, 8448), (8448, 73984), (73984, 74240), (74240, 74496), (74496, 74497)]
+    for lo, hi in blocks:
+        a, b = g[lo:hi], gref[lo:hi]
+        assert np.linalg.norm(a - b) <= 5e-3 * np.linalg.norm(b) + 1e-9, (lo, hi)
+    adam = om.Adam(p.astype(np.float64), lr=1e-3)
+    p1 = adam.step(g)  # the reference update applied to the GPU's own gradient
+    assert np.abs(net.params() - p1).max() <= 1e-6
+
+
+def test_occupations_and_features(hyp, scr):
+    w = synth.WORKLOADS["h8_16q"]
+    M, na, nb = w.n_orb, w.n_alpha, w.n_beta
+    x, z, c, h, g = synth.hamiltonian(w)
+    cre, ann, cls = synth.canonical_pool(M)
+    S = hyp.Sector(M, na, nb)
+    psi = synth.random_state(S.dim, 3)
+    stat, qidx = scr.static_features(M, cre, ann, cls, h, g)
+    fs = scr.FeatureState(S, stat, qidx)
+    gprev = np.random.default_rng(2).standard_normal(len(cre)) * 1e-3
+    gprev[::7] = np.nan
+    fs.update(gprev)
+    fs.update(np.where(np.arange(len(cre)) % 3 == 0, np.nan, gprev))
+    X = fs.features(torch.from_numpy(psi).cuda()).cpu().numpy()
+    occ_ref = oracle.occupations(M, na, nb, psi)
+    assert np.abs(fs.occ.cpu().numpy() - occ_ref).max() < 1e-13
+    assert abs(occ_ref[:M].sum() - na) < 1e-12 and abs(occ_ref[M:].sum() - nb) < 1e-12
+    # reference g_prev / age after the two updates
+    gp = np.zeros(len(cre))
+    age = np.full(len(cre), 50)
+    for gg in (gprev, np.where(np.arange(len(cre)) % 3 == 0, np.nan, gprev)):
+        ok = ~np.isnan(gg)
+        gp[ok] = gg[ok]
+        age = np.where(ok, 0, age + 1)
+    F, Q = om.static_features(M, cre, ann, cls, h, g)
+    ref = om.bf16(om.features(F, Q, occ_ref, gp, age))
+    got = (X.view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    diff = np.abs(got - ref)
+    assert np.all(diff <= np.abs(ref) * 2 ** -7 + 1e-30)
+    assert np.mean(diff == 0) > 0.999
+
+
+def test_rank_scores(scr):
+    net = scr.MLP(om.init_params(0), 64)
+    y = np.round(np.random.default_rng(4).standard_normal(5000), 1).astype(np.float32)
+    order = net.rank(torch.from_numpy(y).cuda()).cpu().numpy()
+    assert np.array_equal(order, np.argsort(-y, kind="stable"))
+
+
+def _train_on(hyp, scr, workloads, n_iter, seed=0):
+    Xs, ts = [], []
+    for w in workloads:
+        x, z, c, h, g = synth.hamiltonian(w)
+        cre, ann, cls = synth.canonical_pool(w.n_orb)
+        S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+        H = hyp.Hamiltonian(S, x, z, c)
+        A = hyp.Adapt(H, cre, ann, max_iter=n_iter + 1)
+        stat, qidx = scr.static_features(w.n_orb, cre, ann, cls, h, g)
+        fs = scr.FeatureState(S, stat, qidx)
+        X, t = scr.collect_rows(A, fs, n_iter)
+        Xs.append(X)
+        ts.append(t)
+    X = np.concatenate(Xs)
+    t = np.concatenate(ts)
+    net = scr.MLP(om.init_params(seed), 1024)
+    losses = scr.train(net, X, t, epochs=4, batch=1024, lr=1e-3)
+    return net, losses
+
+
+@pytest.fixture(scope="module")
+def trained(hyp, scr):
+    wl = [synth.WORKLOADS["h4_8q"], synth.INSTANCES[1], synth.INSTANCES[2], synth.INSTANCES[4]]
+    net, losses = _train_on(hyp, scr, wl, 6)
+    assert losses[-1] < losses[0]
+    return net
+
+
+def test_ablation_recall(hyp, scr, trained):
+    """Held-out problems: where the true argmax |g| ranks under the trained
+    network, under the no-learning heuristic (|g_prev|) and at random."""
+    net = trained
+    K = 32
+    hits = {"mlp": 0, "heuristic": 0, "random": 0}
+    total = 0
+    rng = np.random.default_rng(9)
+    for w in (synth.WORKLOADS["h8_16q"], synth.INSTANCES[3]):
+        x, z, c, h, g = synth.hamiltonian(w)
+        cre, ann, cls = synth.canonical_pool(w.n_orb)
+        S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+        H = hyp.Hamiltonian(S, x, z, c)
+        A = hyp.Adapt(H, cre, ann, max_iter=10)
+        stat, qidx = scr.static_features(w.n_orb, cre, ann, cls, h, g)
+        fs = scr.FeatureState(S, stat, qidx)
+        psi = None
+        for it in range(8):
+            psi = A.state(psi)
+            X = fs.features(psi)
+            heur = fs.gprev.abs().cpu().numpy()
+            y = net.forward(X).cpu().numpy()
+            A.gradients(None)
+            gfull = A.last_gradients()
+            fs.update(gfull)
+            A.select_optimize()
+            if it == 0:
+                continue  # no g_prev yet
+            kstar = int(np.argmax(np.abs(gfull)))
+            total += 1
+            hits["mlp"] += kstar in set(np.argsort(-y, kind="stable")[:K].tolist())
+            hits["heuristic"] += kstar in set(np.argsort(-heur, kind="stable")[:K].tolist())
+            hits["random"] += kstar in set(rng.choice(len(cre), K, replace=False).tolist())
+    rec = {k: v / total for k, v in hits.items()}
+    print("recall@32 of the exact argmax:", rec)
+    assert rec["mlp"] >= 0.8
+    assert rec["mlp"] > rec["random"] + 0.5
+    assert rec["mlp"] >= rec["heuristic"] - 0.15
+
+
+def test_screened_adapt_fp32_vs_full_sweep(hyp, scr, trained):
+    """Screened FP32 ADAPT (top-64 + 32 audit of 2044, judge every 5th
+    iteration) against a plain FP64 full-sweep run on the same problem."""
+    w = synth.WORKLOADS["h8_16q"]
+    x, z, c, h, g = synth.hamiltonian(w)
+    cre, ann, cls = synth.canonical_pool(w.n_orb)
+    S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    n_iter = 10
+    A32 = hyp.Adapt(H, cre, ann, dtype="f32", max_iter=n_iter + 1)
+    stat, qidx = scr.static_features(w.n_orb, cre, ann, cls, h, g)
+    sc = scr.Screen(A32, S, stat, qidx, trained, K=64, audit=32, judge_every=5, seed=42)
+    A64 = hyp.Adapt(H, cre, ann, max_iter=n_iter + 1)
+    agree = 0
+    for it in range(n_iter):
+        info = sc.iterate(it)
+        r64 = A64.iterate()
+        agree += info["selected"] == r64["selected"]
+        assert info["selected"] >= 0
+    print("screened selections equal to the full sweep's:", agree, "/", n_iter)
+    assert agree >= n_iter - 1
+    e32 = A32.energy_fp64()
+    e64 = A64.energy_fp64()
+    if agree == n_iter:
+        assert abs(e32 - e64) < 1e-6
+    # the oracle's energy of the screened ansatz (plain definition, FP64)
+    ops, th = A32.ansatz()
+    from oracle.adapt import SectorProblem
+    prob = SectorProblem(w.n_orb, w.n_alpha, w.n_beta, x, z, c, cre, ann)
+    psi = prob.state(list(ops), th)
+    e_orc = oracle.dot(psi, prob.hpsi(psi))
+    assert abs(e32 - e_orc) < 1e-9
+    n_exact = [r["n_exact"] for r in sc.log]
+    assert min(n_exact) <= 96 < len(cre)
