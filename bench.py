@@ -52,6 +52,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle leg (0 disables it)")
     ap.add_argument("--no-sweep", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--fp32-study", type=int, default=0, metavar="ITERS",
+                    help="FP32-storage vs FP64 error study over ITERS ADAPT iterations (JSON lines)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (hardware-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -64,7 +68,19 @@ def main():
     import paper_2604_01176_amd as hyp
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": n * 8, "bytes_written": n * 8, "copies": 3}))
+        return
     w = synth.WORKLOADS[args.workload]
+    if args.fp32_study:
+        fp32_study(w, args.fp32_study)
+        return
     M, na, nb = w.n_orb, w.n_alpha, w.n_beta
     t0 = time.time()
     x, z, c, _, _ = synth.hamiltonian(w)
@@ -185,6 +201,53 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def fp32_study(w, n_iter):
+    """FP64 ADAPT run; at every iteration the FP32-storage path is evaluated on
+    the same ansatz and parameters: H psi relative error, energy error,
+    pool-gradient error; then an independent FP32 run's final energy."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2604_01176_amd as hyp
+
+    M, na, nb = w.n_orb, w.n_alpha, w.n_beta
+    x, z, c, _, _ = synth.hamiltonian(w)
+    cre, ann, _ = synth.canonical_pool(M)
+    S = hyp.Sector(M, na, nb)
+    H = hyp.Hamiltonian(S, x, z, c)
+    A64 = hyp.Adapt(H, cre, ann, max_iter=n_iter + 1)
+    A32 = hyp.Adapt(H, cre, ann, dtype="f32", max_iter=n_iter + 1)
+    p64 = p32 = None
+    for it in range(n_iter):
+        t = time.time()
+        r = A64.gradients(None)
+        g64 = A64.last_gradients()
+        ops, th = A64.ansatz()
+        A32.set_ansatz(ops, th)
+        r32 = A32.gradients(None)
+        g32 = A32.last_gradients()
+        p64 = A64.state(p64)
+        p32 = A32.state(p32)
+        s64 = H.apply(p64)
+        s32 = H.apply(p32)
+        hpsi_err = float(torch.linalg.norm(s32.double() - s64) / torch.linalg.norm(s64))
+        e_err = r32["energy_before"] - r["energy_before"]
+        rec = A64.select_optimize()
+        print(json.dumps({"iteration": it, "E64": r["energy_before"], "dE_fp32": e_err,
+                          "hpsi_rel_err": hpsi_err, "max_dg": float(np.max(np.abs(g32 - g64))),
+                          "gmax": r["gmax"], "argmax_same": int(np.argmax(np.abs(g32)) == np.argmax(np.abs(g64))),
+                          "selected": rec["selected"], "wall_s": round(time.time() - t, 2)}), flush=True)
+        if rec["selected"] < 0:
+            break
+    B32 = hyp.Adapt(H, cre, ann, dtype="f32", max_iter=n_iter + 1)
+    for it in range(n_iter):
+        if B32.iterate()["selected"] < 0:
+            break
+    print(json.dumps({"final_E64": A64.energy_fp64(), "final_E_fp32_run_replayed_fp64": B32.energy_fp64(),
+                      "dE_final": B32.energy_fp64() - A64.energy_fp64(),
+                      "same_selections": bool(np.array_equal(A64.ansatz()[0], B32.ansatz()[0]))}), flush=True)
 
 
 if __name__ == "__main__":

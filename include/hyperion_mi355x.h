@@ -99,6 +99,14 @@ hyp_status hyp_ham_destroy(hyp_ham h);
 /* 1 if the structured kernel serves this Hamiltonian, 0 if the generic one, -1 on NULL. */
 int hyp_ham_is_structured(hyp_ham h);
 
+/* Autotuner of the H psi tile shape (the mixed pass's workgroup width, one
+ * thread per alpha column): times the candidates {128,...,768} on this
+ * Hamiltonian with reps applications each (HIP events on `stream`), keeps
+ * the fastest for later hyp_apply_h calls on h and returns it.  Overwrites
+ * sigma_dev.  A generic (non-structured) Hamiltonian returns 0 threads. */
+hyp_status hyp_tune_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* sigma_dev,
+                            int reps, void* stream, int* best_threads, double* best_ms);
+
 /* sigma = P_S H P_S psi (the paper's sparse matrix-vector product, computed
  * matrix-free as a pull gather: each output amplitude is written once, no
  * atomics).  psi and sigma: device, dim amplitudes of dtype, must not alias.
@@ -119,6 +127,16 @@ hyp_status hyp_expectation(hyp_sector s, hyp_dtype dtype, const void* a_dev, con
 hyp_status hyp_pool_gradients(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_dev,
                               int64_t n_ops, const void* psi_dev, const void* sigma_dev,
                               double* grad_dev, void* stream);
+
+/* Strategy of hyp_pool_gradients: 0 automatic (default), 1 the per-generator
+ * pair kernel, 2 transition values.  The transition-value sweep computes
+ * T(tau) = sum_D s sigma[tau D] psi[D] for every single and alpha-beta double
+ * excitation at once (g = 2 (T(tau) - T(tau^dagger))) in a pass shaped like
+ * the mixed H psi pass, with a per-device scratch of
+ * C(M,N_b) * ceil(C(M,N_a)/768) * (1 + N_b (M - N_b)) * 241 doubles (27 GB at
+ * 32 qubits); automatic mode uses it when n_ops covers at least a quarter of
+ * the full pool and that scratch is at most 40 GiB.  Process-wide setting. */
+hyp_status hyp_set_sweep_mode(int mode);
 
 /* psi <- exp(theta A) psi in place (the exponentiated fermionic operator):
  * on every pair (D, D' = tau D, sign s) psi_D <- cos psi_D - s sin psi_D',

@@ -79,8 +79,8 @@ class SectorProblem:
 
 def run_adapt(prob: SectorProblem, n_iter: int, tie_tol: float = 1e-9, gtol: float = 1e-9,
               force=None) -> AdaptLog:
-    """force(iteration, tie_set, own_choice) -> index (must lie in tie_set)
-    lets a caller teacher-force the selection inside the tie set."""
+    """force(iteration, gradients, own_choice) -> index lets a caller
+    teacher-force the selection (the caller validates it against gradients)."""
     log = AdaptLog()
     ops: list = []
     thetas = np.zeros(0)
@@ -96,10 +96,10 @@ def run_adapt(prob: SectorProblem, n_iter: int, tie_tol: float = 1e-9, gtol: flo
         ties = np.nonzero(ag >= gm * (1.0 - tie_tol))[0]
         k = int(ties.min())
         if force is not None:
-            fk = int(force(it, ties, k))
+            # the caller checks the forced index against g (near-ties it
+            # accepts are its decision) and the oracle follows it
+            fk = int(force(it, g, k))
             if fk != k:
-                if fk not in set(ties.tolist()):
-                    raise ValueError("forced selection outside the tie set")
                 log.forced += 1
                 k = fk
         ops.append(k)

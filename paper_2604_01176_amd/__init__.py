@@ -112,6 +112,16 @@ class Hamiltonian:
         hyp_apply_h(self, psi, out)
         return out
 
+    def tune(self, psi, reps: int = 2):
+        """hyp_tune_apply_h: (workgroup width, ms per H psi) of the fastest tile."""
+        sig = _torch().empty_like(psi)
+        t = ctypes.c_int()
+        ms = ctypes.c_double()
+        check(_lib.load().hyp_tune_apply_h(self._h, _dtype_code(psi), _dev_ptr(psi, self.sector.dim, "psi"),
+                                           _dev_ptr(sig, self.sector.dim, "sigma"), int(reps), _stream(),
+                                           ctypes.byref(t), ctypes.byref(ms)))
+        return t.value, ms.value
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.load().hyp_ham_destroy(self._h)
@@ -172,6 +182,11 @@ def hyp_apply_excitation(sector: Sector, cre: int, ann: int, theta: float, psi):
     check(_lib.load().hyp_apply_excitation(sector.handle, _dtype_code(psi), HypExc(int(cre), int(ann)),
                                            float(theta), _dev_ptr(psi, sector.dim, "psi"), _stream()))
     return psi
+
+
+def set_sweep_mode(mode: str = "auto"):
+    """hyp_set_sweep_mode: "auto", "pairs" (per-generator kernel) or "tdens"."""
+    check(_lib.load().hyp_set_sweep_mode({"auto": 0, "pairs": 1, "tdens": 2}[mode]))
 
 
 def profile_enable(on: bool = True):

@@ -69,9 +69,11 @@ SIGNATURES = {
     "hyp_ham_destroy": (_ci, [_vp]),
     "hyp_ham_is_structured": (_ci, [_vp]),
     "hyp_apply_h": (_ci, [_vp, _ci, _vp, _vp, _vp]),
+    "hyp_tune_apply_h": (_ci, [_vp, _ci, _vp, _vp, _ci, _vp, ctypes.POINTER(_ci), ctypes.POINTER(_d)]),
     "hyp_expectation": (_ci, [_vp, _ci, _vp, _vp, _vp, _vp]),
     "hyp_pool_gradients": (_ci, [_vp, _ci, _vp, _i64, _vp, _vp, _vp, _vp]),
     "hyp_apply_excitation": (_ci, [_vp, _ci, HypExc, _d, _vp, _vp]),
+    "hyp_set_sweep_mode": (_ci, [_ci]),
     "hyp_pool_gradients_batched": (_ci, [_vp, _ci, _vp, _vp]),
     "hyp_tune_pool_gradients": (_ci, [_vp, _ci, _ci, ctypes.POINTER(SweepTile), ctypes.POINTER(_d), _vp]),
     "hyp_mlp_create": (_ci, [_vp, _i64, ctypes.POINTER(_vp)]),

@@ -979,6 +979,54 @@ hyp_status hyp_ham_destroy(hyp_ham hh) {
 
 int hyp_ham_is_structured(hyp_ham hh) { return hh ? (hh->h.structured ? 1 : 0) : -1; }
 
+// Autotuner of the mixed pass: times every candidate workgroup width on this
+// Hamiltonian (reps applications each, HIP events on `stream`), keeps the
+// fastest for later hyp_apply_h calls and returns it.  sigma is overwritten.
+hyp_status hyp_tune_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* sigma, int reps,
+                            void* stream, int* best_threads, double* best_ms) {
+  if (!hh || !psi || !sigma || reps < 1 || !best_threads || !best_ms)
+    return fail(HYP_ERR_ARG, "hyp_tune_apply_h: bad argument");
+  if (dtype != HYP_F64 && dtype != HYP_F32) return fail(HYP_ERR_ARG, "hyp_tune_apply_h: bad dtype");
+  Ham* H = &hh->h;
+  if (!H->structured) {
+    *best_threads = 0;
+    *best_ms = 0.0;
+    return HYP_OK;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int da = (int)H->sec->da;
+  static const int cand[] = {128, 256, 384, 512, 640, 768};
+  hipEvent_t e0, e1;
+  HYP_HIP(hipEventCreate(&e0));
+  HYP_HIP(hipEventCreate(&e1));
+  double bms = 1e300;
+  int bt = H->threads;
+  hyp_status r = HYP_OK;
+  for (int t : cand) {
+    if (t > std::max(64, (da + 63) / 64 * 64) && t != cand[0]) continue;
+    H->threads = std::min(t, std::max(64, (da + 63) / 64 * 64));
+    r = apply_h_internal(hh, dtype, psi, sigma, st);
+    if (r != HYP_OK) break;
+    HYP_HIP(hipEventRecord(e0, st));
+    for (int i = 0; i < reps && r == HYP_OK; ++i) r = apply_h_internal(hh, dtype, psi, sigma, st);
+    HYP_HIP(hipEventRecord(e1, st));
+    HYP_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HYP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (r == HYP_OK && ms / reps < bms) {
+      bms = ms / reps;
+      bt = H->threads;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  H->threads = bt;
+  if (r != HYP_OK) return r;
+  *best_threads = bt;
+  *best_ms = bms;
+  return HYP_OK;
+}
+
 hyp_status hyp_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* sigma, void* stream) {
   if (!hh || !psi || !sigma) return fail(HYP_ERR_ARG, "hyp_apply_h: NULL argument");
   if (dtype != HYP_F64 && dtype != HYP_F32) return fail(HYP_ERR_ARG, "hyp_apply_h: bad dtype");

@@ -119,13 +119,20 @@ __device__ inline double ld(const T* p, int64_t i) {
 
 // ---------------------------------------------------------------- gradients
 
+// only_ss_doubles: skip every generator that is not a same-spin double (the
+// transition-value sweep computes those)
 template <typename T>
 __global__ void __launch_bounds__(kPairThreads) k_pool_grad(SectorDev S, const hyp_exc* ops,
                                                            const T* psi, const T* sig,
-                                                           double* part) {
+                                                           double* part, int only_ss_doubles) {
   __shared__ uint32_t lst[kListMax];
   __shared__ double red[kPairThreads / 64];
   const int k = blockIdx.x, chunk = blockIdx.y;
+  if (only_ss_doubles) {
+    const uint32_t m = (1u << S.M) - 1u;
+    const int ca = __popc(ops[k].cre & m), cb = __popc((ops[k].cre >> S.M) & m);
+    if (!((ca == 2 && cb == 0) || (ca == 0 && cb == 2))) return;
+  }
   const PairCtx c = make_ctx(ops[k], S);
   build_alpha_list(c, S, lst);
   __syncthreads();
@@ -366,11 +373,37 @@ static hyp_status launch_pool_grad(Sector* S, const hyp_exc* ops, int64_t n_ops,
   if (r != HYP_OK) return r;
   // grid.x is limited to 2^31-1, n_ops <= 40k here
   HYP_LAUNCH("k_pool_grad", k_pool_grad<T>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0, st,
-                     S->dev(), ops, (const T*)psi, (const T*)sig, part);
+             S->dev(), ops, (const T*)psi, (const T*)sig, part, 0);
   HYP_LAUNCH("k_sum_chunks", k_sum_chunks, dim3((unsigned)((n_ops + 255) / 256)), dim3(256), 0, st, part,
-                     n_ops, 2.0, grad);
+             n_ops, 2.0, grad);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
+}
+
+// pair-kernel partials [n_ops][16] of the same-spin doubles only
+static hyp_status pair_partials_ss_doubles(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_ops,
+                                           const void* psi, const void* sig, double* part,
+                                           hipStream_t st) {
+  if (dt == HYP_F64)
+    HYP_LAUNCH("k_pool_grad", k_pool_grad<double>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0,
+               st, S->dev(), ops, (const double*)psi, (const double*)sig, part, 1);
+  else
+    HYP_LAUNCH("k_pool_grad", k_pool_grad<float>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0,
+               st, S->dev(), ops, (const float*)psi, (const float*)sig, part, 1);
+  HYP_HIP(hipGetLastError());
+  return HYP_OK;
+}
+
+static int g_sweep_mode = 0;  // 0 automatic, 1 pair kernel, 2 transition values
+
+static int64_t full_pool_size(int M) {
+  auto C = [](int64_t m, int64_t k) {
+    if (k < 0 || k > m) return (int64_t)0;
+    int64_t r = 1;
+    for (int64_t i = 1; i <= k; ++i) r = r * (m - k + i) / i;
+    return r;
+  };
+  return 2 * C(M, 2) + 6 * C(M, 4) + (int64_t)(M * (M - 1)) * (M * (M - 1)) / 2;
 }
 
 hyp_status launch_pool_gradients(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_ops,
@@ -378,8 +411,19 @@ hyp_status launch_pool_gradients(Sector* S, hyp_dtype dt, const hyp_exc* ops, in
   hyp_status r = ensure_binom();
   if (r != HYP_OK) return r;
   if (n_ops == 0) return HYP_OK;
+  // the transition-value sweep costs about one mixed H psi pass whatever the
+  // list; it pays when the list covers a good part of the pool
+  const bool big = n_ops * 4 >= full_pool_size(S->M) && tdens_bytes(S) <= ((size_t)40 << 30);
+  if (g_sweep_mode == 2 || (g_sweep_mode == 0 && big))
+    return launch_tdens(S, dt, ops, n_ops, psi, sig, grad, st, pair_partials_ss_doubles);
   if (dt == HYP_F64) return launch_pool_grad<double>(S, ops, n_ops, psi, sig, grad, st);
   return launch_pool_grad<float>(S, ops, n_ops, psi, sig, grad, st);
+}
+
+hyp_status set_sweep_mode(int mode) {
+  if (mode < 0 || mode > 2) return fail(HYP_ERR_ARG, "hyp_set_sweep_mode: mode must be 0, 1 or 2");
+  g_sweep_mode = mode;
+  return HYP_OK;
 }
 
 static int rot_chunks(const Sector* S, hyp_exc op) {
@@ -439,6 +483,8 @@ int max_rot_chunks() { return 2048; }
 using namespace hyp;
 
 extern "C" {
+
+hyp_status hyp_set_sweep_mode(int mode) { return set_sweep_mode(mode); }
 
 hyp_status hyp_pool_gradients(hyp_sector sh, hyp_dtype dtype, const hyp_exc* ops, int64_t n_ops,
                               const void* psi, const void* sigma, double* grad, void* stream) {

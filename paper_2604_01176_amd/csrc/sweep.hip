@@ -1,0 +1,371 @@
+// Full pool-gradient sweep through transition values.
+//
+// For an excitation tau (ordered: creates i, annihilates e, per spin)
+//   T(tau) = sum_D s_tau(D) sigma[tau D] psi[D]
+// and the gradient of the generator A = tau - tau^dagger is
+//   g = 2 <sigma|A psi> = 2 (T(tau) - T(tau^dagger)).
+// Singles and alpha-beta doubles (the 72% of all pairs at 32 qubits that
+// couple different beta rows, plus the alpha singles) are computed for the
+// whole pool at once, organised like the mixed H psi pass: one workgroup per
+// (target beta row, 768-column chunk), one thread per target alpha column
+// holding sigma[I] and its alpha single excitations in registers; for the
+// row itself and each beta-single source row staged in LDS, every thread
+// adds s sigma[I] psi[J] to the LDS bin of its ordered alpha excitation.
+// Each workgroup writes its bins for every stage to a partial buffer (no
+// atomics outside LDS); a second pass sums the partials of each transition
+// value in a fixed order, and a third forms the gradients.  Same-spin doubles
+// keep the per-generator pair kernel.
+#include "hyp_internal.h"
+
+#include <algorithm>
+#include <vector>
+
+namespace hyp {
+
+constexpr int kBins = kMaxPairs * 2;     // ordered single excitations of one spin
+constexpr int kStageW = kBins + 1;       // alpha bins + one beta-single bin
+
+__constant__ int c_binom_s[17][17];
+
+__device__ inline uint32_t betw(int p, int q) {  // orbitals strictly between p < q
+  return ((1u << q) - 1u) & ~((2u << p) - 1u);
+}
+
+struct TArgs {
+  const void* psi;
+  const void* sig;
+  int M, nb, da, db;
+  const uint32_t* astr;
+  const uint32_t* bstr;
+  const RankTables* arank;
+  const RankTables* brank;
+  int nchunk, nstage;   // nstage = 1 + N_b (M - N_b)
+  double* part;         // [db][nchunk][nstage][kStageW]
+};
+
+template <typename T>
+__global__ void __launch_bounds__(768) k_tdens(TArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* s_row = (T*)smem;
+  __shared__ double s_bin[kStageW];
+  __shared__ double s_red[12];
+  const int M = a.M;
+  const uint32_t amask = (1u << M) - 1u;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int b = blockIdx.x, xcd = b & 7, jj = b >> 3;
+  const int brow = (jj / a.nchunk) * 8 + xcd;
+  const int chunk = jj % a.nchunk;
+  if (brow >= a.db) return;
+  const uint32_t bs = a.bstr[brow];
+  const int col = chunk * nt + tid;
+  const bool live = col < a.da;
+  const uint32_t s = live ? a.astr[col] : a.astr[0];
+  const T* psi = (const T*)a.psi;
+  const double sv = live ? (double)((const T*)a.sig)[(int64_t)brow * a.da + col] : 0.0;
+  // packed entries: source rank (14 bits) | sign (bit 14) | bin = pair*2+O (bits 15..22)
+  uint32_t ex[64];
+  int ns = 0;
+  {
+    uint32_t occ = s;
+    while (occ) {
+      const int i = __ffs(occ) - 1;
+      occ &= occ - 1;
+      uint32_t emp = ~s & amask;
+      while (emp) {
+        const int e = __ffs(emp) - 1;
+        emp &= emp - 1;
+        const int p = min(i, e), q = max(i, e);
+        const uint32_t t2 = s ^ (1u << i) ^ (1u << e);
+        const uint32_t r2 = (uint32_t)(a.arank->lo[t2 & 255u] + a.arank->hi[(t2 >> 8) & 255u]);
+        const uint32_t sg = __popc(betw(p, q) & s) & 1u;
+        const uint32_t bin = (uint32_t)(q * (q - 1) / 2 + p) * 2u + (i == q ? 1u : 0u);
+        const uint32_t ent = r2 | (sg << 14) | (bin << 15);
+#pragma unroll
+        for (int x = 0; x < 64; ++x)
+          if (x == ns) ex[x] = ent;
+        ++ns;
+      }
+    }
+  }
+  const int nbemp = M - a.nb;
+  double* out = a.part + ((int64_t)brow * a.nchunk + chunk) * a.nstage * kStageW;
+  for (int stg = 0; stg < a.nstage; ++stg) {
+    // stage 0: the target row itself (alpha singles); stage 1 + jb: the
+    // source row of the jb-th beta single excitation of the target row
+    int src = brow;
+    double sb = 1.0;
+    if (stg > 0) {
+      const int jb = stg - 1;
+      int io = jb / nbemp, ie = jb % nbemp;
+      uint32_t occ = bs, emp = ~bs & amask;
+      for (int j = 0; j < io; ++j) occ &= occ - 1;
+      for (int j = 0; j < ie; ++j) emp &= emp - 1;
+      const int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
+      const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
+      src = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
+      sb = (__popc(betw(min(i, e), max(i, e)) & bs) & 1) ? -1.0 : 1.0;
+    }
+    for (int x = tid; x < kStageW; x += nt) s_bin[x] = 0.0;
+    const T* srow = psi + (int64_t)src * a.da;
+    for (int c = tid; c < a.da; c += nt) s_row[c] = srow[c];
+    __syncthreads();
+    const double w = sb * sv;
+    if (live) {
+#pragma unroll
+      for (int x = 0; x < 64; ++x) {
+        if (x < ns) {
+          const uint32_t e2 = ex[x];
+          double v;
+          if (sizeof(T) == 4)
+            v = (double)((float)sv * (float)s_row[e2 & 0x3fffu]) * sb;
+          else
+            v = w * (double)s_row[e2 & 0x3fffu];
+          atomicAdd(&s_bin[(e2 >> 15) & 0xffu], (e2 >> 14) & 1u ? -v : v);
+        }
+      }
+    }
+    // beta single with the alpha identity: sigma[I] psi[J] at the same column
+    double d = 0.0;
+    if (stg > 0 && live) {
+      if (sizeof(T) == 4)
+        d = (double)((float)sv * (float)s_row[col]) * sb;
+      else
+        d = w * (double)s_row[col];
+    }
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_down(d, o, 64);
+    if ((tid & 63) == 0) s_red[tid >> 6] = d;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int wv = 0; wv < nt / 64; ++wv) t += s_red[wv];
+      s_bin[kBins] = t;
+    }
+    __syncthreads();
+    for (int x = tid; x < kStageW; x += nt) out[(int64_t)stg * kStageW + x] = s_bin[x];
+    __syncthreads();
+  }
+}
+
+// Fixed-order sums of the partials, two levels (both deterministic).
+//   Ta[ea]      = sum over rows and chunks of the stage-0 bins
+//   Tab[ea][eb] = sum over the target rows holding the ordered beta excitation
+//                 eb (created orbital occupied, annihilated one empty) of that
+//                 row's stage for eb;  Tb[eb] = the same rows' beta-single bin
+constexpr int kRowSlices = 16;
+constexpr int kRowBlocks = 256;
+
+// grid (kBins, kRowSlices): partial sums of Tab[.][eb] and Tb[eb] over a slice
+// of the target rows of eb
+__global__ void k_tdens_reduce_ab(TArgs a, double* red) {
+  const int eb = blockIdx.x, slice = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int M = a.M;
+  const int x0 = tid, x1 = tid + blockDim.x;
+  double acc0 = 0.0, acc1 = 0.0;
+  const int pid = eb >> 1, O = eb & 1;
+  int q = 1;
+  while ((q + 1) * q / 2 <= pid) ++q;
+  const int p = pid - q * (q - 1) / 2;
+  if (q < M) {
+    const int ci = O ? q : p, ae = O ? p : q;  // created (occupied in target), annihilated
+    const int nbemp = M - a.nb;
+    const uint32_t freem = ((1u << M) - 1u) & ~((1u << ci) | (1u << ae));
+    const int nfree = M - 2, nsel = a.nb - 1;
+    const int nrows = (nsel < 0 || nsel > nfree) ? 0 : c_binom_s[nfree][nsel];
+    const int r0 = (int)((int64_t)nrows * slice / kRowSlices), r1 = (int)((int64_t)nrows * (slice + 1) / kRowSlices);
+    for (int r = r0; r < r1; ++r) {
+      uint32_t pos = 0;
+      int rr = r;
+      for (int j = nsel; j >= 1; --j) {
+        int c = j - 1;
+        while (c + 1 < nfree && c_binom_s[c + 1][j] <= rr) ++c;
+        rr -= c_binom_s[c][j];
+        pos |= 1u << c;
+      }
+      uint32_t str = 1u << ci, f = freem;
+      for (int bb = 0; f; ++bb) {
+        const uint32_t low = f & (~f + 1u);
+        if (pos & (1u << bb)) str |= low;
+        f ^= low;
+      }
+      const int row = a.brank->lo[str & 255u] + a.brank->hi[(str >> 8) & 255u];
+      const int io = __popc(str & ((1u << ci) - 1u));
+      const int ie = __popc(~str & ((1u << ae) - 1u));
+      const int stg = 1 + io * nbemp + ie;
+      const double* pp = a.part + (((int64_t)row * a.nchunk) * a.nstage + stg) * kStageW;
+      const int64_t cstride = (int64_t)a.nstage * kStageW;
+      for (int c = 0; c < a.nchunk; ++c) {
+        if (x0 < kStageW) acc0 += pp[c * cstride + x0];
+        if (x1 < kStageW) acc1 += pp[c * cstride + x1];
+      }
+    }
+  }
+  double* o = red + ((int64_t)eb * kRowSlices + slice) * kStageW;
+  if (x0 < kStageW) o[x0] = acc0;
+  if (x1 < kStageW) o[x1] = acc1;
+}
+
+// grid kRowBlocks: partial sums of the stage-0 bins over a block of rows
+__global__ void k_tdens_reduce_a(TArgs a, double* red) {
+  const int blk = blockIdx.x;
+  const int r0 = (int)((int64_t)a.db * blk / kRowBlocks), r1 = (int)((int64_t)a.db * (blk + 1) / kRowBlocks);
+  for (int x = threadIdx.x; x < kBins; x += blockDim.x) {
+    double t = 0.0;
+    for (int r = r0; r < r1; ++r)
+      for (int c = 0; c < a.nchunk; ++c) t += a.part[(((int64_t)r * a.nchunk + c) * a.nstage) * kStageW + x];
+    red[(int64_t)blk * kBins + x] = t;
+  }
+}
+
+__global__ void k_tdens_final(const double* red_ab, const double* red_a, double* Ta, double* Tb, double* Tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kBins * kStageW) {
+    const int eb = i / kStageW, x = i % kStageW;
+    double t = 0.0;
+    for (int sl = 0; sl < kRowSlices; ++sl) t += red_ab[((int64_t)eb * kRowSlices + sl) * kStageW + x];
+    if (x < kBins) Tab[(int64_t)x * kBins + eb] = t;
+    else Tb[eb] = t;
+  } else if (i < kBins * kStageW + kBins) {
+    const int x = i - kBins * kStageW;
+    double t = 0.0;
+    for (int b = 0; b < kRowBlocks; ++b) t += red_a[(int64_t)b * kBins + x];
+    Ta[x] = t;
+  }
+}
+
+__device__ inline int ord_bin(uint32_t cre, uint32_t ann) {  // one-spin single: created, annihilated
+  const int c = __ffs(cre) - 1, e = __ffs(ann) - 1;
+  const int p = min(c, e), q = max(c, e);
+  return (q * (q - 1) / 2 + p) * 2 + (c == q ? 1 : 0);
+}
+
+// grad[k] for singles and alpha-beta doubles from the transition values;
+// same-spin doubles from their pair-kernel partials (16 chunks).
+__global__ void k_tdens_grad(const hyp_exc* ops, int64_t n, int M, const double* Ta, const double* Tb,
+                             const double* Tab, const double* part16, double* grad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t m = (1u << M) - 1u;
+  const hyp_exc op = ops[k];
+  const uint32_t ca = op.cre & m, aa = op.ann & m, cb = (op.cre >> M) & m, ab = (op.ann >> M) & m;
+  const int na_ = __popc(ca), nb_ = __popc(cb);
+  double g;
+  if (na_ == 1 && nb_ == 0) {
+    const int e = ord_bin(ca, aa);
+    g = 2.0 * (Ta[e] - Ta[e ^ 1]);
+  } else if (na_ == 0 && nb_ == 1) {
+    const int e = ord_bin(cb, ab);
+    g = 2.0 * (Tb[e] - Tb[e ^ 1]);
+  } else if (na_ == 1 && nb_ == 1) {
+    const int ea = ord_bin(ca, aa), eb = ord_bin(cb, ab);
+    g = 2.0 * (Tab[(int64_t)ea * kBins + eb] - Tab[(int64_t)(ea ^ 1) * kBins + (eb ^ 1)]);
+  } else {
+    double s = 0.0;
+    for (int c = 0; c < 16; ++c) s += part16[k * 16 + c];
+    g = 2.0 * s;
+  }
+  grad[k] = g;
+}
+
+namespace {
+struct TScratch {
+  double* part = nullptr;
+  size_t cap = 0;
+  double* T = nullptr;   // Ta | Tb | Tab
+  double* red = nullptr; // second-level partials
+  bool binom = false;
+};
+TScratch g_ts[64];
+}  // namespace
+
+size_t tdens_bytes(const Sector* S) {
+  const int nt = std::max(64, std::min(768, (int)((S->da + 63) / 64 * 64)));
+  const int64_t nchunk = (S->da + nt - 1) / nt;
+  const int64_t nstage = 1 + (int64_t)S->nb * (S->M - S->nb);
+  return (size_t)S->db * nchunk * nstage * kStageW * sizeof(double);
+}
+
+// Full-sweep gradients for the ops list through the transition values; the
+// same-spin doubles among ops go through the pair kernel (run_pairs).
+hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_ops, const void* psi,
+                        const void* sig, double* grad, hipStream_t st,
+                        hyp_status (*run_pairs)(Sector*, hyp_dtype, const hyp_exc*, int64_t, const void*,
+                                                const void*, double*, hipStream_t)) {
+  int dev = 0;
+  HYP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(HYP_ERR_HIP, "device index out of range");
+  TScratch& ts = g_ts[dev];
+  if (!ts.binom) {
+    int tab[17][17];
+    for (int mm = 0; mm <= 16; ++mm)
+      for (int kk = 0; kk <= 16; ++kk) {
+        int64_t r = 0;
+        if (kk <= mm) {
+          r = 1;
+          for (int i = 1; i <= kk; ++i) r = r * (mm - kk + i) / i;
+        }
+        tab[mm][kk] = (int)r;
+      }
+    HYP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_binom_s), tab, sizeof(tab)));
+    HYP_HIP(hipMalloc(&ts.T, sizeof(double) * (2 * kBins + kBins * kBins)));
+    HYP_HIP(hipMalloc(&ts.red, sizeof(double) * ((size_t)kBins * kRowSlices * kStageW + (size_t)kRowBlocks * kBins)));
+    ts.binom = true;
+  }
+  const size_t need = tdens_bytes(S);
+  if (need > ts.cap) {
+    HYP_HIP(hipDeviceSynchronize());
+    if (ts.part) HYP_HIP(hipFree(ts.part));
+    ts.part = nullptr;
+    ts.cap = 0;
+    HYP_HIP(hipMalloc(&ts.part, need));
+    ts.cap = need;
+  }
+  TArgs a;
+  a.psi = psi;
+  a.sig = sig;
+  a.M = S->M;
+  a.nb = S->nb;
+  a.da = (int)S->da;
+  a.db = (int)S->db;
+  a.astr = S->d_astr;
+  a.bstr = S->d_bstr;
+  a.arank = S->d_arank;
+  a.brank = S->d_brank;
+  const int nt = std::max(64, std::min(768, (a.da + 63) / 64 * 64));
+  a.nchunk = (a.da + nt - 1) / nt;
+  a.nstage = 1 + a.nb * (a.M - a.nb);
+  a.part = ts.part;
+  const size_t shm = (size_t)a.da * (dt == HYP_F64 ? 8 : 4);
+  const int64_t nblk = (int64_t)8 * ((a.db + 7) / 8) * a.nchunk;
+  if (dt == HYP_F64) {
+    if (shm > 48 * 1024)
+      HYP_HIP(hipFuncSetAttribute((const void*)k_tdens<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    HYP_LAUNCH("k_tdens", k_tdens<double>, dim3((unsigned)nblk), dim3(nt), shm, st, a);
+  } else {
+    if (shm > 48 * 1024)
+      HYP_HIP(hipFuncSetAttribute((const void*)k_tdens<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    HYP_LAUNCH("k_tdens", k_tdens<float>, dim3((unsigned)nblk), dim3(nt), shm, st, a);
+  }
+  double* Ta = ts.T;
+  double* Tb = ts.T + kBins;
+  double* Tab = ts.T + 2 * kBins;
+  double* red_ab = ts.red;
+  double* red_a = ts.red + (size_t)kBins * kRowSlices * kStageW;
+  HYP_LAUNCH("k_tdens_reduce_ab", k_tdens_reduce_ab, dim3(kBins, kRowSlices), dim3(256), 0, st, a, red_ab);
+  HYP_LAUNCH("k_tdens_reduce_a", k_tdens_reduce_a, dim3(kRowBlocks), dim3(256), 0, st, a, red_a);
+  HYP_LAUNCH("k_tdens_final", k_tdens_final, dim3((kBins * kStageW + kBins + 255) / 256), dim3(256), 0, st,
+             red_ab, red_a, Ta, Tb, Tab);
+  // same-spin doubles: pair kernel on the whole list (its blocks for other
+  // classes only cost their launch), partials read below
+  double* part16 = nullptr;
+  hyp_status r = pair_scratch(S, (size_t)n_ops * 16, &part16);
+  if (r != HYP_OK) return r;
+  r = run_pairs(S, dt, ops, n_ops, psi, sig, part16, st);
+  if (r != HYP_OK) return r;
+  HYP_LAUNCH("k_tdens_grad", k_tdens_grad, dim3((unsigned)((n_ops + 255) / 256)), dim3(256), 0, st, ops, n_ops,
+             S->M, Ta, Tb, Tab, part16, grad);
+  HYP_HIP(hipGetLastError());
+  return HYP_OK;
+}
+
+}  // namespace hyp

@@ -35,11 +35,20 @@ def _run_pair(hyp, w, n_iter, dtype="f64", use_graph=True):
             break
     sel = [r["selected"] for r in recs if r["selected"] >= 0]
     prob = SectorProblem(w.n_orb, w.n_alpha, w.n_beta, x, z, c, cre, ann)
+    checks = []
 
-    def force(it, ties, own):
-        return sel[it]
+    def force(it, gvec, own):
+        # the GPU pick must be the oracle's argmax up to a near-tie: both
+        # optimisers stop at max|dE/dtheta| <= 1e-9, so gradients of the two
+        # runs differ by ~1e-9; below |g| ~ 1e-7 the selection is noise
+        k = sel[it]
+        gm = float(np.abs(gvec).max())
+        checks.append((it, k, own, float(abs(gvec[k])), gm))
+        assert abs(gvec[k]) >= gm * (1 - 1e-6) - 1e-7, (it, k, own, abs(gvec[k]), gm)
+        return k
 
     log = run_adapt(prob, len(sel), force=force)
+    log.checks = checks
     return A, recs, sel, log, (x, z, c, h, g)
 
 
@@ -47,12 +56,14 @@ def test_adapt_8q_fp64_parity_and_fci():
     import paper_2604_01176_amd as hyp
     w = synth.WORKLOADS["h4_8q"]
     A, recs, sel, log, (x, z, c, h, g) = _run_pair(hyp, w, w.iterations)
-    assert len(sel) == len(log.selected)
-    assert log.selected == sel  # forced picks were all inside the oracle's tie sets
+    n = len(log.selected)  # the oracle may stop earlier (max|g| < 1e-10 at noise level)
+    assert n >= 1 and log.selected == sel[:n]  # every pick passed the near-tie check in force()
+    print("selection checks (it, gpu, oracle, |g_gpu_pick|, max|g|):", log.checks)
     e_gpu = np.array([r["energy"] for r in recs if r["selected"] >= 0])
     e_orc = np.array(log.energies)
-    assert np.abs(e_gpu - e_orc).max() < 1e-9
-    assert all(r["converged"] for r in recs if r["selected"] >= 0)
+    assert np.abs(e_gpu[:n] - e_orc).max() < 1e-9
+    assert np.all(e_gpu[n:] >= e_orc[-1] - 1e-9)
+    assert all(r["converged"] for r in recs[:n])
     # variational: non-increasing and above the FCI energy (dense diagonalisation)
     basis = brute.sector_basis(w.n_orb, w.n_alpha, w.n_beta)
     efci = brute.fci(brute.sector_matrix(brute.fermion_hamiltonian(h, g), basis))
@@ -90,7 +101,9 @@ def test_adapt_16q_fp64_parity():
     w = synth.WORKLOADS["h8_16q"]
     A, recs, sel, log, _ = _run_pair(hyp, w, 8)
     e_gpu = np.array([r["energy"] for r in recs if r["selected"] >= 0])
-    assert log.selected == sel
+    n = len(log.selected)
+    assert n == len(sel) and log.selected == sel
+    print("selection checks (it, gpu, oracle, |g_gpu_pick|, max|g|):", log.checks)
     assert np.abs(e_gpu - np.array(log.energies)).max() < 1e-9
     assert np.all(np.diff(e_gpu) <= 1e-10)
 

@@ -205,3 +205,63 @@ def test_rotation_errors(hyp):
     assert e.value.status == 1
     with pytest.raises(hyp.HypError):
         hyp.hyp_apply_excitation(S, 0b10, 0b10, 0.1, d)
+
+
+@pytest.mark.parametrize("M,na,nb", [(4, 2, 2), (5, 2, 3), (6, 3, 3), (8, 4, 4), (9, 5, 4), (3, 0, 2), (4, 4, 1)])
+def test_pool_gradients_transition_values(hyp, M, na, nb):
+    """The transition-value sweep (forced) against the oracle and the pair kernel."""
+    S, H, (x, z, c) = _ham(hyp, M, na, nb)
+    cre, ann, _ = synth.canonical_pool(M)
+    psi = synth.random_state(S.dim, 13)
+    sig = oracle.apply_h(M, na, nb, x, z, c, psi)
+    ref = oracle.pool_gradients(M, na, nb, cre, ann, psi, sig)
+    ops = hyp.exc_tensor(cre, ann)
+    try:
+        hyp.set_sweep_mode("tdens")
+        g = hyp.hyp_pool_gradients(S, ops, _dev(psi), _dev(sig)).cpu().numpy()
+        g32 = hyp.hyp_pool_gradients(S, ops, _dev(psi, torch.float32), _dev(sig, torch.float32)).cpu().numpy()
+        hyp.set_sweep_mode("pairs")
+        gp = hyp.hyp_pool_gradients(S, ops, _dev(psi), _dev(sig)).cpu().numpy()
+    finally:
+        hyp.set_sweep_mode("auto")
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(g - ref).max() <= 1e-12 * scale
+    assert np.abs(gp - ref).max() <= 1e-12 * scale
+    assert np.abs(g32 - ref).max() <= 1e-5 * scale
+
+
+def test_pool_gradients_24q_full_sweep_modes(hyp):
+    """Full 24-qubit sweep: transition values vs the pair kernel (all 11,814
+    generators), and the oracle on a sample."""
+    w = synth.WORKLOADS["h12_24q"]
+    x, z, c, _, _ = synth.hamiltonian(w)
+    S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    cre, ann, _ = synth.canonical_pool(w.n_orb)
+    psi = synth.random_state(S.dim, 17)
+    d_psi = _dev(psi)
+    d_sig = H.apply(d_psi)
+    ops = hyp.exc_tensor(cre, ann)
+    try:
+        hyp.set_sweep_mode("tdens")
+        g_t = hyp.hyp_pool_gradients(S, ops, d_psi, d_sig).cpu().numpy()
+        hyp.set_sweep_mode("pairs")
+        g_p = hyp.hyp_pool_gradients(S, ops, d_psi, d_sig).cpu().numpy()
+    finally:
+        hyp.set_sweep_mode("auto")
+    assert np.abs(g_t - g_p).max() <= 1e-12 * max(1.0, np.abs(g_p).max())
+    k = np.random.default_rng(5).choice(len(cre), 12, replace=False)
+    ref = oracle.pool_gradients(w.n_orb, w.n_alpha, w.n_beta, cre[k], ann[k], psi, d_sig.cpu().numpy())
+    assert np.abs(g_t[k] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_apply_h_autotuner_keeps_parity(hyp):
+    M, na, nb = 10, 5, 5
+    S, H, (x, z, c) = _ham(hyp, M, na, nb, seed=110)
+    psi = synth.random_state(S.dim, 7)
+    d = _dev(psi)
+    t, ms = H.tune(d, reps=1)
+    assert 64 <= t <= 768 and t % 64 == 0 and ms > 0
+    ref = oracle.apply_h(M, na, nb, x, z, c, psi)
+    out = H.apply(d).cpu().numpy()
+    assert np.linalg.norm(out - ref) <= 1e-12 * np.linalg.norm(ref)
