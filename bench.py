@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--fp32-study", type=int, default=0, metavar="ITERS",
                     help="FP32-storage vs FP64 error study over ITERS ADAPT iterations (JSON lines)")
+    ap.add_argument("--adapt-compare", type=int, default=0, metavar="ITERS",
+                    help="screened FP32 vs plain FP64 ADAPT iterations on the workload (JSON lines)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (hardware-counter calibration)")
     args = ap.parse_args()
@@ -80,6 +82,9 @@ def main():
     w = synth.WORKLOADS[args.workload]
     if args.fp32_study:
         fp32_study(w, args.fp32_study)
+        return
+    if args.adapt_compare:
+        adapt_compare(w, args.adapt_compare)
         return
     M, na, nb = w.n_orb, w.n_alpha, w.n_beta
     t0 = time.time()
@@ -201,6 +206,67 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def adapt_compare(w, n_iter):
+    """The screen is trained on the GPU with the library's own kernels on
+    exact sweeps of the 8-, 16- and 24-qubit workloads; then on the target
+    workload: one plain FP64 ADAPT iteration per step (full sweep + BFGS)
+    against screened FP32 iterations (top-512 + 256 audit, full sweep on the
+    judge iterations, BFGS)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2604_01176_amd as hyp
+    from paper_2604_01176_amd import screen as scr
+
+    t0 = time.time()
+    Xs, ts = [], []
+    for name, iters in (("h4_8q", 6), ("h8_16q", 6), ("h12_24q", 4)):
+        v = synth.WORKLOADS[name]
+        x, z, c, h, g = synth.hamiltonian(v)
+        cre, ann, cls = synth.canonical_pool(v.n_orb)
+        S = hyp.Sector(v.n_orb, v.n_alpha, v.n_beta)
+        H = hyp.Hamiltonian(S, x, z, c)
+        A = hyp.Adapt(H, cre, ann, max_iter=iters + 1)
+        stat, qidx = scr.static_features(v.n_orb, cre, ann, cls, h, g)
+        X, t = scr.collect_rows(A, scr.FeatureState(S, stat, qidx), iters)
+        Xs.append(X)
+        ts.append(t)
+    X = np.concatenate(Xs)
+    t = np.concatenate(ts)
+    net = scr.MLP(synth.mlp_init(0), 1 << 16)
+    losses = scr.train(net, X, t, epochs=4, batch=1024, lr=1e-3)
+    print(json.dumps({"screen_training_rows": int(X.shape[0]), "losses": [round(l, 4) for l in losses],
+                      "train_s": round(time.time() - t0, 1)}), flush=True)
+
+    M, na, nb = w.n_orb, w.n_alpha, w.n_beta
+    x, z, c, h, g = synth.hamiltonian(w)
+    cre, ann, cls = synth.canonical_pool(M)
+    S = hyp.Sector(M, na, nb)
+    H = hyp.Hamiltonian(S, x, z, c)
+    A64 = hyp.Adapt(H, cre, ann, max_iter=n_iter + 1)
+    A32 = hyp.Adapt(H, cre, ann, dtype="f32", max_iter=n_iter + 1)
+    stat, qidx = scr.static_features(M, cre, ann, cls, h, g)
+    sc = scr.Screen(A32, S, stat, qidx, net, K=512, audit=256, judge_every=10, seed=42)
+    for it in range(n_iter):
+        torch.cuda.synchronize()
+        t1 = time.time()
+        r64 = A64.iterate()
+        t2 = time.time()
+        info = sc.iterate(it)
+        t3 = time.time()
+        print(json.dumps({"iteration": it, "plain_fp64": {"selected": r64["selected"], "E": r64["energy"],
+                                                         "grad_ms": round(r64["grad_ms"], 1),
+                                                         "opt_ms": round(r64["opt_ms"], 1),
+                                                         "iter_s": round(t2 - t1, 2)},
+                          "screened_fp32": {"selected": info["selected"], "E": info["energy"],
+                                            "judge": info["judge"], "fallback": info["fallback"],
+                                            "n_exact": info["n_exact"], "grad_ms": round(info["grad_ms"], 1),
+                                            "opt_ms": round(info["opt_ms"], 1), "iter_s": round(t3 - t2, 2)},
+                          "same_selection": r64["selected"] == info["selected"]}), flush=True)
+    print(json.dumps({"final_E_plain_fp64": A64.energy_fp64(), "final_E_screened_fp32_replayed_fp64": A32.energy_fp64(),
+                      "dE": A32.energy_fp64() - A64.energy_fp64()}), flush=True)
 
 
 def fp32_study(w, n_iter):

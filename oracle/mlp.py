@@ -46,15 +46,6 @@ def pack(W1, b1, W2, b2, W3, b3):
     return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3, np.atleast_1d(b3)])
 
 
-def init_params(seed: int):
-    """He-uniform weights, zero biases (a seeded input of the screen)."""
-    rng = np.random.default_rng(seed)
-    W1 = rng.uniform(-1, 1, (HID, N_FEAT)) * math.sqrt(6.0 / N_FEAT)
-    W2 = rng.uniform(-1, 1, (HID, HID)) * math.sqrt(6.0 / HID)
-    W3 = rng.uniform(-1, 1, HID) * math.sqrt(6.0 / HID)
-    return pack(W1, np.zeros(HID), W2, np.zeros(HID), W3, np.zeros(1)).astype(np.float32)
-
-
 def forward(p, X, quant=True):
     q = bf16 if quant else (lambda v: np.asarray(v, dtype=np.float64))
     W1, b1, W2, b2, W3, b3 = unpack(p)

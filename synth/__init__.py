@@ -269,6 +269,22 @@ def sector_dim(n_orb: int, n_alpha: int, n_beta: int) -> int:
 
 
 # ---------------------------------------------------------------------------
+# screen network initialisation
+# ---------------------------------------------------------------------------
+
+def mlp_init(seed: int, n_feat: int = 32, hidden: int = 256):
+    """Seeded initial parameters of the 32-256-256-1 screen network, float32,
+    layout W1[256][32], b1, W2[256][256], b2, W3[256], b3: He-uniform weights,
+    zero biases."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.uniform(-1, 1, (hidden, n_feat)) * math.sqrt(6.0 / n_feat)
+    W2 = rng.uniform(-1, 1, (hidden, hidden)) * math.sqrt(6.0 / hidden)
+    W3 = rng.uniform(-1, 1, hidden) * math.sqrt(6.0 / hidden)
+    return np.concatenate([W1.ravel(), np.zeros(hidden), W2.ravel(), np.zeros(hidden), W3,
+                           np.zeros(1)]).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
 # workload configurations
 # ---------------------------------------------------------------------------
 

@@ -32,7 +32,7 @@ def _bf16_bits(x):
 
 
 def test_mlp_forward_parity(scr):
-    p = om.init_params(11)
+    p = synth.mlp_init(11)
     rng = np.random.default_rng(0)
     X = rng.standard_normal((1000, om.N_FEAT))
     net = scr.MLP(p, 1024)
@@ -44,7 +44,7 @@ def test_mlp_forward_parity(scr):
 
 
 def test_mlp_train_step_parity(scr):
-    p = om.init_params(5)
+    p = synth.mlp_init(5)
     rng = np.random.default_rng(1)
     B = 1024
     X = rng.standard_normal((B, om.N_FEAT))
@@ -97,7 +97,7 @@ def test_occupations_and_features(hyp, scr):
 
 
 def test_rank_scores(scr):
-    net = scr.MLP(om.init_params(0), 64)
+    net = scr.MLP(synth.mlp_init(0), 64)
     y = np.round(np.random.default_rng(4).standard_normal(5000), 1).astype(np.float32)
     order = net.rank(torch.from_numpy(y).cuda()).cpu().numpy()
     assert np.array_equal(order, np.argsort(-y, kind="stable"))
@@ -118,7 +118,7 @@ def _train_on(hyp, scr, workloads, n_iter, seed=0):
         ts.append(t)
     X = np.concatenate(Xs)
     t = np.concatenate(ts)
-    net = scr.MLP(om.init_params(seed), 1024)
+    net = scr.MLP(synth.mlp_init(seed), 1024)
     losses = scr.train(net, X, t, epochs=4, batch=1024, lr=1e-3)
     return net, losses
 

@@ -27,7 +27,7 @@ def test_bf16_rounding_matches_definition():
 def test_mlp_backward_finite_differences():
     """Exact (unquantised) backward against central differences of the loss."""
     rng = np.random.default_rng(0)
-    p = om.init_params(3).astype(np.float64)
+    p = synth.mlp_init(3).astype(np.float64)
     X = rng.standard_normal((32, om.N_FEAT))
     t = rng.standard_normal(32)
     loss, _, g = om.loss_grad(p, X, t, quant=False)
