@@ -43,6 +43,59 @@ def hpsi_gather_bytes(m, S=8):
     return (m["nnz"] + m["dim"]) * S + 16 * m["T"]
 
 
+def kernel_flops(name, m):
+    """Algorithmic flops of one launch: 2 per structural nonzero (FMA) the
+    kernel handles, 2 per (target, source) product of the transition-value
+    pass, 2 M N K for the Gram GEMMs, 4 per pair for the pair kernel."""
+    dim, sa, sb = m["dim"], m["sa"], m["sb"]
+    if name == "k_mixed":
+        return 2.0 * dim * (sa * sb + sa + sb + 1), "alu"
+    if name == "k_ss_apply":  # mean of the alpha- and the beta-row launch
+        return 2.0 * dim * (1 + (sa + m["dda"] + sb + m["ddb"]) / 2), "alu"
+    if name == "k_tdens":
+        return 2.0 * dim * (sa + sb * (sa + 1)), "alu"
+    if name == "rocblas_dgemm_gram_a":
+        return 2.0 * m["da"] * m["da"] * m["db"], "mfma"
+    if name == "rocblas_dgemm_gram_b":
+        return 2.0 * m["db"] * m["db"] * m["da"], "mfma"
+    if name == "k_pool_grad":
+        return 4.0 * m["pairs"], "alu"
+    return 2.0 * m["nnz"], "alu"
+
+
+def roofline(name, ms, m):
+    flops, bound = kernel_flops(name, m)
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"bound": bound, "kernel": name, "achieved": round(achieved, 3), "peak": FP64_VECTOR_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_TFLOPS, 4), "traffic": None,
+            "ms_per_launch": round(ms, 3)}
+
+
+def source_digest():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_01176_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_digest") != source_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,31 +185,20 @@ def main():
     for k_, (ms, n) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
         print(f"[bench]   {k_:20s} {ms / max(n, 1):10.3f} ms/launch x {n}", file=sys.stderr)
 
-    hpsi_kernels = ("k_transpose", "k_same_spin", "k_mixed")
+    hpsi_kernels = ("k_transpose", "k_ss_apply", "k_mixed")
     hpsi_ms = sum(prof.get(k, (0.0, 0))[0] for k in hpsi_kernels) / args.steps
     hpsi_bytes = hpsi_gather_bytes(m)
     value = hpsi_bytes / (hpsi_ms * 1e-3) / 1e9
-    sweep_ms = sum(prof.get(k, (0.0, 0))[0] for k in ("k_pool_grad", "k_sum_chunks")) / args.steps
+    sweep_kernels = ("k_pool_grad", "k_sum_chunks", "k_tdens", "k_tdens_reduce_ab", "k_tdens_reduce_a",
+                     "k_tdens_final", "k_gram_grad", "k_tdens_grad", "k_widen", "rocblas_dgemm_gram_a",
+                     "rocblas_dgemm_gram_b")
+    sweep_ms = sum(prof.get(k, (0.0, 0))[0] for k in sweep_kernels) / args.steps
 
     # dominant kernel of the step and its roofline
     dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
     dom_ms = prof[dom][0] / prof[dom][1]
-    if dom == "k_mixed":
-        # alpha-beta doubles + the beta-single dressing and the alpha-beta diagonal:
-        # one FMA per structural nonzero handled by this kernel
-        flops = 2.0 * m["dim"] * (m["sa"] * m["sb"] + m["sa"] + m["sb"] + 1)
-    elif dom == "k_same_spin":
-        flops = 2.0 * m["dim"] * (1 + (m["sa"] + m["dda"] + m["sb"] + m["ddb"]) / 2)
-    elif dom == "k_pool_grad":
-        flops = 4.0 * m["pairs"]
-    else:
-        flops = 2.0 * m["nnz"]
-    achieved = flops / (dom_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
-            "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_VECTOR_TFLOPS, 4), "traffic": None,
-            "ms_per_launch": round(dom_ms, 3)}
-
+    roof = roofline(dom, dom_ms, m)
+    roof["traffic"] = measured_traffic(w.name, dom)
     cpu = None
     if args.cpu_seconds > 0:
         import oracle

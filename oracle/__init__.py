@@ -73,6 +73,8 @@ def lib():
         L.orc_pair_count.restype = i64
         L.orc_pair_count.argtypes = [ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32]
         L.orc_occupations.argtypes = [ci, ci, ci, f64p, f64p]
+        L.orc_pair_list.restype = i64
+        L.orc_pair_list.argtypes = [ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, i64p, i64p, ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -177,3 +179,14 @@ def occupations(M, na, nb, psi):
     out = np.empty(2 * M)
     lib().orc_occupations(M, na, nb, _p(psi), _p(out))
     return out
+
+
+def pair_list(M, na, nb, cre, ann):
+    """(D, D', s) arrays of one generator's pairs, by literal application of tau."""
+    n = pair_count(M, na, nb, cre, ann)
+    src = np.empty(n, dtype=np.int64)
+    dst = np.empty(n, dtype=np.int64)
+    sg = np.empty(n, dtype=np.int8)
+    m = lib().orc_pair_list(M, na, nb, int(cre), int(ann), _p(src), _p(dst), _p(sg))
+    assert m == n
+    return src, dst, sg

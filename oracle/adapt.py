@@ -77,6 +77,63 @@ class SectorProblem:
         return E, grad
 
 
+class DenseSectorProblem(SectorProblem):
+    """The same definitions on small sectors with faster linear algebra: H as
+    the dense sector matrix of the Pauli sum (element by element from the
+    Pauli strings), each generator A as a sparse matrix of its literal pairs,
+    exp(theta A) = 1 + sin(theta) A + (1 - cos(theta)) A^2 (A^3 = -A), and
+    g_k = 2 sigma^T A_k psi.  For dim <= ~5,000."""
+
+    def __init__(self, M, na, nb, x, z, c, cre, ann):
+        super().__init__(M, na, nb, x, z, c, cre, ann)
+        import scipy.sparse as sp
+        from . import brute, pair_list
+        self.H = brute.sector_matrix_from_paulis(M, na, nb, x, z, c).real
+        self._sp = sp
+        self._pair_list = pair_list
+        self._A = {}
+
+    def A(self, k):
+        if k not in self._A:
+            src, dst, sg = self._pair_list(self.M, self.na, self.nb, self.cre[k], self.ann[k])
+            s = sg.astype(np.float64)
+            # A|D> = s|D'>, A|D'> = -s|D>
+            rows = np.concatenate([dst, src])
+            cols = np.concatenate([src, dst])
+            vals = np.concatenate([s, -s])
+            self._A[k] = self._sp.csr_matrix((vals, (rows, cols)), shape=(self.dim, self.dim))
+        return self._A[k]
+
+    def hpsi(self, psi):
+        return self.H @ psi
+
+    def rot(self, k, th, v):
+        Av = self.A(k) @ v
+        return v + np.sin(th) * Av + (1.0 - np.cos(th)) * (self.A(k) @ Av)
+
+    def state(self, ops, thetas):
+        psi = self.hf()
+        for k, th in zip(ops, thetas):
+            psi = self.rot(k, th, psi)
+        return psi
+
+    def energy_grad(self, ops, thetas):
+        psi = self.state(ops, thetas)
+        sig = self.hpsi(psi)
+        E = float(psi @ sig)
+        grad = np.zeros(len(ops))
+        for i in range(len(ops)):
+            v = self.state(ops[: i + 1], thetas[: i + 1])
+            v = self.A(ops[i]) @ v
+            for kk, th in zip(ops[i + 1:], thetas[i + 1:]):
+                v = self.rot(kk, th, v)
+            grad[i] = 2.0 * float(sig @ v)
+        return E, grad
+
+    def gradients(self, psi, sig):
+        return np.array([2.0 * float(sig @ (self.A(k) @ psi)) for k in range(len(self.cre))])
+
+
 def run_adapt(prob: SectorProblem, n_iter: int, tie_tol: float = 1e-9, gtol: float = 1e-9,
               force=None) -> AdaptLog:
     """force(iteration, gradients, own_choice) -> index lets a caller
@@ -88,7 +145,10 @@ def run_adapt(prob: SectorProblem, n_iter: int, tie_tol: float = 1e-9, gtol: flo
     log.e_hf = dot(psi, prob.hpsi(psi))
     for it in range(n_iter):
         sig = prob.hpsi(psi)
-        g = pool_gradients(prob.M, prob.na, prob.nb, prob.cre, prob.ann, psi, sig)
+        if isinstance(prob, DenseSectorProblem):
+            g = prob.gradients(psi, sig)
+        else:
+            g = pool_gradients(prob.M, prob.na, prob.nb, prob.cre, prob.ann, psi, sig)
         ag = np.abs(g)
         gm = float(ag.max())
         if gm < 1e-10:

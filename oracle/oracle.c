@@ -268,3 +268,22 @@ void orc_occupations(int M, int na, int nb, const double *psi, double *occ) {
             if (b & (1u << q)) occ[q] += psi[d] * psi[d];
     }
 }
+
+/* The pairs (D, D' = tau D, sign) of one generator, by literal application
+ * of tau to every sector state; returns their number (arrays hold at least
+ * orc_pair_count entries). */
+int64_t orc_pair_list(int M, int na, int nb, uint32_t cre, uint32_t ann, int64_t *src, int64_t *dst,
+                      int8_t *sign) {
+    sector_t S; sector_init(&S, M, na, nb);
+    int64_t n = 0;
+    for (int64_t d = 0; d < S.dim; ++d) {
+        uint32_t bp;
+        int s = orc_apply_tau(cre, ann, sector_unrank(&S, d), &bp);
+        if (!s) continue;
+        src[n] = d;
+        dst[n] = sector_rank(&S, bp);
+        sign[n] = (int8_t)s;
+        ++n;
+    }
+    return n;
+}

@@ -157,8 +157,6 @@ hyp_status launch_adjoint_step(Sector* S, hyp_dtype dt, hyp_exc op, const double
 int max_rot_chunks();
 size_t tdens_bytes(const Sector* S);
 hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_ops, const void* psi,
-                        const void* sig, double* grad, hipStream_t st,
-                        hyp_status (*run_pairs)(Sector*, hyp_dtype, const hyp_exc*, int64_t, const void*,
-                                                const void*, double*, hipStream_t));
+                        const void* sig, double* grad, hipStream_t st);
 
 }  // namespace hyp

@@ -119,20 +119,13 @@ __device__ inline double ld(const T* p, int64_t i) {
 
 // ---------------------------------------------------------------- gradients
 
-// only_ss_doubles: skip every generator that is not a same-spin double (the
-// transition-value sweep computes those)
 template <typename T>
 __global__ void __launch_bounds__(kPairThreads) k_pool_grad(SectorDev S, const hyp_exc* ops,
                                                            const T* psi, const T* sig,
-                                                           double* part, int only_ss_doubles) {
+                                                           double* part) {
   __shared__ uint32_t lst[kListMax];
   __shared__ double red[kPairThreads / 64];
   const int k = blockIdx.x, chunk = blockIdx.y;
-  if (only_ss_doubles) {
-    const uint32_t m = (1u << S.M) - 1u;
-    const int ca = __popc(ops[k].cre & m), cb = __popc((ops[k].cre >> S.M) & m);
-    if (!((ca == 2 && cb == 0) || (ca == 0 && cb == 2))) return;
-  }
   const PairCtx c = make_ctx(ops[k], S);
   build_alpha_list(c, S, lst);
   __syncthreads();
@@ -373,23 +366,9 @@ static hyp_status launch_pool_grad(Sector* S, const hyp_exc* ops, int64_t n_ops,
   if (r != HYP_OK) return r;
   // grid.x is limited to 2^31-1, n_ops <= 40k here
   HYP_LAUNCH("k_pool_grad", k_pool_grad<T>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0, st,
-             S->dev(), ops, (const T*)psi, (const T*)sig, part, 0);
+             S->dev(), ops, (const T*)psi, (const T*)sig, part);
   HYP_LAUNCH("k_sum_chunks", k_sum_chunks, dim3((unsigned)((n_ops + 255) / 256)), dim3(256), 0, st, part,
              n_ops, 2.0, grad);
-  HYP_HIP(hipGetLastError());
-  return HYP_OK;
-}
-
-// pair-kernel partials [n_ops][16] of the same-spin doubles only
-static hyp_status pair_partials_ss_doubles(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_ops,
-                                           const void* psi, const void* sig, double* part,
-                                           hipStream_t st) {
-  if (dt == HYP_F64)
-    HYP_LAUNCH("k_pool_grad", k_pool_grad<double>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0,
-               st, S->dev(), ops, (const double*)psi, (const double*)sig, part, 1);
-  else
-    HYP_LAUNCH("k_pool_grad", k_pool_grad<float>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0,
-               st, S->dev(), ops, (const float*)psi, (const float*)sig, part, 1);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
 }
@@ -415,7 +394,7 @@ hyp_status launch_pool_gradients(Sector* S, hyp_dtype dt, const hyp_exc* ops, in
   // list; it pays when the list covers a good part of the pool
   const bool big = n_ops * 4 >= full_pool_size(S->M) && tdens_bytes(S) <= ((size_t)40 << 30);
   if (g_sweep_mode == 2 || (g_sweep_mode == 0 && big))
-    return launch_tdens(S, dt, ops, n_ops, psi, sig, grad, st, pair_partials_ss_doubles);
+    return launch_tdens(S, dt, ops, n_ops, psi, sig, grad, st);
   if (dt == HYP_F64) return launch_pool_grad<double>(S, ops, n_ops, psi, sig, grad, st);
   return launch_pool_grad<float>(S, ops, n_ops, psi, sig, grad, st);
 }

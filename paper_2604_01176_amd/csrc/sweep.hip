@@ -1,5 +1,11 @@
 // Full pool-gradient sweep through transition values.
 //
+// Same-spin doubles use the Gram matrices of the two states instead:
+//   G_a[I][J] = sum_beta sigma[beta][I] psi[beta][J]   (alpha strings I, J)
+//   G_b[I][J] = sum_alpha sigma[I][alpha] psi[J][alpha] (beta strings)
+// (two plain FP64 GEMMs on the matrix cores, rocBLAS), then
+// T(tau) = sum over the generator's string pairs of s G[I][J].
+//
 // For an excitation tau (ordered: creates i, annihilates e, per spin)
 //   T(tau) = sum_D s_tau(D) sigma[tau D] psi[D]
 // and the gradient of the generator A = tau - tau^dagger is
@@ -16,6 +22,8 @@
 // value in a fixed order, and a third forms the gradients.  Same-spin doubles
 // keep the per-generator pair kernel.
 #include "hyp_internal.h"
+
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <vector>
@@ -240,9 +248,9 @@ __device__ inline int ord_bin(uint32_t cre, uint32_t ann) {  // one-spin single:
 }
 
 // grad[k] for singles and alpha-beta doubles from the transition values;
-// same-spin doubles from their pair-kernel partials (16 chunks).
+// same-spin doubles were written by k_gram_grad.
 __global__ void k_tdens_grad(const hyp_exc* ops, int64_t n, int M, const double* Ta, const double* Tb,
-                             const double* Tab, const double* part16, double* grad) {
+                             const double* Tab, double* grad) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const uint32_t m = (1u << M) - 1u;
@@ -260,11 +268,90 @@ __global__ void k_tdens_grad(const hyp_exc* ops, int64_t n, int M, const double*
     const int ea = ord_bin(ca, aa), eb = ord_bin(cb, ab);
     g = 2.0 * (Tab[(int64_t)ea * kBins + eb] - Tab[(int64_t)(ea ^ 1) * kBins + (eb ^ 1)]);
   } else {
-    double s = 0.0;
-    for (int c = 0; c < 16; ++c) s += part16[k * 16 + c];
-    g = 2.0 * s;
+    return;  // same-spin double: k_gram_grad
   }
   grad[k] = g;
+}
+
+__device__ inline uint32_t gram_string(uint32_t cm, uint32_t am, int M, int N, int i) {
+  // i-th string (colex over the free orbitals) holding am and not cm
+  const uint32_t freem = ((1u << M) - 1u) & ~(cm | am);
+  const int nfree = __popc(freem), nsel = N - __popc(am);
+  uint32_t pos = 0;
+  int r = i;
+  for (int j = nsel; j >= 1; --j) {
+    int c = j - 1;
+    while (c + 1 < nfree && c_binom_s[c + 1][j] <= r) ++c;
+    r -= c_binom_s[c][j];
+    pos |= 1u << c;
+  }
+  uint32_t s = am, f = freem;
+  for (int b = 0; f; ++b) {
+    const uint32_t low = f & (~f + 1u);
+    if (pos & (1u << b)) s |= low;
+    f ^= low;
+  }
+  return s;
+}
+
+__device__ inline int gram_sign(uint32_t cm, uint32_t am, uint32_t s) {
+  int odd = 0;
+  uint32_t a = am;
+  while (a) {
+    const int q = __ffs(a) - 1;
+    a &= a - 1;
+    odd += __popc(s & ((1u << q) - 1u));
+    s ^= 1u << q;
+  }
+  uint32_t c = cm;
+  while (c) {
+    const int q = 31 - __clz(c);
+    c ^= 1u << q;
+    odd += __popc(s & ((1u << q) - 1u));
+    s ^= 1u << q;
+  }
+  return odd & 1;
+}
+
+// One workgroup per generator: same-spin doubles get
+// g = 2 sum_{J} s (G[tau J][J] - G[J][tau J]) over the generator's strings J
+// (G column-major: G(I, J) at G[I + J * D]); other generators are skipped.
+__global__ void k_gram_grad(const hyp_exc* ops, int M, int na, int nb, const double* Ga, int64_t da,
+                            const double* Gb, int64_t db, const RankTables* arank, const RankTables* brank,
+                            double* grad) {
+  __shared__ double red[4];
+  const int64_t k = blockIdx.x;
+  const uint32_t m = (1u << M) - 1u;
+  const hyp_exc op = ops[k];
+  const int ca = __popc(op.cre & m), cb = __popc((op.cre >> M) & m);
+  const bool alpha = ca == 2 && cb == 0, beta = ca == 0 && cb == 2;
+  if (!alpha && !beta) return;
+  const uint32_t cm = alpha ? (op.cre & m) : ((op.cre >> M) & m);
+  const uint32_t am = alpha ? (op.ann & m) : ((op.ann >> M) & m);
+  const int N = alpha ? na : nb;
+  const double* G = alpha ? Ga : Gb;
+  const int64_t D = alpha ? da : db;
+  const RankTables* R = alpha ? arank : brank;
+  const int nfree = M - 4, nsel = N - 2;
+  const int cnt = (nsel < 0 || nsel > nfree) ? 0 : c_binom_s[nfree][nsel];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const uint32_t J = gram_string(cm, am, M, N, i);
+    const uint32_t I = J ^ cm ^ am;
+    const int64_t rj = R->lo[J & 255u] + R->hi[(J >> 8) & 255u];
+    const int64_t ri = R->lo[I & 255u] + R->hi[(I >> 8) & 255u];
+    const double v = G[ri + rj * D] - G[rj + ri * D];
+    acc += gram_sign(cm, am, J) ? -v : v;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) grad[k] = 2.0 * (red[0] + red[1] + red[2] + red[3]);
+}
+
+__global__ void k_widen(const float* a, int64_t n, double* b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (double)a[i];
 }
 
 namespace {
@@ -274,6 +361,9 @@ struct TScratch {
   double* T = nullptr;   // Ta | Tb | Tab
   double* red = nullptr; // second-level partials
   bool binom = false;
+  rocblas_handle blas = nullptr;
+  double* gram = nullptr;  // G_a | G_b | widened psi | widened sigma
+  size_t gram_cap = 0;
 };
 TScratch g_ts[64];
 }  // namespace
@@ -285,12 +375,10 @@ size_t tdens_bytes(const Sector* S) {
   return (size_t)S->db * nchunk * nstage * kStageW * sizeof(double);
 }
 
-// Full-sweep gradients for the ops list through the transition values; the
-// same-spin doubles among ops go through the pair kernel (run_pairs).
+// Full-sweep gradients for the ops list: transition values for singles and
+// alpha-beta doubles, Gram matrices for same-spin doubles.
 hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_ops, const void* psi,
-                        const void* sig, double* grad, hipStream_t st,
-                        hyp_status (*run_pairs)(Sector*, hyp_dtype, const hyp_exc*, int64_t, const void*,
-                                                const void*, double*, hipStream_t)) {
+                        const void* sig, double* grad, hipStream_t st) {
   int dev = 0;
   HYP_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) return fail(HYP_ERR_HIP, "device index out of range");
@@ -355,15 +443,55 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
   HYP_LAUNCH("k_tdens_reduce_a", k_tdens_reduce_a, dim3(kRowBlocks), dim3(256), 0, st, a, red_a);
   HYP_LAUNCH("k_tdens_final", k_tdens_final, dim3((kBins * kStageW + kBins + 255) / 256), dim3(256), 0, st,
              red_ab, red_a, Ta, Tb, Tab);
-  // same-spin doubles: pair kernel on the whole list (its blocks for other
-  // classes only cost their launch), partials read below
-  double* part16 = nullptr;
-  hyp_status r = pair_scratch(S, (size_t)n_ops * 16, &part16);
-  if (r != HYP_OK) return r;
-  r = run_pairs(S, dt, ops, n_ops, psi, sig, part16, st);
-  if (r != HYP_OK) return r;
+  // same-spin doubles: Gram matrices on the matrix cores, then the gather
+  const int64_t da = S->da, db = S->db;
+  const size_t gneed = (size_t)(da * da + db * db) + (dt == HYP_F32 ? 2 * (size_t)S->dim : 0);
+  if (gneed > ts.gram_cap) {
+    HYP_HIP(hipDeviceSynchronize());
+    if (ts.gram) HYP_HIP(hipFree(ts.gram));
+    ts.gram = nullptr;
+    ts.gram_cap = 0;
+    HYP_HIP(hipMalloc(&ts.gram, gneed * sizeof(double)));
+    ts.gram_cap = gneed;
+  }
+  if (!ts.blas && rocblas_create_handle(&ts.blas) != rocblas_status_success)
+    return fail(HYP_ERR_HIP, "rocblas_create_handle failed");
+  double* Ga = ts.gram;
+  double* Gb = Ga + da * da;
+  const double* X = (const double*)psi;
+  const double* Y = (const double*)sig;
+  if (dt == HYP_F32) {
+    double* xw = Gb + db * db;
+    double* yw = xw + S->dim;
+    HYP_LAUNCH("k_widen", k_widen, dim3(4096), dim3(256), 0, st, (const float*)psi, S->dim, xw);
+    HYP_LAUNCH("k_widen", k_widen, dim3(4096), dim3(256), 0, st, (const float*)sig, S->dim, yw);
+    X = xw;
+    Y = yw;
+  }
+  if (rocblas_set_stream(ts.blas, st) != rocblas_status_success)
+    return fail(HYP_ERR_HIP, "rocblas_set_stream failed");
+  const double one = 1.0, zero = 0.0;
+  // column-major view: sigma, psi are D_a x D_b with leading dimension D_a
+  // G_a = Y X^T (D_a x D_a), G_b = Y^T X (D_b x D_b)
+  rocblas_status bs;
+  {
+    ProfScope ps_("rocblas_dgemm_gram_a", st);
+    bs = rocblas_dgemm(ts.blas, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)da,
+                       (rocblas_int)da, (rocblas_int)db, &one, Y, (rocblas_int)da, X, (rocblas_int)da, &zero,
+                       Ga, (rocblas_int)da);
+  }
+  if (bs != rocblas_status_success) return fail(HYP_ERR_HIP, "rocblas_dgemm (alpha Gram) failed");
+  {
+    ProfScope ps_("rocblas_dgemm_gram_b", st);
+    bs = rocblas_dgemm(ts.blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)db,
+                       (rocblas_int)db, (rocblas_int)da, &one, Y, (rocblas_int)da, X, (rocblas_int)da, &zero,
+                       Gb, (rocblas_int)db);
+  }
+  if (bs != rocblas_status_success) return fail(HYP_ERR_HIP, "rocblas_dgemm (beta Gram) failed");
+  HYP_LAUNCH("k_gram_grad", k_gram_grad, dim3((unsigned)n_ops), dim3(256), 0, st, ops, S->M, S->na, S->nb, Ga, da,
+             Gb, db, S->d_arank, S->d_brank, grad);
   HYP_LAUNCH("k_tdens_grad", k_tdens_grad, dim3((unsigned)((n_ops + 255) / 256)), dim3(256), 0, st, ops, n_ops,
-             S->M, Ta, Tb, Tab, part16, grad);
+             S->M, Ta, Tb, Tab, grad);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
 }

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from oracle import brute
-from oracle.adapt import SectorProblem, run_adapt
+from oracle.adapt import DenseSectorProblem, SectorProblem, run_adapt
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -34,7 +34,8 @@ def _run_pair(hyp, w, n_iter, dtype="f64", use_graph=True):
         if r["selected"] < 0:
             break
     sel = [r["selected"] for r in recs if r["selected"] >= 0]
-    prob = SectorProblem(w.n_orb, w.n_alpha, w.n_beta, x, z, c, cre, ann)
+    cls_ = DenseSectorProblem if w.dim <= 5000 else SectorProblem
+    prob = cls_(w.n_orb, w.n_alpha, w.n_beta, x, z, c, cre, ann)
     checks = []
 
     def force(it, gvec, own):
@@ -97,9 +98,10 @@ def test_adapt_step1_closed_form(hyp):
 
 
 def test_adapt_16q_fp64_parity():
+    """The 16-qubit workload's 30 ADAPT iterations against the oracle."""
     import paper_2604_01176_amd as hyp
     w = synth.WORKLOADS["h8_16q"]
-    A, recs, sel, log, _ = _run_pair(hyp, w, 8)
+    A, recs, sel, log, _ = _run_pair(hyp, w, w.iterations)
     e_gpu = np.array([r["energy"] for r in recs if r["selected"] >= 0])
     n = len(log.selected)
     assert n == len(sel) and log.selected == sel

@@ -351,3 +351,28 @@ def test_gradient_at_hf_is_slater_condon_element():
             assert abs(grad[k] + 2 * s2 * Hs[j, 0]) < 1e-12
         else:
             assert grad[k] == 0.0
+
+
+def test_dense_sector_problem_equals_plain():
+    """The dense/sparse ADAPT helper equals the term-by-term oracle."""
+    from oracle.adapt import DenseSectorProblem, SectorProblem, run_adapt
+    w = synth.WORKLOADS["h4_8q"]
+    x, z, c, h, g = synth.hamiltonian(w)
+    cre, ann, _ = synth.canonical_pool(w.n_orb)
+    p1 = SectorProblem(w.n_orb, w.n_alpha, w.n_beta, x, z, c, cre, ann)
+    p2 = DenseSectorProblem(w.n_orb, w.n_alpha, w.n_beta, x, z, c, cre, ann)
+    ops, th = [5, 80, 3], np.array([0.1, -0.2, 0.3])
+    e1, g1 = p1.energy_grad(ops, th)
+    e2, g2 = p2.energy_grad(ops, th)
+    assert abs(e1 - e2) < 1e-13 and np.abs(g1 - g2).max() < 1e-13
+    psi = p1.state(ops, th)
+    sig = p1.hpsi(psi)
+    ref = oracle.pool_gradients(w.n_orb, w.n_alpha, w.n_beta, cre, ann, psi, sig)
+    assert np.abs(p2.gradients(psi, sig) - ref).max() < 1e-13
+    l1, l2 = run_adapt(p1, 4), run_adapt(p2, 4)
+    assert l1.selected == l2.selected
+    assert np.abs(np.array(l1.energies) - np.array(l2.energies)).max() < 1e-10
+    # ADAPT energies: non-increasing, above FCI
+    basis = brute.sector_basis(w.n_orb, w.n_alpha, w.n_beta)
+    efci = brute.fci(brute.sector_matrix(brute.fermion_hamiltonian(h, g), basis))
+    assert np.all(np.diff(l2.energies) <= 1e-12) and min(l2.energies) >= efci - 1e-10
