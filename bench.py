@@ -113,8 +113,9 @@ def main():
                     help="only run a plain device-to-device copy of MIB MiB (hardware-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the row-partitioned design is described, not built).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the beta-row-partitioned design is described in the design notes, not implemented).",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -129,13 +129,18 @@ hyp_status hyp_pool_gradients(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_
                               double* grad_dev, void* stream);
 
 /* Strategy of hyp_pool_gradients: 0 automatic (default), 1 the per-generator
- * pair kernel, 2 transition values.  The transition-value sweep computes
- * T(tau) = sum_D s sigma[tau D] psi[D] for every single and alpha-beta double
- * excitation at once (g = 2 (T(tau) - T(tau^dagger))) in a pass shaped like
- * the mixed H psi pass, with a per-device scratch of
- * C(M,N_b) * ceil(C(M,N_a)/768) * (1 + N_b (M - N_b)) * 241 doubles (27 GB at
- * 32 qubits); automatic mode uses it when n_ops covers at least a quarter of
- * the full pool and that scratch is at most 40 GiB.  Process-wide setting. */
+ * pair kernel, 2 transition values, 3 transition values with per-stage bins.
+ * The transition-value sweep computes T(tau) = sum_D s sigma[tau D] psi[D]
+ * for every single and alpha-beta double excitation at once
+ * (g = 2 (T(tau) - T(tau^dagger))), and the same-spin doubles from the two
+ * Gram matrices sigma^T psi and sigma psi^T (FP64 GEMMs; per-device scratch of
+ * C(M,N_a)^2 + C(M,N_b)^2 doubles, plus 2 dim doubles in FP32 mode).  Mode 2
+ * walks the row pairs of each beta excitation with register accumulators
+ * (small scratch); mode 3 bins every (beta row, stage) in LDS and needs
+ * C(M,N_b) * ceil(C(M,N_a)/768) * (1 + N_b (M - N_b)) * 241 doubles of scratch
+ * (27 GB at 32 qubits, refused above 40 GiB).  Automatic mode uses mode 2 when
+ * n_ops covers at least a quarter of the full pool, else mode 1.
+ * Process-wide setting. */
 hyp_status hyp_set_sweep_mode(int mode);
 
 /* psi <- exp(theta A) psi in place (the exponentiated fermionic operator):
@@ -203,12 +208,13 @@ typedef struct {
   int32_t tie_count;  /* size of the tie set */
   int32_t n_evals;    /* energy+gradient evaluations of the optimiser */
   int32_t bfgs_iters;
-  int32_t converged;  /* 1 if the gradient tolerance was met */
+  int32_t converged;  /* 1 if max|dE/dtheta| <= gtol, or the line search stalled below 100 gtol */
   int32_t reserved;
   double gmax;        /* max |g| over the computed gradients */
   double energy_before;  /* E of the state the gradients were taken on */
   double energy;      /* E after optimisation */
   double grad_ms, opt_ms;  /* host wall time of the two phases */
+  double grad_inf;    /* max |dE/dtheta_i| at the optimiser's last point */
 } hyp_adapt_record;
 
 /* pool: host array of n_pool validated excitations (the operator pool). */

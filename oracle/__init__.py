@@ -62,6 +62,8 @@ def lib():
         L.orc_sector_unrank.argtypes = [ci, ci, ci, i64p, i64, u32p]
         L.orc_apply_h.restype = ci
         L.orc_apply_h.argtypes = [ci, ci, ci, i64, u32p, u32p, f64p, f64p, i64p, i64, f64p]
+        L.orc_apply_h_sparse.restype = ci
+        L.orc_apply_h_sparse.argtypes = [ci, ci, ci, i64, u32p, u32p, f64p, i64, i64p, f64p, f64p]
         L.orc_dot.restype = ctypes.c_double
         L.orc_dot.argtypes = [i64, f64p, f64p]
         L.orc_apply_tau.restype = ci
@@ -126,6 +128,19 @@ def apply_h(M, na, nb, x, z, c, psi, out_idx=None):
         out = np.empty(out_idx.size)
         rc = lib().orc_apply_h(M, na, nb, c.size, _p(x), _p(z), _p(c), _p(psi), _p(out_idx),
                                out_idx.size, _p(out))
+    if rc != 0:
+        raise ValueError("odd-n_Y term: Hamiltonian is not real")
+    return out
+
+
+def apply_h_sparse(M, na, nb, x, z, c, in_idx, in_val):
+    """sigma = H psi (all dim outputs) for psi given by its nonzeros."""
+    x, z, c = _u32(x), _u32(z), _f64(c)
+    in_idx = np.ascontiguousarray(in_idx, dtype=np.int64)
+    in_val = _f64(in_val)
+    out = np.empty(sector_dim(M, na, nb))
+    rc = lib().orc_apply_h_sparse(M, na, nb, c.size, _p(x), _p(z), _p(c), in_idx.size, _p(in_idx),
+                                  _p(in_val), _p(out))
     if rc != 0:
         raise ValueError("odd-n_Y term: Hamiltonian is not real")
     return out

@@ -147,6 +147,35 @@ int orc_apply_h(int M, int na, int nb, int64_t nterm, const uint32_t *x, const u
     return 0;
 }
 
+/*
+ * sigma = H psi for a psi given by its nonzeros (sector indices, values):
+ * every term applied to every nonzero basis state b, adding
+ * c_t (-1)^{n_Y/2} (-1)^{popc(z_t & b)} psi[b] to sigma[b ^ x_t] when that
+ * state is in the sector (the definition of orc_apply_h summed from the input
+ * side).  out holds all dim entries and is overwritten.  -1 on an odd-n_Y term.
+ */
+int orc_apply_h_sparse(int M, int na, int nb, int64_t nterm, const uint32_t *x, const uint32_t *z,
+                       const double *c, int64_t n_in, const int64_t *in_idx, const double *in_val,
+                       double *out) {
+    sector_t S; sector_init(&S, M, na, nb);
+    for (int64_t t = 0; t < nterm; ++t)
+        if (popc32(x[t] & z[t]) & 1) return -1;
+    #pragma omp parallel for schedule(static)
+    for (int64_t d = 0; d < S.dim; ++d) out[d] = 0.0;
+    for (int64_t i = 0; i < n_in; ++i) {
+        uint32_t b = sector_unrank(&S, in_idx[i]);
+        for (int64_t t = 0; t < nterm; ++t) {
+            uint32_t bo = b ^ x[t];
+            if (!in_sector(&S, bo)) continue;
+            int ny = popc32(x[t] & z[t]);
+            double ph = ((ny / 2) & 1) ? -1.0 : 1.0;
+            if (popc32(z[t] & b) & 1) ph = -ph;
+            out[sector_rank(&S, bo)] += c[t] * ph * in_val[i];
+        }
+    }
+    return 0;
+}
+
 double orc_dot(int64_t n, const double *a, const double *b) {
     double s = 0.0;
     for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];

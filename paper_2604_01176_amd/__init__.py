@@ -9,6 +9,7 @@ the library's HIP kernels.  Importing this package needs the built library
 from __future__ import annotations
 
 import ctypes
+import math
 
 import numpy as np
 
@@ -60,6 +61,8 @@ class Sector:
         self._h = h
         self.n_orb, self.n_alpha, self.n_beta = n_orb, n_alpha, n_beta
         self.dim = int(_lib.load().hyp_sector_dim(h))
+        self.da = math.comb(n_orb, n_alpha)
+        self.db = math.comb(n_orb, n_beta)
 
     @property
     def handle(self):
@@ -185,8 +188,9 @@ def hyp_apply_excitation(sector: Sector, cre: int, ann: int, theta: float, psi):
 
 
 def set_sweep_mode(mode: str = "auto"):
-    """hyp_set_sweep_mode: "auto", "pairs" (per-generator kernel) or "tdens"."""
-    check(_lib.load().hyp_set_sweep_mode({"auto": 0, "pairs": 1, "tdens": 2}[mode]))
+    """hyp_set_sweep_mode: "auto", "pairs" (per-generator kernel), "tdens"
+    (row-batched transition values) or "tdens_bins" (per-stage LDS bins)."""
+    check(_lib.load().hyp_set_sweep_mode({"auto": 0, "pairs": 1, "tdens": 2, "tdens_bins": 3}[mode]))
 
 
 def profile_enable(on: bool = True):

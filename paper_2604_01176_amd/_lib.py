@@ -32,7 +32,7 @@ class AdaptRecord(ctypes.Structure):
                 ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("gmax", ctypes.c_double), ("energy_before", ctypes.c_double),
                 ("energy", ctypes.c_double), ("grad_ms", ctypes.c_double),
-                ("opt_ms", ctypes.c_double)]
+                ("opt_ms", ctypes.c_double), ("grad_inf", ctypes.c_double)]
 
 
 class GradJob(ctypes.Structure):

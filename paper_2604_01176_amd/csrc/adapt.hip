@@ -277,7 +277,8 @@ static hyp_status wolfe(Adapt* A, const std::vector<double>& x, double f0,
   return HYP_OK;
 }
 
-static hyp_status bfgs(Adapt* A, std::vector<double>& x, double* fout, int* iters, int* conv) {
+static hyp_status bfgs(Adapt* A, std::vector<double>& x, double* fout, int* iters, int* conv,
+                       double* ginf) {
   const size_t n = x.size();
   std::vector<double> g(n), p(n), s(n), y(n), Hy(n);
   double f;
@@ -337,6 +338,10 @@ static hyp_status bfgs(Adapt* A, std::vector<double>& x, double* fout, int* iter
   }
   *fout = f;
   *iters = it;
+  *ginf = infnorm(g);
+  // converged: the gradient test held, or the line search could not improve
+  // on a point whose gradient is at the precision floor (100 gtol)
+  *conv = (*ginf <= A->o.gtol || (*conv == 0 && *ginf <= 100.0 * A->o.gtol)) ? 1 : 0;
   return HYP_OK;
 }
 
@@ -523,8 +528,9 @@ hyp_status hyp_adapt_select_optimize(hyp_adapt h, hyp_adapt_record* rec) {
   A.n_evals = 0;
   double f = 0.0;
   int iters = 0, conv = 0;
+  double ginf = 0.0;
   std::vector<double> x = A.theta;
-  hyp_status r = bfgs(&A, x, &f, &iters, &conv);
+  hyp_status r = bfgs(&A, x, &f, &iters, &conv, &ginf);
   if (r != HYP_OK) {
     A.ops.pop_back();
     A.theta.pop_back();
@@ -536,6 +542,7 @@ hyp_status hyp_adapt_select_optimize(hyp_adapt h, hyp_adapt_record* rec) {
   rec->n_evals = A.n_evals;
   rec->bfgs_iters = iters;
   rec->converged = conv;
+  rec->grad_inf = ginf;
   rec->opt_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
   return HYP_OK;
 }

@@ -305,7 +305,6 @@ __global__ void __launch_bounds__(768) k_mixed(MixedArgs a) {
   __shared__ double s_srow[kMaxPairs * 4];  // [(pid*2+O)*2 + sign]
   __shared__ double s_dmix[kMaxOrb];
   __shared__ double s_bdress[kMaxOrb];
-  __shared__ int s_brank;
 
   const int M = a.M;
   const uint32_t amask = (1u << M) - 1u;
@@ -374,7 +373,7 @@ __global__ void __launch_bounds__(768) k_mixed(MixedArgs a) {
   const T* psi = (const T*)a.psi;
   {
     const T* prow = psi + (int64_t)brow * a.da;
-    for (int i = tid; i < a.da; i += nt) s_row[i] = prow[i];
+    stage_row(s_row, prow, a.da, tid, nt);
   }
   __syncthreads();
 
@@ -413,7 +412,7 @@ __global__ void __launch_bounds__(768) k_mixed(MixedArgs a) {
     const int pb = pair_id(p, q);
     const int Ob = (i == q) ? 1 : 0;
     const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
-    if (tid == 0) s_brank = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
+    const int srank = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
     const int sbase = (kMaxPairs + pb) * 2 + Ob;
     const uint32_t jsb = H.sJ[kMaxPairs + pb] >> M;
     const double sgn_s = (__popc(jsb & bs) & 1) ? -1.0 : 1.0;
@@ -425,9 +424,8 @@ __global__ void __launch_bounds__(768) k_mixed(MixedArgs a) {
       s_fab[2 * x] = f;
       s_fab[2 * x + 1] = -f;
     }
-    __syncthreads();
-    const T* src = psi + (int64_t)s_brank * a.da;
-    for (int c = tid; c < a.da; c += nt) s_row[c] = src[c];
+    const T* src = psi + (int64_t)srank * a.da;
+    stage_row(s_row, src, a.da, tid, nt);
     __syncthreads();
     double dr = 0.0;
     uint32_t o = s;

@@ -140,6 +140,26 @@ struct Ham {
 hyp_status launch_dot(Sector* S, hyp_dtype dt, const void* a, const void* b, double* out,
                       hipStream_t st);
 
+// Copy n elements of a global row into LDS with all of a thread's loads in
+// flight before its first LDS store (kUnroll independent loads per round), so
+// one staging costs about one memory latency instead of one per element.
+template <typename T, int kUnroll = 72 / (int)sizeof(T)>
+__device__ inline void stage_row(T* __restrict__ dst, const T* __restrict__ src, int n, int tid, int nt) {
+  for (int base = tid; base < n; base += nt * kUnroll) {
+    T v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int c = base + u * nt;
+      v[u] = c < n ? src[c] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int c = base + u * nt;
+      if (c < n) dst[c] = v[u];
+    }
+  }
+}
+
 // shared entry points between translation units
 Sector* sector_of(hyp_sector h);
 Ham* ham_of(hyp_ham h);
@@ -157,6 +177,6 @@ hyp_status launch_adjoint_step(Sector* S, hyp_dtype dt, hyp_exc op, const double
 int max_rot_chunks();
 size_t tdens_bytes(const Sector* S);
 hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_ops, const void* psi,
-                        const void* sig, double* grad, hipStream_t st);
+                        const void* sig, double* grad, hipStream_t st, bool bins);
 
 }  // namespace hyp

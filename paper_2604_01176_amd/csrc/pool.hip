@@ -373,7 +373,7 @@ static hyp_status launch_pool_grad(Sector* S, const hyp_exc* ops, int64_t n_ops,
   return HYP_OK;
 }
 
-static int g_sweep_mode = 0;  // 0 automatic, 1 pair kernel, 2 transition values
+static int g_sweep_mode = 0;  // 0 automatic, 1 pairs, 2 transition values, 3 per-stage bins
 
 static int64_t full_pool_size(int M) {
   auto C = [](int64_t m, int64_t k) {
@@ -392,15 +392,20 @@ hyp_status launch_pool_gradients(Sector* S, hyp_dtype dt, const hyp_exc* ops, in
   if (n_ops == 0) return HYP_OK;
   // the transition-value sweep costs about one mixed H psi pass whatever the
   // list; it pays when the list covers a good part of the pool
-  const bool big = n_ops * 4 >= full_pool_size(S->M) && tdens_bytes(S) <= ((size_t)40 << 30);
+  const bool big = n_ops * 4 >= full_pool_size(S->M);
   if (g_sweep_mode == 2 || (g_sweep_mode == 0 && big))
-    return launch_tdens(S, dt, ops, n_ops, psi, sig, grad, st);
+    return launch_tdens(S, dt, ops, n_ops, psi, sig, grad, st, false);
+  if (g_sweep_mode == 3) {
+    if (tdens_bytes(S) > ((size_t)40 << 30))
+      return fail(HYP_ERR_ARG, "hyp_pool_gradients: per-stage bin scratch above 40 GiB for this sector");
+    return launch_tdens(S, dt, ops, n_ops, psi, sig, grad, st, true);
+  }
   if (dt == HYP_F64) return launch_pool_grad<double>(S, ops, n_ops, psi, sig, grad, st);
   return launch_pool_grad<float>(S, ops, n_ops, psi, sig, grad, st);
 }
 
 hyp_status set_sweep_mode(int mode) {
-  if (mode < 0 || mode > 2) return fail(HYP_ERR_ARG, "hyp_set_sweep_mode: mode must be 0, 1 or 2");
+  if (mode < 0 || mode > 3) return fail(HYP_ERR_ARG, "hyp_set_sweep_mode: mode must be 0, 1, 2 or 3");
   g_sweep_mode = mode;
   return HYP_OK;
 }

@@ -55,6 +55,8 @@ template <typename T>
 __global__ void __launch_bounds__(768) k_tdens(TArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* s_row = (T*)smem;
+  // one private bin array per wave (no contention between waves)
+  __shared__ double s_wbin[12][kBins];
   __shared__ double s_bin[kStageW];
   __shared__ double s_red[12];
   const int M = a.M;
@@ -71,6 +73,142 @@ __global__ void __launch_bounds__(768) k_tdens(TArgs a) {
   const T* psi = (const T*)a.psi;
   const double sv = live ? (double)((const T*)a.sig)[(int64_t)brow * a.da + col] : 0.0;
   // packed entries: source rank (14 bits) | sign (bit 14) | bin = pair*2+O (bits 15..22)
+  // Every string has the same number of single excitations, na (M - na).
+  // Lane l stores its n-th excitation at slot (n + l) mod that count, so the
+  // lanes of a wave, whose neighbouring strings list their excitations in
+  // nearly the same order, hit different bins at any one unrolled step
+  // instead of queueing on one LDS address.
+  const int nsx = __popc(s) * (M - __popc(s));
+  const int rot = nsx ? (tid & 63) % nsx : 0;
+  uint32_t ex[64];
+  int ns = 0;
+  {
+    uint32_t occ = s;
+    while (occ) {
+      const int i = __ffs(occ) - 1;
+      occ &= occ - 1;
+      uint32_t emp = ~s & amask;
+      while (emp) {
+        const int e = __ffs(emp) - 1;
+        emp &= emp - 1;
+        const int p = min(i, e), q = max(i, e);
+        const uint32_t t2 = s ^ (1u << i) ^ (1u << e);
+        const uint32_t r2 = (uint32_t)(a.arank->lo[t2 & 255u] + a.arank->hi[(t2 >> 8) & 255u]);
+        const uint32_t sg = __popc(betw(p, q) & s) & 1u;
+        const uint32_t bin = (uint32_t)(q * (q - 1) / 2 + p) * 2u + (i == q ? 1u : 0u);
+        const uint32_t ent = r2 | (sg << 14) | (bin << 15);
+        int pos = ns + rot;
+        if (pos >= nsx) pos -= nsx;
+#pragma unroll
+        for (int x = 0; x < 64; ++x)
+          if (x == pos) ex[x] = ent;
+        ++ns;
+      }
+    }
+  }
+  const int nbemp = M - a.nb;
+  double* out = a.part + ((int64_t)brow * a.nchunk + chunk) * a.nstage * kStageW;
+  for (int stg = 0; stg < a.nstage; ++stg) {
+    // stage 0: the target row itself (alpha singles); stage 1 + jb: the
+    // source row of the jb-th beta single excitation of the target row
+    int src = brow;
+    double sb = 1.0;
+    if (stg > 0) {
+      const int jb = stg - 1;
+      int io = jb / nbemp, ie = jb % nbemp;
+      uint32_t occ = bs, emp = ~bs & amask;
+      for (int j = 0; j < io; ++j) occ &= occ - 1;
+      for (int j = 0; j < ie; ++j) emp &= emp - 1;
+      const int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
+      const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
+      src = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
+      sb = (__popc(betw(min(i, e), max(i, e)) & bs) & 1) ? -1.0 : 1.0;
+    }
+    for (int x = tid; x < 12 * kBins; x += nt) s_wbin[x / kBins][x % kBins] = 0.0;
+    const T* srow = psi + (int64_t)src * a.da;
+    stage_row(s_row, srow, a.da, tid, nt);
+    __syncthreads();
+    const double w = sb * sv;
+    if (live) {
+#pragma unroll
+      for (int x = 0; x < 64; ++x) {
+        if (x < ns) {
+          const uint32_t e2 = ex[x];
+          double v;
+          if (sizeof(T) == 4)
+            v = (double)((float)sv * (float)s_row[e2 & 0x3fffu]) * sb;
+          else
+            v = w * (double)s_row[e2 & 0x3fffu];
+          atomicAdd(&s_wbin[tid >> 6][(e2 >> 15) & 0xffu], (e2 >> 14) & 1u ? -v : v);
+        }
+      }
+    }
+    // beta single with the alpha identity: sigma[I] psi[J] at the same column
+    double d = 0.0;
+    if (stg > 0 && live) {
+      if (sizeof(T) == 4)
+        d = (double)((float)sv * (float)s_row[col]) * sb;
+      else
+        d = w * (double)s_row[col];
+    }
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_down(d, o, 64);
+    if ((tid & 63) == 0) s_red[tid >> 6] = d;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int wv = 0; wv < nt / 64; ++wv) t += s_red[wv];
+      s_bin[kBins] = t;
+    }
+    for (int x = tid; x < kBins; x += nt) {
+      double t = 0.0;
+      for (int wv = 0; wv < nt / 64; ++wv) t += s_wbin[wv][x];
+      s_bin[x] = t;
+    }
+    __syncthreads();
+    for (int x = tid; x < kStageW; x += nt) out[(int64_t)stg * kStageW + x] = s_bin[x];
+    __syncthreads();
+  }
+}
+
+// Row-batched form of the same transition values, without atomics in the
+// inner loop.  A workgroup owns one ordered beta excitation eb (or, for the
+// alpha singles, a slice of rows paired with themselves) and one chunk of
+// target alpha columns, and walks every (target row, source row) pair of eb:
+// the source row is staged through LDS, and each thread keeps one FP64 sum per
+// alpha excitation of its column in registers,
+//   acc[x] += s_eb * sigma[target][J] * psi[source][I_x],
+// plus the alpha-identity sum for the beta single itself.  The alpha signs and
+// bins are applied once, when the sums are flushed.
+struct TRArgs {
+  const void* psi;
+  const void* sig;
+  int M, da, db;
+  const uint32_t* astr;
+  const RankTables* arank;
+  const int2* rows;   // [n_eb][K]: (source row, target row | sign << 31)
+  int K, Kid;         // row pairs per beta excitation; rows per identity slice
+  int n_eb, n_id, nchunk;
+  double* part;       // [n_eb + n_id][nchunk][kStageW]
+};
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* s_row = (T*)smem;
+  __shared__ double s_red[8];
+  const int M = a.M;
+  const uint32_t amask = (1u << M) - 1u;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // XCD-aware: the column chunks of one slot run on one XCD and stage the
+  // same source rows at about the same time
+  const int b = blockIdx.x, xcd = b & 7, jj = b >> 3;
+  const int slot = (jj / a.nchunk) * 8 + xcd;
+  const int chunk = jj % a.nchunk;
+  if (slot >= a.n_eb + a.n_id) return;
+  const int col = chunk * nt + tid;
+  const bool live = col < a.da;
+  const uint32_t s = live ? a.astr[col] : a.astr[0];
+  // packed entries: source rank (14 bits) | sign (bit 14) | bin (bits 15..22)
   uint32_t ex[64];
   int ns = 0;
   {
@@ -95,63 +233,134 @@ __global__ void __launch_bounds__(768) k_tdens(TArgs a) {
       }
     }
   }
-  const int nbemp = M - a.nb;
-  double* out = a.part + ((int64_t)brow * a.nchunk + chunk) * a.nstage * kStageW;
-  for (int stg = 0; stg < a.nstage; ++stg) {
-    // stage 0: the target row itself (alpha singles); stage 1 + jb: the
-    // source row of the jb-th beta single excitation of the target row
-    int src = brow;
-    double sb = 1.0;
-    if (stg > 0) {
-      const int jb = stg - 1;
-      int io = jb / nbemp, ie = jb % nbemp;
-      uint32_t occ = bs, emp = ~bs & amask;
-      for (int j = 0; j < io; ++j) occ &= occ - 1;
-      for (int j = 0; j < ie; ++j) emp &= emp - 1;
-      const int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
-      const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
-      src = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
-      sb = (__popc(betw(min(i, e), max(i, e)) & bs) & 1) ? -1.0 : 1.0;
-    }
-    for (int x = tid; x < kStageW; x += nt) s_bin[x] = 0.0;
-    const T* srow = psi + (int64_t)src * a.da;
-    for (int c = tid; c < a.da; c += nt) s_row[c] = srow[c];
-    __syncthreads();
-    const double w = sb * sv;
-    if (live) {
+  double acc[64];
 #pragma unroll
-      for (int x = 0; x < 64; ++x) {
-        if (x < ns) {
-          const uint32_t e2 = ex[x];
-          double v;
-          if (sizeof(T) == 4)
-            v = (double)((float)sv * (float)s_row[e2 & 0x3fffu]) * sb;
-          else
-            v = w * (double)s_row[e2 & 0x3fffu];
-          atomicAdd(&s_bin[(e2 >> 15) & 0xffu], (e2 >> 14) & 1u ? -v : v);
-        }
+  for (int x = 0; x < 64; ++x) acc[x] = 0.0;
+  double acc_id = 0.0;
+  const bool ident = slot >= a.n_eb;
+  const int row0 = ident ? (slot - a.n_eb) * a.Kid : 0;
+  const int nrows = ident ? min(a.Kid, a.db - row0) : a.K;
+  const T* psi = (const T*)a.psi;
+  const T* sig = (const T*)a.sig;
+  const int2* rl = a.rows + (int64_t)(ident ? 0 : slot) * a.K;
+  for (int k = 0; k < nrows; ++k) {
+    int src, tgt;
+    double sb = 1.0;
+    if (ident) {
+      src = tgt = row0 + k;
+    } else {
+      const int2 e = rl[k];
+      src = e.x;
+      tgt = e.y & 0x7fffffff;
+      if (e.y < 0) sb = -1.0;
+    }
+    __syncthreads();
+    stage_row(s_row, psi + (int64_t)src * a.da, a.da, tid, nt);
+    const T sv = live ? sig[(int64_t)tgt * a.da + col] : T(0);
+    __syncthreads();
+    if (live) {
+      if (sizeof(T) == 4) {
+#pragma unroll
+        for (int x = 0; x < 64; ++x)
+          if (x < ns) acc[x] += (double)((float)sv * (float)s_row[ex[x] & 0x3fffu]) * sb;
+        if (!ident) acc_id += (double)((float)sv * (float)s_row[col]) * sb;
+      } else {
+        const double w = sb * (double)sv;
+#pragma unroll
+        for (int x = 0; x < 64; ++x)
+          if (x < ns) acc[x] += w * (double)s_row[ex[x] & 0x3fffu];
+        if (!ident) acc_id += w * (double)s_row[col];
       }
     }
-    // beta single with the alpha identity: sigma[I] psi[J] at the same column
-    double d = 0.0;
-    if (stg > 0 && live) {
-      if (sizeof(T) == 4)
-        d = (double)((float)sv * (float)s_row[col]) * sb;
-      else
-        d = w * (double)s_row[col];
-    }
-    for (int o = 32; o > 0; o >>= 1) d += __shfl_down(d, o, 64);
-    if ((tid & 63) == 0) s_red[tid >> 6] = d;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int wv = 0; wv < nt / 64; ++wv) t += s_red[wv];
-      s_bin[kBins] = t;
-    }
-    __syncthreads();
-    for (int x = tid; x < kStageW; x += nt) out[(int64_t)stg * kStageW + x] = s_bin[x];
-    __syncthreads();
   }
+  // flush: per-wave LDS bins (the row buffer is free now), then one slot of
+  // the partial buffer per (slot, chunk)
+  __syncthreads();
+  double* s_bins = (double*)smem;  // [nt / 64][kBins]
+  const int nw = nt >> 6;
+  for (int i = tid; i < nw * kBins; i += nt) s_bins[i] = 0.0;
+  __syncthreads();
+  if (live) {
+#pragma unroll
+    for (int x = 0; x < 64; ++x) {
+      if (x < ns) {
+        const uint32_t e = ex[x];
+        atomicAdd(&s_bins[(tid >> 6) * kBins + ((e >> 15) & 0xffu)], (e >> 14) & 1u ? -acc[x] : acc[x]);
+      }
+    }
+  }
+  double d = acc_id;
+  for (int o = 32; o > 0; o >>= 1) d += __shfl_down(d, o, 64);
+  if ((tid & 63) == 0) s_red[tid >> 6] = d;
+  __syncthreads();
+  double* out = a.part + ((int64_t)slot * a.nchunk + chunk) * kStageW;
+  for (int x = tid; x < kBins; x += nt) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += s_bins[w * kBins + x];
+    out[x] = t;
+  }
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += s_red[w];
+    out[kBins] = t;
+  }
+}
+
+// Fixed-order sums of the row-batched partials:
+//   Tab[ea][eb] = sum over chunks of slot eb's bin ea,  Tb[eb] = the same of
+//   its identity bin,  Ta[ea] = sum over the identity slices and chunks.
+__global__ void k_tdens_rows_final(const double* part, int n_eb, int n_id, int nchunk, double* Ta, double* Tb,
+                                   double* Tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kBins * kStageW) {
+    const int eb = i / kStageW, x = i % kStageW;
+    double t = 0.0;
+    if (eb < n_eb)
+      for (int c = 0; c < nchunk; ++c) t += part[((int64_t)eb * nchunk + c) * kStageW + x];
+    if (x < kBins) Tab[(int64_t)x * kBins + eb] = t;
+    else Tb[eb] = t;
+  } else if (i < kBins * kStageW + kBins) {
+    const int x = i - kBins * kStageW;
+    double t = 0.0;
+    for (int sl = 0; sl < n_id; ++sl)
+      for (int c = 0; c < nchunk; ++c) t += part[((int64_t)(n_eb + sl) * nchunk + c) * kStageW + x];
+    Ta[x] = t;
+  }
+}
+
+// (source row, target row | sign << 31) of every ordered beta single
+// excitation eb = (created ci, annihilated ae): source rows hold ae and not
+// ci, in colex order over the other orbitals.  One thread per (eb, k).
+__global__ void k_eb_rows(int M, int nb, int n_eb, int K, const RankTables* brank, int2* rows) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_eb * K) return;
+  const int eb = (int)(i / K), k = (int)(i % K);
+  const int pid = eb >> 1, O = eb & 1;
+  int q = 1;
+  while ((q + 1) * q / 2 <= pid) ++q;
+  const int p = pid - q * (q - 1) / 2;
+  const int ci = O ? q : p, ae = O ? p : q;
+  const uint32_t freem = ((1u << M) - 1u) & ~((1u << ci) | (1u << ae));
+  const int nfree = M - 2, nsel = nb - 1;
+  uint32_t pos = 0;
+  int rr = k;
+  for (int j = nsel; j >= 1; --j) {
+    int c = j - 1;
+    while (c + 1 < nfree && c_binom_s[c + 1][j] <= rr) ++c;
+    rr -= c_binom_s[c][j];
+    pos |= 1u << c;
+  }
+  uint32_t src = 1u << ae, f = freem;
+  for (int bb = 0; f; ++bb) {
+    const uint32_t low = f & (~f + 1u);
+    if (pos & (1u << bb)) src |= low;
+    f ^= low;
+  }
+  const uint32_t tgt = src ^ (1u << ci) ^ (1u << ae);
+  const uint32_t sg = __popc(betw(p, q) & src) & 1u;
+  const int rs = brank->lo[src & 255u] + brank->hi[(src >> 8) & 255u];
+  const int rt = brank->lo[tgt & 255u] + brank->hi[(tgt >> 8) & 255u];
+  rows[i] = make_int2(rs, (int)((uint32_t)rt | (sg << 31)));
 }
 
 // Fixed-order sums of the partials, two levels (both deterministic).
@@ -364,6 +573,11 @@ struct TScratch {
   rocblas_handle blas = nullptr;
   double* gram = nullptr;  // G_a | G_b | widened psi | widened sigma
   size_t gram_cap = 0;
+  int2* rows = nullptr;    // beta excitation row pairs of the row-batched kernel
+  int rows_M = -1, rows_nb = -1;
+  size_t rows_cap = 0;
+  double* rpart = nullptr; // partials of the row-batched kernel
+  size_t rpart_cap = 0;
 };
 TScratch g_ts[64];
 }  // namespace
@@ -377,8 +591,78 @@ size_t tdens_bytes(const Sector* S) {
 
 // Full-sweep gradients for the ops list: transition values for singles and
 // alpha-beta doubles, Gram matrices for same-spin doubles.
+static int64_t binom64(int m, int k) {
+  if (k < 0 || k > m) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (m - k + i) / i;
+  return r;
+}
+
+// Transition values of singles and alpha-beta doubles (Ta, Tb, Tab) by the
+// row-batched kernel.
+static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* psi, const void* sig,
+                             double* Ta, double* Tb, double* Tab, hipStream_t st) {
+  TRArgs a;
+  a.psi = psi;
+  a.sig = sig;
+  a.M = S->M;
+  a.da = (int)S->da;
+  a.db = (int)S->db;
+  a.astr = S->d_astr;
+  a.arank = S->d_arank;
+  a.K = (int)binom64(S->M - 2, S->nb - 1);
+  a.Kid = a.K > 0 ? a.K : a.db;
+  a.n_eb = (int)(2 * binom64(S->M, 2));
+  a.n_id = (a.db + a.Kid - 1) / a.Kid;
+  const int nt = std::max(64, std::min(512, (a.da + 63) / 64 * 64));
+  a.nchunk = (a.da + nt - 1) / nt;
+  const size_t rows_need = (size_t)a.n_eb * a.K;
+  if (rows_need > 0 && (ts.rows_M != S->M || ts.rows_nb != S->nb)) {
+    if (rows_need > ts.rows_cap) {
+      HYP_HIP(hipDeviceSynchronize());
+      if (ts.rows) HYP_HIP(hipFree(ts.rows));
+      ts.rows = nullptr;
+      ts.rows_cap = 0;
+      HYP_HIP(hipMalloc(&ts.rows, rows_need * sizeof(int2)));
+      ts.rows_cap = rows_need;
+    }
+    HYP_LAUNCH("k_eb_rows", k_eb_rows, dim3((unsigned)((rows_need + 255) / 256)), dim3(256), 0, st, S->M, S->nb,
+               a.n_eb, a.K, S->d_brank, ts.rows);
+    ts.rows_M = S->M;
+    ts.rows_nb = S->nb;
+  }
+  a.rows = ts.rows;
+  const size_t pneed = (size_t)(a.n_eb + a.n_id) * a.nchunk * kStageW;
+  if (pneed > ts.rpart_cap) {
+    HYP_HIP(hipDeviceSynchronize());
+    if (ts.rpart) HYP_HIP(hipFree(ts.rpart));
+    ts.rpart = nullptr;
+    ts.rpart_cap = 0;
+    HYP_HIP(hipMalloc(&ts.rpart, pneed * sizeof(double)));
+    ts.rpart_cap = pneed;
+  }
+  a.part = ts.rpart;
+  const size_t shm = std::max((size_t)a.da * (dt == HYP_F64 ? 8 : 4), (size_t)(nt / 64) * kBins * sizeof(double));
+  const int64_t nslot = a.n_eb + a.n_id;
+  const int64_t nblk = (int64_t)8 * ((nslot + 7) / 8) * a.nchunk;
+  if (dt == HYP_F64) {
+    if (shm > 48 * 1024)
+      HYP_HIP(hipFuncSetAttribute((const void*)k_tdens_rows<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)shm));
+    HYP_LAUNCH("k_tdens_rows", k_tdens_rows<double>, dim3((unsigned)nblk), dim3(nt), shm, st, a);
+  } else {
+    if (shm > 48 * 1024)
+      HYP_HIP(hipFuncSetAttribute((const void*)k_tdens_rows<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)shm));
+    HYP_LAUNCH("k_tdens_rows", k_tdens_rows<float>, dim3((unsigned)nblk), dim3(nt), shm, st, a);
+  }
+  HYP_LAUNCH("k_tdens_rows_final", k_tdens_rows_final, dim3((kBins * kStageW + kBins + 255) / 256), dim3(256), 0,
+             st, ts.rpart, a.n_eb, a.n_id, a.nchunk, Ta, Tb, Tab);
+  return HYP_OK;
+}
+
 hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_ops, const void* psi,
-                        const void* sig, double* grad, hipStream_t st) {
+                        const void* sig, double* grad, hipStream_t st, bool bins) {
   int dev = 0;
   HYP_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) return fail(HYP_ERR_HIP, "device index out of range");
@@ -399,6 +683,13 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
     HYP_HIP(hipMalloc(&ts.red, sizeof(double) * ((size_t)kBins * kRowSlices * kStageW + (size_t)kRowBlocks * kBins)));
     ts.binom = true;
   }
+  double* Ta = ts.T;
+  double* Tb = ts.T + kBins;
+  double* Tab = ts.T + 2 * kBins;
+  if (!bins) {
+    hyp_status r = tdens_rows(S, dt, ts, psi, sig, Ta, Tb, Tab, st);
+    if (r != HYP_OK) return r;
+  } else {
   const size_t need = tdens_bytes(S);
   if (need > ts.cap) {
     HYP_HIP(hipDeviceSynchronize());
@@ -434,15 +725,13 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
       HYP_HIP(hipFuncSetAttribute((const void*)k_tdens<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     HYP_LAUNCH("k_tdens", k_tdens<float>, dim3((unsigned)nblk), dim3(nt), shm, st, a);
   }
-  double* Ta = ts.T;
-  double* Tb = ts.T + kBins;
-  double* Tab = ts.T + 2 * kBins;
   double* red_ab = ts.red;
   double* red_a = ts.red + (size_t)kBins * kRowSlices * kStageW;
   HYP_LAUNCH("k_tdens_reduce_ab", k_tdens_reduce_ab, dim3(kBins, kRowSlices), dim3(256), 0, st, a, red_ab);
   HYP_LAUNCH("k_tdens_reduce_a", k_tdens_reduce_a, dim3(kRowBlocks), dim3(256), 0, st, a, red_a);
   HYP_LAUNCH("k_tdens_final", k_tdens_final, dim3((kBins * kStageW + kBins + 255) / 256), dim3(256), 0, st,
              red_ab, red_a, Ta, Tb, Tab);
+  }
   // same-spin doubles: Gram matrices on the matrix cores, then the gather
   const int64_t da = S->da, db = S->db;
   const size_t gneed = (size_t)(da * da + db * db) + (dt == HYP_F32 ? 2 * (size_t)S->dim : 0);

@@ -256,6 +256,20 @@ def hf_bits(n_orb: int, n_alpha: int, n_beta: int) -> int:
     return ((1 << n_alpha) - 1) | (((1 << n_beta) - 1) << n_orb)
 
 
+def sparse_state(dim: int, d_alpha: int, n_random: int = 64, seed: int = 21):
+    """Sparse sector vector as (sorted indices, values), norm 1: the 16
+    lowest alpha ranks with the lowest beta string, the 16 lowest beta ranks
+    with the lowest alpha string (Hartree-Fock and the strings next to it in
+    colex order), and n_random uniform indices; N(0,1) values."""
+    rng = np.random.default_rng(seed)
+    near = [i for i in range(min(16, d_alpha))] + [j * d_alpha for j in range(1, min(16, dim // d_alpha))]
+    idx = np.unique(np.concatenate([np.array(near, dtype=np.int64),
+                                    rng.choice(dim, size=min(n_random, dim), replace=False).astype(np.int64)]))
+    val = rng.standard_normal(idx.size)
+    val /= math.sqrt(float(np.dot(val, val)))
+    return idx, val
+
+
 def random_state(dim: int, seed: int = 7, dtype=np.float64) -> np.ndarray:
     """Dense N(0,1) sector vector normalised to 1 (FP64 norm)."""
     rng = np.random.default_rng(seed)

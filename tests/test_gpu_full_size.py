@@ -1,0 +1,139 @@
+"""Parity at the 32-qubit workload's full size (sector (8, 8), dim 165,636,900,
+94,849 Pauli terms, pool 39,960), in the launch configuration the benchmark
+times.
+
+* A sparse input state makes the oracle's sigma cheap (every term pushed
+  from every nonzero), so sigma, the energy and the rotations are compared
+  element by element over all 165,636,900 entries.  The kernels' control
+  flow does not depend on the values, so this exercises every tile and the
+  ragged tail of every row.
+* The benchmark's dense random state: sigma on sampled rows (the oracle's
+  term-by-term sum per row), including the first and last rows and both
+  edges of the column chunks.
+* The full pool-gradient sweep in all three strategies against each other
+  and, on a sample of generators, against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+W = synth.WORKLOADS["h16_32q"]
+
+
+@pytest.fixture(scope="module")
+def hyp():
+    import paper_2604_01176_amd as hyp
+    return hyp
+
+
+@pytest.fixture(scope="module")
+def prob(hyp):
+    x, z, c, _, _ = synth.hamiltonian(W)
+    S = hyp.Sector(W.n_orb, W.n_alpha, W.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    assert H.structured
+    idx, val = synth.sparse_state(S.dim, S.da)
+    print(f"[full-size] dim {S.dim}, sparse input with {idx.size} nonzeros", flush=True)
+    sig_ref = oracle.apply_h_sparse(W.n_orb, W.n_alpha, W.n_beta, x, z, c, idx, val)
+    return dict(S=S, H=H, x=x, z=z, c=c, idx=idx, val=val, sig_ref=sig_ref)
+
+
+def _sparse_dev(S, idx, val, dtype=torch.float64):
+    d = torch.zeros(S.dim, dtype=dtype, device="cuda")
+    d[torch.from_numpy(idx).cuda()] = torch.from_numpy(val).to(dtype).cuda()
+    return d
+
+
+def _full(S, idx, val):
+    v = np.zeros(S.dim)
+    v[idx] = val
+    return v
+
+
+def test_hpsi_32q_sparse_input_every_entry(hyp, prob):
+    S, H = prob["S"], prob["H"]
+    psi = _sparse_dev(S, prob["idx"], prob["val"])
+    sig = H.apply(psi).cpu().numpy()
+    ref = prob["sig_ref"]
+    nz = np.count_nonzero(ref)
+    print(f"[full-size] oracle sigma has {nz} nonzeros", flush=True)
+    assert nz > 100000
+    assert np.linalg.norm(sig - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.abs(sig - ref).max() <= 1e-12 * np.abs(ref).max()
+    # rows outside the oracle's support are exactly zero on the GPU too
+    assert np.count_nonzero(sig[ref == 0.0]) == 0
+    # energy <psi|sigma> / <psi|psi>
+    e = hyp.hyp_expectation(S, psi, H.apply(psi)).item()
+    e_ref = float(np.dot(prob["val"], ref[prob["idx"]]))
+    assert abs(e - e_ref) <= 1e-9
+
+
+def test_hpsi_32q_sparse_input_fp32(hyp, prob):
+    S, H = prob["S"], prob["H"]
+    psi = _sparse_dev(S, prob["idx"], prob["val"], torch.float32)
+    sig = H.apply(psi).cpu().numpy().astype(np.float64)
+    ref = prob["sig_ref"]
+    assert np.linalg.norm(sig - ref) <= 2e-6 * np.linalg.norm(ref)
+
+
+def test_hpsi_32q_benchmark_state_sampled_rows(hyp, prob):
+    S, H = prob["S"], prob["H"]
+    psi_h = synth.random_state(S.dim, 7)
+    sig = H.apply(torch.from_numpy(psi_h).cuda())
+    da = S.da
+    rng = np.random.default_rng(3)
+    rows = [0, 1, S.dim - 1, S.dim - 2, 767, 768, 1535, 1536, da - 1, da, 6 * da + 12799, 12869 * da + 1]
+    rows += rng.choice(S.dim, 36, replace=False).tolist()
+    rows = np.unique(np.array(rows, dtype=np.int64))
+    got = sig[torch.from_numpy(rows).cuda()].cpu().numpy()
+    ref = oracle.apply_h(W.n_orb, W.n_alpha, W.n_beta, prob["x"], prob["z"], prob["c"], psi_h, out_idx=rows)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_sweep_32q_all_strategies_and_oracle_sample(hyp, prob):
+    S, H = prob["S"], prob["H"]
+    cre, ann, cls = synth.canonical_pool(W.n_orb)
+    ops = hyp.exc_tensor(cre, ann)
+    psi = _sparse_dev(S, prob["idx"], prob["val"])
+    sig = H.apply(psi)
+    g = {}
+    try:
+        for mode in ("auto", "tdens", "tdens_bins", "pairs"):
+            hyp.set_sweep_mode(mode)
+            g[mode] = hyp.hyp_pool_gradients(S, ops, psi, sig).cpu().numpy()
+            print(f"[full-size] sweep mode {mode} done", flush=True)
+    finally:
+        hyp.set_sweep_mode("auto")
+    scale = max(1.0, np.abs(g["pairs"]).max())
+    for mode in ("auto", "tdens", "tdens_bins"):
+        assert np.abs(g[mode] - g["pairs"]).max() <= 1e-12 * scale, mode
+    # oracle on a sample: the largest gradients and random ones of every class
+    rng = np.random.default_rng(4)
+    pick = list(np.argsort(-np.abs(g["auto"]), kind="stable")[:6])
+    for k in range(5):
+        members = np.nonzero(cls == k)[0]
+        pick += rng.choice(members, 2, replace=False).tolist()
+    pick = np.array(sorted(set(int(p) for p in pick)))
+    psi_full = _full(S, prob["idx"], prob["val"])
+    ref = oracle.pool_gradients(W.n_orb, W.n_alpha, W.n_beta, cre[pick], ann[pick], psi_full, prob["sig_ref"])
+    assert np.abs(ref).max() > 1e-3
+    assert np.abs(g["auto"][pick] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("cls_pick", [0, 4])
+def test_rotation_32q_every_entry(hyp, prob, cls_pick):
+    S = prob["S"]
+    cre, ann, cls = synth.canonical_pool(W.n_orb)
+    k = int(np.nonzero(cls == cls_pick)[0][0])
+    psi = _sparse_dev(S, prob["idx"], prob["val"])
+    hyp.hyp_apply_excitation(S, int(cre[k]), int(ann[k]), 0.37, psi)
+    got = psi.cpu().numpy()
+    ref = oracle.rotate(W.n_orb, W.n_alpha, W.n_beta, int(cre[k]), int(ann[k]), 0.37, _full(S, prob["idx"], prob["val"]))
+    assert np.abs(got - ref).max() <= 1e-13
+    assert np.count_nonzero(ref) > np.size(prob["idx"])  # the rotation moved weight

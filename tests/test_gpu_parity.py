@@ -217,17 +217,21 @@ def test_pool_gradients_transition_values(hyp, M, na, nb):
     ref = oracle.pool_gradients(M, na, nb, cre, ann, psi, sig)
     ops = hyp.exc_tensor(cre, ann)
     try:
-        hyp.set_sweep_mode("tdens")
-        g = hyp.hyp_pool_gradients(S, ops, _dev(psi), _dev(sig)).cpu().numpy()
-        g32 = hyp.hyp_pool_gradients(S, ops, _dev(psi, torch.float32), _dev(sig, torch.float32)).cpu().numpy()
+        res = {}
+        for mode in ("tdens", "tdens_bins"):
+            hyp.set_sweep_mode(mode)
+            res[mode] = (hyp.hyp_pool_gradients(S, ops, _dev(psi), _dev(sig)).cpu().numpy(),
+                         hyp.hyp_pool_gradients(S, ops, _dev(psi, torch.float32),
+                                                _dev(sig, torch.float32)).cpu().numpy())
         hyp.set_sweep_mode("pairs")
         gp = hyp.hyp_pool_gradients(S, ops, _dev(psi), _dev(sig)).cpu().numpy()
     finally:
         hyp.set_sweep_mode("auto")
     scale = max(1.0, np.abs(ref).max())
-    assert np.abs(g - ref).max() <= 1e-12 * scale
     assert np.abs(gp - ref).max() <= 1e-12 * scale
-    assert np.abs(g32 - ref).max() <= 1e-5 * scale
+    for mode, (g, g32) in res.items():
+        assert np.abs(g - ref).max() <= 1e-12 * scale, mode
+        assert np.abs(g32 - ref).max() <= 1e-5 * scale, mode
 
 
 def test_pool_gradients_24q_full_sweep_modes(hyp):
@@ -243,6 +247,8 @@ def test_pool_gradients_24q_full_sweep_modes(hyp):
     d_sig = H.apply(d_psi)
     ops = hyp.exc_tensor(cre, ann)
     try:
+        hyp.set_sweep_mode("tdens_bins")
+        g_b = hyp.hyp_pool_gradients(S, ops, d_psi, d_sig).cpu().numpy()
         hyp.set_sweep_mode("tdens")
         g_t = hyp.hyp_pool_gradients(S, ops, d_psi, d_sig).cpu().numpy()
         hyp.set_sweep_mode("pairs")
@@ -250,6 +256,7 @@ def test_pool_gradients_24q_full_sweep_modes(hyp):
     finally:
         hyp.set_sweep_mode("auto")
     assert np.abs(g_t - g_p).max() <= 1e-12 * max(1.0, np.abs(g_p).max())
+    assert np.abs(g_b - g_p).max() <= 1e-12 * max(1.0, np.abs(g_p).max())
     k = np.random.default_rng(5).choice(len(cre), 12, replace=False)
     ref = oracle.pool_gradients(w.n_orb, w.n_alpha, w.n_beta, cre[k], ann[k], psi, d_sig.cpu().numpy())
     assert np.abs(g_t[k] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())

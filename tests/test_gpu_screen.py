@@ -118,7 +118,7 @@ def _train_on(hyp, scr, workloads, n_iter, seed=0):
         ts.append(t)
     X = np.concatenate(Xs)
     t = np.concatenate(ts)
-    net = scr.MLP(synth.mlp_init(seed), 1024)
+    net = scr.MLP(synth.mlp_init(seed), 1 << 16)
     losses = scr.train(net, X, t, epochs=4, batch=1024, lr=1e-3)
     return net, losses
 

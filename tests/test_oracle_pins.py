@@ -196,6 +196,28 @@ def test_sampled_rows_match_full():
     assert np.array_equal(part, full[idx])
 
 
+@pytest.mark.parametrize("M,na,nb", [(4, 2, 2), (5, 2, 3)])
+def test_apply_h_sparse_input_equals_dense_fermionic(M, na, nb):
+    """The input-side (push) sum for a sparse psi against the dense
+    second-quantised sector matrix, and empty / single-state inputs."""
+    h, g = synth.integrals(M, 12)
+    x, z, c = synth.jw_pauli_list(h, g)
+    basis = brute.sector_basis(M, na, nb)
+    Hs = brute.sector_matrix(brute.fermion_hamiltonian(h, g), basis).real
+    rng = np.random.default_rng(3)
+    idx = rng.choice(basis.size, 4, replace=False)
+    val = rng.standard_normal(4)
+    psi = np.zeros(basis.size)
+    psi[idx] = val
+    s = oracle.apply_h_sparse(M, na, nb, x, z, c, idx, val)
+    assert np.abs(s - Hs @ psi).max() < 1e-12 * np.abs(Hs @ psi).max()
+    assert np.array_equal(oracle.apply_h_sparse(M, na, nb, x, z, c, idx[:0], val[:0]), np.zeros(basis.size))
+    one = oracle.apply_h_sparse(M, na, nb, x, z, c, idx[:1], np.ones(1))
+    assert np.abs(one - Hs[:, idx[0]]).max() < 1e-12
+    with pytest.raises(ValueError):
+        oracle.apply_h_sparse(M, na, nb, np.array([1]), np.array([1]), np.array([1.0]), idx, val)
+
+
 # ---------------------------------------------------------------- energy
 
 @pytest.mark.parametrize("name", ["h4_8q", "h8_16q", "h12_24q", "h14_28q", "h16_32q"])
