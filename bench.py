@@ -166,6 +166,11 @@ def main():
             hyp.hyp_pool_gradients(S, ops, psi, sig, grad)
         hyp.hyp_apply_excitation(S, int(cre[k_rot]), int(ann[k_rot]), 1e-3, psi)
 
+    # the library's tile autotuner picks the mixed pass's workgroup width on
+    # this Hamiltonian (it overwrites sig, which step() recomputes)
+    hpsi_threads, tune_ms = H.tune(psi, reps=1)
+    print(f"[bench] H psi autotune: {hpsi_threads} threads per workgroup ({tune_ms:.1f} ms)",
+          file=sys.stderr, flush=True)
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -241,7 +246,7 @@ def main():
         "config": {"workload": f"{w.name}: {2 * M} qubits, sector ({na},{nb}), dim {m['dim']}, "
                                f"{m['T']} Pauli terms, pool {m['pool']}",
                    "parallelism": "1 GPU"},
-        "hpsi_ms": round(hpsi_ms, 3),
+        "hpsi_ms": round(hpsi_ms, 3), "hpsi_threads": int(hpsi_threads),
         "hpsi_frac_hbm_gather_model": round(value / HBM_PEAK_GBS, 4),
         "pool_grad_evals_per_s": round(m["pool"] / (sweep_ms * 1e-3), 1) if sweep_ms > 0 else None,
         "sweep_ms": round(sweep_ms, 3),
@@ -253,7 +258,8 @@ def main():
 
 def adapt_compare(w, n_iter):
     """The screen is trained on the GPU with the library's own kernels on
-    exact sweeps of the 8-, 16- and 24-qubit workloads; then on the target
+    exact sweeps of the 8-, 16- and 24-qubit workloads and the eight batch
+    instances (floored residual targets, 16 epochs); then on the target
     workload: one plain FP64 ADAPT iteration per step (full sweep + BFGS)
     against screened FP32 iterations (top-512 + 256 audit, full sweep on the
     judge iterations, BFGS)."""
@@ -265,21 +271,22 @@ def adapt_compare(w, n_iter):
 
     t0 = time.time()
     Xs, ts = [], []
-    for name, iters in (("h4_8q", 6), ("h8_16q", 6), ("h12_24q", 4)):
-        v = synth.WORKLOADS[name]
+    train_set = [(synth.WORKLOADS[n], it) for n, it in (("h4_8q", 8), ("h8_16q", 8), ("h12_24q", 6))]
+    train_set += [(v, 8) for v in synth.INSTANCES]
+    for k, (v, iters) in enumerate(train_set):
         x, z, c, h, g = synth.hamiltonian(v)
         cre, ann, cls = synth.canonical_pool(v.n_orb)
         S = hyp.Sector(v.n_orb, v.n_alpha, v.n_beta)
         H = hyp.Hamiltonian(S, x, z, c)
         A = hyp.Adapt(H, cre, ann, max_iter=iters + 1)
         stat, qidx = scr.static_features(v.n_orb, cre, ann, cls, h, g)
-        X, t = scr.collect_rows(A, scr.FeatureState(S, stat, qidx), iters)
+        X, t = scr.collect_rows(A, scr.FeatureState(S, stat, qidx), iters, seed=k)
         Xs.append(X)
         ts.append(t)
     X = np.concatenate(Xs)
     t = np.concatenate(ts)
     net = scr.MLP(synth.mlp_init(0), 1 << 16)
-    losses = scr.train(net, X, t, epochs=4, batch=1024, lr=1e-3)
+    losses = scr.train(net, X, t, epochs=16, batch=1024, lr=1e-3)
     print(json.dumps({"screen_training_rows": int(X.shape[0]), "losses": [round(l, 4) for l in losses],
                       "train_s": round(time.time() - t0, 1)}), flush=True)
 

@@ -100,7 +100,7 @@ hyp_status hyp_ham_destroy(hyp_ham h);
 int hyp_ham_is_structured(hyp_ham h);
 
 /* Autotuner of the H psi tile shape (the mixed pass's workgroup width, one
- * thread per alpha column): times the candidates {128,...,768} on this
+ * thread per alpha column): times the candidates {128,...,1024} on this
  * Hamiltonian with reps applications each (HIP events on `stream`), keeps
  * the fastest for later hyp_apply_h calls on h and returns it.  Overwrites
  * sigma_dev.  A generic (non-structured) Hamiltonian returns 0 threads. */
@@ -267,6 +267,12 @@ hyp_status hyp_mlp_forward(hyp_mlp m, const uint16_t* X_dev, int64_t n, float* y
  * y_dev receives the forward scores. */
 hyp_status hyp_mlp_train_step(hyp_mlp m, const uint16_t* X_dev, const float* t_dev, int64_t B,
                               float lr, float* y_dev, void* stream);
+/* Full training state (host, 3 * 74,497 + 1 floats): parameters, Adam first
+ * and second moments (parameter layout each), then the Adam step count.
+ * set_state also refreshes the BF16 weight copies; a network restored this
+ * way continues training exactly as the one it was taken from. */
+hyp_status hyp_mlp_get_state(hyp_mlp m, float* host_out);
+hyp_status hyp_mlp_set_state(hyp_mlp m, const float* host_in);
 /* Parameter gradients of the last train step (host, parameter layout). */
 hyp_status hyp_mlp_grads(hyp_mlp m, float* host_out);
 /* Static feature rows (host): stat[n][32] FP32 = class one-hot (0..4),
@@ -291,11 +297,21 @@ hyp_status hyp_features(const float* stat_dev, const int32_t* qidx_dev, const do
  * and age[k] = 0; every other age grows by one. */
 hyp_status hyp_screen_update(const double* g_dev, int64_t n, double* gprev_dev, int32_t* age_dev,
                              void* stream);
-/* Training rows: Xo[i] = X[idx[i]] (32 BF16), t[i] = log10(|g[idx[i]]| + 1e-12). */
+/* Base score of every operator, taken with the feature rows (before the
+ * sweep that updates g_prev): base[k] = max(log10(|g_prev[k]| + 1e-12), t_floor)
+ * (FP32).  The network predicts the change of the floored log gradient since
+ * its last exact value; an operator's score is base + network output. */
+hyp_status hyp_screen_base(const double* gprev_dev, int64_t n, float t_floor, float* base_dev, void* stream);
+/* Training rows: Xo[i] = X[idx[i]] (32 BF16),
+ * t[i] = max(log10(|g[idx[i]]| + 1e-12), t_floor) - base[idx[i]] (FP32;
+ * base_dev NULL: no base; t_floor = -12 keeps the plain log target). */
 hyp_status hyp_screen_batch(const uint16_t* X_dev, const double* g_dev, const int32_t* idx_dev,
-                            int64_t m, uint16_t* Xo_dev, float* t_dev, void* stream);
-/* Operator indices sorted by descending score (stable: ties keep index order). */
-hyp_status hyp_rank_scores(hyp_mlp m, const float* y_dev, int64_t n, int32_t* order_dev, void* stream);
+                            int64_t m, float t_floor, const float* base_dev, uint16_t* Xo_dev, float* t_dev,
+                            void* stream);
+/* Operator indices sorted by descending score y + base (base_dev NULL: y);
+ * stable: ties keep index order. */
+hyp_status hyp_rank_scores(hyp_mlp m, const float* y_dev, const float* base_dev, int64_t n, int32_t* order_dev,
+                           void* stream);
 
 /* Kernel timing (tracing).  While enabled, every kernel the library launches
  * is bracketed by HIP events on its stream; hyp_profile_count() waits for

@@ -82,12 +82,15 @@ SIGNATURES = {
     "hyp_mlp_forward": (_ci, [_vp, _vp, _i64, _vp, _vp]),
     "hyp_mlp_train_step": (_ci, [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp]),
     "hyp_mlp_grads": (_ci, [_vp, _vp]),
+    "hyp_mlp_get_state": (_ci, [_vp, _vp]),
+    "hyp_mlp_set_state": (_ci, [_vp, _vp]),
     "hyp_screen_static": (_ci, [_ci, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "hyp_occupations": (_ci, [_vp, _ci, _vp, _vp, _vp, _vp]),
     "hyp_features": (_ci, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp]),
     "hyp_screen_update": (_ci, [_vp, _i64, _vp, _vp, _vp]),
-    "hyp_screen_batch": (_ci, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
-    "hyp_rank_scores": (_ci, [_vp, _vp, _i64, _vp, _vp]),
+    "hyp_screen_base": (_ci, [_vp, _i64, ctypes.c_float, _vp, _vp]),
+    "hyp_screen_batch": (_ci, [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp, _vp, _vp]),
+    "hyp_rank_scores": (_ci, [_vp, _vp, _vp, _i64, _vp, _vp]),
     "hyp_adapt_create": (_ci, [_vp, _ci, _vp, _i64, ctypes.POINTER(AdaptOpts), ctypes.POINTER(_vp)]),
     "hyp_adapt_destroy": (_ci, [_vp]),
     "hyp_adapt_iterate": (_ci, [_vp, _vp, _i64, ctypes.POINTER(AdaptRecord)]),

@@ -298,13 +298,14 @@ struct MixedArgs {
 // the alpha-beta doubles).  Coefficient tables with both signs pre-applied sit
 // in LDS, so one term is two LDS reads and one FMA.
 template <typename T>
-__global__ void __launch_bounds__(768) k_mixed(MixedArgs a) {
+__global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* s_row = (T*)smem;  // [da]
   __shared__ double s_fab[kMaxPairs * 4];   // [(pid*2+O)*2 + sign]
   __shared__ double s_srow[kMaxPairs * 4];  // [(pid*2+O)*2 + sign]
   __shared__ double s_dmix[kMaxOrb];
   __shared__ double s_bdress[kMaxOrb];
+  __shared__ int2 s_stage[64];  // per beta single: (source rank, pair | O << 16 | signs << 17)
 
   const int M = a.M;
   const uint32_t amask = (1u << M) - 1u;
@@ -342,8 +343,12 @@ __global__ void __launch_bounds__(768) k_mixed(MixedArgs a) {
     s_srow[2 * i] = v;
     s_srow[2 * i + 1] = -v;
   }
-  // packed excitation entries of this thread's alpha string
+  // packed excitation entries of this thread's alpha string; slots past the
+  // string's excitations point at the zero slot s_row[da] (coefficient 0), so
+  // the product loops run all 64 slots without predication
   uint32_t ex[64];
+#pragma unroll
+  for (int x = 0; x < 64; ++x) ex[x] = (uint32_t)a.da * (uint32_t)sizeof(T);
   int ns = 0;
   {
     const RankTables* R = a.arank;
@@ -362,7 +367,11 @@ __global__ void __launch_bounds__(768) k_mixed(MixedArgs a) {
         const uint32_t sab = __popc(H.abJa[pid] & s) & 1u;
         const uint32_t ssg = __popc(H.sJ[pid] & s) & 1u;
         const uint32_t O = (i == q) ? 1u : 0u;
-        const uint32_t ent = r2 | (sab << 14) | (((uint32_t)pid * 2u + O) << 15) | (ssg << 23);
+        // LDS byte offsets: the source amplitude (bits 0..16) and the
+        // coefficient s_fab[(pair*2 + O)*2 + sab] (bits 17..28); bit 29 is
+        // the sign of the singles' dressing
+        const uint32_t ent = (r2 * (uint32_t)sizeof(T)) | (((((uint32_t)pid * 2u + O) * 2u + sab) * 8u) << 17) |
+                             (ssg << 29);
 #pragma unroll
         for (int x = 0; x < 64; ++x)
           if (x == ns) ex[x] = ent;
@@ -371,10 +380,8 @@ __global__ void __launch_bounds__(768) k_mixed(MixedArgs a) {
     }
   }
   const T* psi = (const T*)a.psi;
-  {
-    const T* prow = psi + (int64_t)brow * a.da;
-    stage_row(s_row, prow, a.da, tid, nt);
-  }
+  if (tid == 0) s_row[a.da] = T(0);
+  stage_row_lds(s_row, psi + (int64_t)brow * a.da, a.da * (int)sizeof(T), tid, nt);
   __syncthreads();
 
   double acc = 0.0;
@@ -390,42 +397,57 @@ __global__ void __launch_bounds__(768) k_mixed(MixedArgs a) {
     acc += Acc<T>::prod(v, s_row[live ? col : 0]);
 #pragma unroll
     for (int x = 0; x < 64; ++x) {
-      if (x < ns) {
-        const uint32_t e = ex[x];
-        const int fi = (int)(((e >> 15) & 0xffu) * 2u + (e >> 23));
-        acc += Acc<T>::prod(s_srow[fi], s_row[e & 0x3fffu]);
-      }
+      const uint32_t e = ex[x];
+      const int fi = (int)(((e >> 20) & 0x1feu) | ((e >> 29) & 1u));
+      acc += Acc<T>::prod(s_srow[fi], *(const T*)((const char*)s_row + (e & 0x1ffffu)));
     }
+    asm volatile("" : "+v"(acc));  // finish the products here, not after the table loop below
   }
 
-  // (2) beta-single source rows
+  // (2) beta-single source rows.  Per stage jb: the source row's rank, the
+  // pair and orientation of the beta excitation and its two signs are
+  // tabulated once per workgroup, so no dependent lookup precedes a stage's
+  // row loads.
   const int nbemp = M - a.nb;
   const int nbs = a.nb * nbemp;
-  for (int jb = 0; jb < nbs; ++jb) {
-    __syncthreads();
-    int io = jb / nbemp, ie = jb % nbemp;
+  for (int jb = tid; jb < nbs; jb += nt) {
+    const int io = jb / nbemp, ie = jb % nbemp;
     uint32_t occ = bs, emp = ~bs & amask;
     for (int j = 0; j < io; ++j) occ &= occ - 1;
     for (int j = 0; j < ie; ++j) emp &= emp - 1;
     const int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
     const int p = min(i, e), q = max(i, e);
     const int pb = pair_id(p, q);
-    const int Ob = (i == q) ? 1 : 0;
     const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
-    const int srank = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
-    const int sbase = (kMaxPairs + pb) * 2 + Ob;
     const uint32_t jsb = H.sJ[kMaxPairs + pb] >> M;
-    const double sgn_s = (__popc(jsb & bs) & 1) ? -1.0 : 1.0;
-    for (int k = tid; k < M; k += nt) s_bdress[k] = sgn_s * H.sB[(size_t)sbase * 32 + k];
-    const double sgn_ab = (__popc((H.abJb[pb] >> M) & bs) & 1) ? -1.0 : 1.0;
+    const uint32_t sgn_s = __popc(jsb & bs) & 1u;
+    const uint32_t sgn_ab = __popc((H.abJb[pb] >> M) & bs) & 1u;
+    s_stage[jb] = make_int2(a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u],
+                            pb | ((i == q) ? 1 << 16 : 0) | (int)(sgn_s << 17) | (int)(sgn_ab << 18));
+  }
+  __syncthreads();
+  for (int jb = 0; jb < nbs; ++jb) {
+    // the entries are opaque to the optimiser here: otherwise it hoists the
+    // 128 addresses derived from them out of the loop and spills
+#pragma unroll
+    for (int x = 0; x < 64; ++x) asm volatile("" : "+v"(ex[x]));
+    __syncthreads();
+    // the stage's coefficients and dressing are loaded in the same phase as
+    // the row, so their latencies overlap
+    const int info = s_stage[jb].y;
+    const int pb = info & 0xffff, Ob = (info >> 16) & 1;
     for (int x = tid; x < kMaxPairs * 2; x += nt) {
       const int pa = x >> 1, Oa = x & 1;
-      const double f = sgn_ab * H.abF[((size_t)pa * kMaxPairs + pb) * 4 + Oa * 2 + Ob];
+      const double f0 = H.abF[((size_t)pa * kMaxPairs + pb) * 4 + Oa * 2 + Ob];
+      const double f = ((info >> 18) & 1) ? -f0 : f0;
       s_fab[2 * x] = f;
       s_fab[2 * x + 1] = -f;
     }
-    const T* src = psi + (int64_t)srank * a.da;
-    stage_row(s_row, src, a.da, tid, nt);
+    if (tid < M) {
+      const double d = H.sB[(size_t)((kMaxPairs + pb) * 2 + Ob) * 32 + tid];
+      s_bdress[tid] = ((info >> 17) & 1) ? -d : d;
+    }
+    stage_row_lds(s_row, psi + (int64_t)s_stage[jb].x * a.da, a.da * (int)sizeof(T), tid, nt);
     __syncthreads();
     double dr = 0.0;
     uint32_t o = s;
@@ -437,12 +459,12 @@ __global__ void __launch_bounds__(768) k_mixed(MixedArgs a) {
     double sum = Acc<T>::prod(dr, s_row[live ? col : 0]);
 #pragma unroll
     for (int x = 0; x < 64; ++x) {
-      if (x < ns) {
-        const uint32_t e2 = ex[x];
-        sum += Acc<T>::prod(s_fab[(e2 >> 14) & 0x1ffu], s_row[e2 & 0x3fffu]);
-      }
+      const uint32_t e2 = ex[x];
+      sum += Acc<T>::prod(*(const double*)((const char*)s_fab + ((e2 >> 17) & 0xfffu)),
+                          *(const T*)((const char*)s_row + (e2 & 0x1ffffu)));
     }
     acc += sum;
+    asm volatile("" : "+v"(acc));
   }
 
   // (3) combine with the two same-spin partials and store
@@ -550,9 +572,9 @@ static hyp_status build_same_spin(Ham* Hm, HamWork* W, hipStream_t st) {
   return HYP_OK;
 }
 
-// threads per mixed-kernel workgroup: one per alpha column, at most 768 (a
-// 12-wave workgroup leaves 168 registers per lane for the cached entries)
-static int pick_threads(int da) { return std::max(64, std::min(768, (da + 63) / 64 * 64)); }
+// threads per mixed-kernel workgroup: one per alpha column, at most 1024 (a
+// 16-wave workgroup leaves 128 registers per lane; the kernel needs about 105)
+static int pick_threads(int da) { return std::max(64, std::min(1024, (da + 63) / 64 * 64)); }
 
 template <typename T>
 static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sigma,
@@ -604,7 +626,8 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   ma.H = Hm->dev;
   const int nt = Hm->threads;
   ma.nchunk = (da + nt - 1) / nt;
-  const size_t shm = (size_t)da * sizeof(T);
+  // the row plus one zero slot (index da) that padded excitation entries read
+  const size_t shm = ((size_t)(da + 1) * sizeof(T) + 15) & ~(size_t)15;
   if (shm > 48 * 1024)
     HYP_HIP(hipFuncSetAttribute((const void*)k_mixed<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
   const int64_t nblk = (int64_t)8 * ((db + 7) / 8) * ma.nchunk;
@@ -993,7 +1016,7 @@ hyp_status hyp_tune_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* 
   }
   hipStream_t st = (hipStream_t)stream;
   const int da = (int)H->sec->da;
-  static const int cand[] = {128, 256, 384, 512, 640, 768};
+  static const int cand[] = {128, 256, 384, 512, 640, 768, 896, 1024};
   hipEvent_t e0, e1;
   HYP_HIP(hipEventCreate(&e0));
   HYP_HIP(hipEventCreate(&e1));

@@ -160,6 +160,37 @@ __device__ inline void stage_row(T* __restrict__ dst, const T* __restrict__ src,
   }
 }
 
+// Copy nbytes of a global row into LDS with direct global->LDS loads
+// (global_load_lds: lane l of a wave writes its piece at the wave's uniform
+// LDS base + 16 l), 16-byte pieces when the source is 16-byte aligned and
+// nbytes a multiple of 16, else 4-byte pieces.  No registers hold the data
+// and every piece of the row is in flight at once.  The caller's barrier
+// publishes the row (the compiler waits for these loads before it).
+// Requires nt % 64 == 0 and a 16-byte aligned dst.
+__device__ inline void stage_row_lds(void* dst, const void* src, int nbytes, int tid, int nt) {
+  const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
+  const char* s = (const char*)src;
+  char* d = (char*)dst;
+  if ((((uintptr_t)s & 15u) == 0) && (nbytes & 15) == 0) {
+    const int n = nbytes >> 4;
+    for (int base = w * 64; base < n; base += nw * 64) {
+      const int c = base + lane;
+      if (c < n)
+        __builtin_amdgcn_global_load_lds((const void*)(s + (size_t)c * 16),
+                                         (__attribute__((address_space(3))) void*)(d + (size_t)base * 16), 16, 0, 0);
+    }
+  } else {
+    const int n = nbytes >> 2;
+    for (int base = w * 64; base < n; base += nw * 64) {
+      const int c = base + lane;
+      if (c < n)
+        __builtin_amdgcn_global_load_lds((const void*)(s + (size_t)c * 4),
+                                         (__attribute__((address_space(3))) void*)(d + (size_t)base * 4), 4, 0, 0);
+    }
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 // shared entry points between translation units
 Sector* sector_of(hyp_sector h);
 Ham* ham_of(hyp_ham h);

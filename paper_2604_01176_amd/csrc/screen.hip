@@ -273,15 +273,28 @@ __global__ void k_screen_update(const double* g, int64_t n, double* gprev, int* 
   }
 }
 
-// training rows: Xo[i] = X[idx[i]], t[i] = log10(|g[idx[i]]| + 1e-12)
+// base[k] = max(log10(|g_prev[k]| + 1e-12), floor): the score the network corrects
+__global__ void k_screen_base(const double* gprev, int64_t n, float t_floor, float* base) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  base[k] = fmaxf((float)log10(fabs(gprev[k]) + 1e-12), t_floor);
+}
+
+// ranking key = network output + base
+__global__ void k_add_base(const float* y, const float* base, int64_t n, float* key) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) key[k] = y[k] + base[k];
+}
+
+// training rows: Xo[i] = X[idx[i]], t[i] = max(log10(|g[idx[i]]| + 1e-12), floor) - base[idx[i]]
 __global__ void k_screen_batch(const uint16_t* X, const double* g, const int* idx, int64_t m,
-                               uint16_t* Xo, float* t) {
+                               float t_floor, const float* base, uint16_t* Xo, float* t) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m * 32) return;
   const int64_t r = i / 32, c = i % 32;
   const int64_t k = idx[r];
   Xo[i] = X[k * 32 + c];
-  if (c == 0) t[r] = (float)log10(fabs(g[k]) + 1e-12);
+  if (c == 0) t[r] = fmaxf((float)log10(fabs(g[k]) + 1e-12), t_floor) - (base ? base[k] : 0.f);
 }
 
 static unsigned g1(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
@@ -306,7 +319,7 @@ struct hyp_mlp_s {
   void* sort_tmp;
   size_t sort_tmp_bytes;
   int64_t sort_cap;
-  float *keys_out;
+  float *keys_out, *keys_in;
   int *idx_in, *idx_out;
 };
 
@@ -372,6 +385,7 @@ hyp_status hyp_mlp_destroy(hyp_mlp m) {
   (void)hipFree(m->H1b);
   (void)hipFree(m->sort_tmp);
   (void)hipFree(m->keys_out);
+  (void)hipFree(m->keys_in);
   (void)hipFree(m->idx_in);
   (void)hipFree(m->idx_out);
   delete m;
@@ -463,6 +477,36 @@ hyp_status hyp_mlp_train_step(hyp_mlp m, const uint16_t* X_dev, const float* t_d
 }
 
 // Gradients of the last training step, host layout = parameter layout.
+// Full training state: parameters, Adam first and second moments (each in
+// the parameter layout) and the Adam step count (one float), 3 np + 1 floats.
+hyp_status hyp_mlp_get_state(hyp_mlp m, float* host_out) {
+  if (!m || !host_out) return fail(HYP_ERR_ARG, "hyp_mlp_get_state: NULL argument");
+  const int64_t np = kW1 + 256 + kW2 + 256 + kW3 + 1;
+  HYP_HIP(hipDeviceSynchronize());
+  HYP_HIP(hipMemcpy(host_out, m->W1, sizeof(float) * np, hipMemcpyDeviceToHost));
+  HYP_HIP(hipMemcpy(host_out + np, m->mW1, sizeof(float) * np, hipMemcpyDeviceToHost));
+  HYP_HIP(hipMemcpy(host_out + 2 * np, m->vW1, sizeof(float) * np, hipMemcpyDeviceToHost));
+  host_out[3 * np] = (float)m->step;
+  return HYP_OK;
+}
+
+hyp_status hyp_mlp_set_state(hyp_mlp m, const float* host_in) {
+  if (!m || !host_in) return fail(HYP_ERR_ARG, "hyp_mlp_set_state: NULL argument");
+  const int64_t np = kW1 + 256 + kW2 + 256 + kW3 + 1;
+  const float st = host_in[3 * np];
+  if (!(st >= 0.f) || st > 1e9f || st != (float)(int64_t)st)
+    return fail(HYP_ERR_ARG, "hyp_mlp_set_state: bad step count");
+  HYP_HIP(hipDeviceSynchronize());
+  HYP_HIP(hipMemcpy(m->W1, host_in, sizeof(float) * np, hipMemcpyHostToDevice));
+  HYP_HIP(hipMemcpy(m->mW1, host_in + np, sizeof(float) * np, hipMemcpyHostToDevice));
+  HYP_HIP(hipMemcpy(m->vW1, host_in + 2 * np, sizeof(float) * np, hipMemcpyHostToDevice));
+  m->step = (int64_t)st;
+  HYP_LAUNCH("k_cast_bf16", k_cast_bf16, dim3(g1(kW1)), dim3(256), 0, 0, m->W1, kW1, m->W1b);
+  HYP_LAUNCH("k_cast_bf16", k_cast_bf16, dim3(g1(kW2)), dim3(256), 0, 0, m->W2, kW2, m->W2b);
+  HYP_HIP(hipDeviceSynchronize());
+  return HYP_OK;
+}
+
 hyp_status hyp_mlp_grads(hyp_mlp m, float* host_out) {
   if (!m || !host_out) return fail(HYP_ERR_ARG, "hyp_mlp_grads: NULL argument");
   const int64_t np = kW1 + 256 + kW2 + 256 + kW3 + 1;
@@ -554,18 +598,28 @@ hyp_status hyp_screen_update(const double* g_dev, int64_t n, double* gprev_dev, 
   return HYP_OK;
 }
 
+hyp_status hyp_screen_base(const double* gprev_dev, int64_t n, float t_floor, float* base_dev, void* stream) {
+  if (!gprev_dev || !base_dev || n < 0) return fail(HYP_ERR_ARG, "hyp_screen_base: NULL argument");
+  if (n == 0) return HYP_OK;
+  HYP_LAUNCH("k_screen_base", k_screen_base, dim3(g1(n)), dim3(256), 0, (hipStream_t)stream, gprev_dev, n, t_floor,
+             base_dev);
+  HYP_HIP(hipGetLastError());
+  return HYP_OK;
+}
+
 hyp_status hyp_screen_batch(const uint16_t* X_dev, const double* g_dev, const int32_t* idx_dev, int64_t m,
-                            uint16_t* Xo_dev, float* t_dev, void* stream) {
+                            float t_floor, const float* base_dev, uint16_t* Xo_dev, float* t_dev, void* stream) {
   if (!X_dev || !g_dev || !idx_dev || !Xo_dev || !t_dev || m < 0) return fail(HYP_ERR_ARG, "hyp_screen_batch: NULL argument");
   if (m == 0) return HYP_OK;
   HYP_LAUNCH("k_screen_batch", k_screen_batch, dim3(g1(m * 32)), dim3(256), 0, (hipStream_t)stream, X_dev, g_dev,
-             idx_dev, m, Xo_dev, t_dev);
+             idx_dev, m, t_floor, base_dev, Xo_dev, t_dev);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
 }
 
 // order_dev[0..n) = operator indices sorted by descending score (ties: lower index first)
-hyp_status hyp_rank_scores(hyp_mlp m, const float* y_dev, int64_t n, int32_t* order_dev, void* stream) {
+hyp_status hyp_rank_scores(hyp_mlp m, const float* y_dev, const float* base_dev, int64_t n, int32_t* order_dev,
+                           void* stream) {
   if (!m || !y_dev || !order_dev || n < 1 || n > (1 << 30)) return fail(HYP_ERR_ARG, "hyp_rank_scores: bad argument");
   hipStream_t st = (hipStream_t)stream;
   if (n > m->sort_cap) {
@@ -580,12 +634,20 @@ hyp_status hyp_rank_scores(hyp_mlp m, const float* y_dev, int64_t n, int32_t* or
     HYP_HIP(hipMalloc(&m->sort_tmp, bytes));
     HYP_HIP(hipMalloc(&m->keys_out, sizeof(float) * n));
     HYP_HIP(hipMalloc(&m->idx_in, sizeof(int) * n));
+    (void)hipFree(m->keys_in);
+    m->keys_in = nullptr;
+    HYP_HIP(hipMalloc(&m->keys_in, sizeof(float) * n));
     m->sort_tmp_bytes = bytes;
     m->sort_cap = n;
   }
   HYP_LAUNCH("k_iota", k_iota, dim3(g1(n)), dim3(256), 0, st, m->idx_in, n);
+  const float* keys = y_dev;
+  if (base_dev) {
+    HYP_LAUNCH("k_add_base", k_add_base, dim3(g1(n)), dim3(256), 0, st, y_dev, base_dev, n, m->keys_in);
+    keys = m->keys_in;
+  }
   size_t bytes = m->sort_tmp_bytes;
-  HYP_HIP(hipcub::DeviceRadixSort::SortPairsDescending(m->sort_tmp, bytes, y_dev, m->keys_out, m->idx_in,
+  HYP_HIP(hipcub::DeviceRadixSort::SortPairsDescending(m->sort_tmp, bytes, keys, m->keys_out, m->idx_in,
                                                        (int*)order_dev, (int)n, 0, 32, st));
   return HYP_OK;
 }

@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(768) k_tdens(TArgs a) {
     }
     for (int x = tid; x < 12 * kBins; x += nt) s_wbin[x / kBins][x % kBins] = 0.0;
     const T* srow = psi + (int64_t)src * a.da;
-    stage_row(s_row, srow, a.da, tid, nt);
+    stage_row_lds(s_row, srow, a.da * (int)sizeof(T), tid, nt);
     __syncthreads();
     const double w = sb * sv;
     if (live) {
@@ -187,9 +187,63 @@ struct TRArgs {
   const RankTables* arank;
   const int2* rows;   // [n_eb][K]: (source row, target row | sign << 31)
   int K, Kid;         // row pairs per beta excitation; rows per identity slice
+  int nsx;            // alpha single excitations of every string, N_a (M - N_a)
   int n_eb, n_id, nchunk;
   double* part;       // [n_eb + n_id][nchunk][kStageW]
 };
+
+// Source ranks of a string's alpha single excitations (colex ranks < 2^14),
+// two per register, in the enumeration order (occupied i ascending, then empty
+// e ascending); unused slots hold pad; *ns receives their number.
+__device__ inline void alpha_sources(uint32_t s, uint32_t amask, const RankTables* R, uint32_t pad,
+                                     uint32_t (&ex)[32], int* ns) {
+#pragma unroll
+  for (int x = 0; x < 32; ++x) ex[x] = pad | (pad << 16);
+  int n = 0;
+  uint32_t occ = s;
+  while (occ) {
+    const int i = __ffs(occ) - 1;
+    occ &= occ - 1;
+    uint32_t emp = ~s & amask;
+    while (emp) {
+      const int e = __ffs(emp) - 1;
+      emp &= emp - 1;
+      const uint32_t t2 = s ^ (1u << i) ^ (1u << e);
+      const uint32_t r2 = (uint32_t)(R->lo[t2 & 255u] + R->hi[(t2 >> 8) & 255u]);
+#pragma unroll
+      for (int x = 0; x < 32; ++x)
+        if (2 * x == n) ex[x] = (ex[x] & 0xffff0000u) | r2;
+        else if (2 * x + 1 == n) ex[x] = (ex[x] & 0xffffu) | (r2 << 16);
+      ++n;
+    }
+  }
+  *ns = n;
+}
+
+// Bins (8 bits each, four per register) and signs (one bit each) of the same
+// excitations, in the same order.
+__device__ inline void alpha_bins(uint32_t s, uint32_t amask, uint32_t (&bins)[16], uint64_t* signs) {
+  int n = 0;
+  uint64_t sgm = 0;
+  uint32_t occ = s;
+  while (occ) {
+    const int i = __ffs(occ) - 1;
+    occ &= occ - 1;
+    uint32_t emp = ~s & amask;
+    while (emp) {
+      const int e = __ffs(emp) - 1;
+      emp &= emp - 1;
+      const int p = min(i, e), q = max(i, e);
+      if (__popc(betw(p, q) & s) & 1) sgm |= 1ull << n;
+      const uint32_t bin = (uint32_t)(q * (q - 1) / 2 + p) * 2u + (i == q ? 1u : 0u);
+#pragma unroll
+      for (int x = 0; x < 16; ++x)
+        if ((n >> 2) == x) bins[x] = (bins[x] & ~(0xffu << ((n & 3) * 8))) | (bin << ((n & 3) * 8));
+      ++n;
+    }
+  }
+  *signs = sgm;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
@@ -208,31 +262,10 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
   const int col = chunk * nt + tid;
   const bool live = col < a.da;
   const uint32_t s = live ? a.astr[col] : a.astr[0];
-  // packed entries: source rank (14 bits) | sign (bit 14) | bin (bits 15..22)
-  uint32_t ex[64];
+  // unused excitation slots read the zero slot s_row[da]
+  uint32_t ex[32];
   int ns = 0;
-  {
-    uint32_t occ = s;
-    while (occ) {
-      const int i = __ffs(occ) - 1;
-      occ &= occ - 1;
-      uint32_t emp = ~s & amask;
-      while (emp) {
-        const int e = __ffs(emp) - 1;
-        emp &= emp - 1;
-        const int p = min(i, e), q = max(i, e);
-        const uint32_t t2 = s ^ (1u << i) ^ (1u << e);
-        const uint32_t r2 = (uint32_t)(a.arank->lo[t2 & 255u] + a.arank->hi[(t2 >> 8) & 255u]);
-        const uint32_t sg = __popc(betw(p, q) & s) & 1u;
-        const uint32_t bin = (uint32_t)(q * (q - 1) / 2 + p) * 2u + (i == q ? 1u : 0u);
-        const uint32_t ent = r2 | (sg << 14) | (bin << 15);
-#pragma unroll
-        for (int x = 0; x < 64; ++x)
-          if (x == ns) ex[x] = ent;
-        ++ns;
-      }
-    }
-  }
+  alpha_sources(s, amask, a.arank, (uint32_t)a.da, ex, &ns);
   double acc[64];
 #pragma unroll
   for (int x = 0; x < 64; ++x) acc[x] = 0.0;
@@ -242,33 +275,39 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
   const int nrows = ident ? min(a.Kid, a.db - row0) : a.K;
   const T* psi = (const T*)a.psi;
   const T* sig = (const T*)a.sig;
+  if (tid == 0) s_row[a.da] = T(0);
   const int2* rl = a.rows + (int64_t)(ident ? 0 : slot) * a.K;
+  // the row pair of the next iteration is read one iteration ahead, so its
+  // latency is off the path to the staging loads
+  int2 cur = ident ? make_int2(row0, row0) : (nrows > 0 ? rl[0] : make_int2(0, 0));
   for (int k = 0; k < nrows; ++k) {
-    int src, tgt;
-    double sb = 1.0;
-    if (ident) {
-      src = tgt = row0 + k;
-    } else {
-      const int2 e = rl[k];
-      src = e.x;
-      tgt = e.y & 0x7fffffff;
-      if (e.y < 0) sb = -1.0;
-    }
+    const int2 nxt = (k + 1 < nrows) ? (ident ? make_int2(row0 + k + 1, row0 + k + 1) : rl[k + 1]) : cur;
+    const int src = cur.x, tgt = cur.y & 0x7fffffff;
+    const double sb = cur.y < 0 ? -1.0 : 1.0;
     __syncthreads();
-    stage_row(s_row, psi + (int64_t)src * a.da, a.da, tid, nt);
     const T sv = live ? sig[(int64_t)tgt * a.da + col] : T(0);
+    stage_row_lds(s_row, psi + (int64_t)src * a.da, a.da * (int)sizeof(T), tid, nt);
     __syncthreads();
+    cur = nxt;
     if (live) {
+      // nsx (every string's excitation count) is a kernel argument, so the
+      // guard below is a uniform scalar branch
       if (sizeof(T) == 4) {
 #pragma unroll
         for (int x = 0; x < 64; ++x)
-          if (x < ns) acc[x] += (double)((float)sv * (float)s_row[ex[x] & 0x3fffu]) * sb;
+          if (x < a.nsx) {
+            const uint32_t r = (ex[x >> 1] >> ((x & 1) * 16)) & 0xffffu;
+            acc[x] += (double)((float)sv * (float)s_row[r]) * sb;
+          }
         if (!ident) acc_id += (double)((float)sv * (float)s_row[col]) * sb;
       } else {
         const double w = sb * (double)sv;
 #pragma unroll
         for (int x = 0; x < 64; ++x)
-          if (x < ns) acc[x] += w * (double)s_row[ex[x] & 0x3fffu];
+          if (x < a.nsx) {
+            const uint32_t r = (ex[x >> 1] >> ((x & 1) * 16)) & 0xffffu;
+            acc[x] += w * (double)s_row[r];
+          }
         if (!ident) acc_id += w * (double)s_row[col];
       }
     }
@@ -281,11 +320,16 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
   for (int i = tid; i < nw * kBins; i += nt) s_bins[i] = 0.0;
   __syncthreads();
   if (live) {
+    uint32_t bins[16];
+#pragma unroll
+    for (int x = 0; x < 16; ++x) bins[x] = 0u;
+    uint64_t signs = 0;
+    alpha_bins(s, amask, bins, &signs);
 #pragma unroll
     for (int x = 0; x < 64; ++x) {
       if (x < ns) {
-        const uint32_t e = ex[x];
-        atomicAdd(&s_bins[(tid >> 6) * kBins + ((e >> 15) & 0xffu)], (e >> 14) & 1u ? -acc[x] : acc[x]);
+        const uint32_t bin = (bins[x >> 2] >> ((x & 3) * 8)) & 0xffu;
+        atomicAdd(&s_bins[(tid >> 6) * kBins + bin], ((signs >> x) & 1ull) ? -acc[x] : acc[x]);
       }
     }
   }
@@ -611,6 +655,7 @@ static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* 
   a.astr = S->d_astr;
   a.arank = S->d_arank;
   a.K = (int)binom64(S->M - 2, S->nb - 1);
+  a.nsx = S->na * (S->M - S->na);
   a.Kid = a.K > 0 ? a.K : a.db;
   a.n_eb = (int)(2 * binom64(S->M, 2));
   a.n_id = (a.db + a.Kid - 1) / a.Kid;
@@ -642,7 +687,9 @@ static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* 
     ts.rpart_cap = pneed;
   }
   a.part = ts.rpart;
-  const size_t shm = std::max((size_t)a.da * (dt == HYP_F64 ? 8 : 4), (size_t)(nt / 64) * kBins * sizeof(double));
+  // the row plus a zero slot, or the flush's per-wave bins
+  const size_t row_bytes = (((size_t)a.da + 1) * (dt == HYP_F64 ? 8 : 4) + 15) & ~(size_t)15;
+  const size_t shm = std::max(row_bytes, (size_t)(nt / 64) * kBins * sizeof(double));
   const int64_t nslot = a.n_eb + a.n_id;
   const int64_t nblk = (int64_t)8 * ((nslot + 7) / 8) * a.nchunk;
   if (dt == HYP_F64) {

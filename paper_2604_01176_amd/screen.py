@@ -7,8 +7,17 @@ the arithmetic runs in the library's kernels):
   on the host from a generator seeded by (seed, iteration)) -> exact
   gradients of the candidates -> fallback to the full sweep if the audit's
   largest |g| beats the top-K's -> selection + BFGS -> g_prev / age update ->
-  one online Adam step on the freshly computed (feature, log10|g|) rows.
+  one online Adam step on the freshly computed (feature, target) rows.
 Every judge_every-th iteration (iteration 0 included) runs the full sweep.
+
+Scores are residual: an operator's score is its base, the floored log of
+its last exact gradient max(log10(|g_prev| + 1e-12), T_FLOOR), plus the
+network's output, which is trained on the change of the floored log gradient
+since that value (an untrained network ranks like |g_prev|).  The floor keeps
+the regression on the large gradients that decide the selection rather than
+the many near-zero ones.  Offline training keeps, per exact sweep, the rows
+within BAND decades of the sweep's largest floored target plus REST_FRAC of
+the others.
 """
 from __future__ import annotations
 
@@ -21,6 +30,9 @@ from ._lib import check
 from . import _dev_ptr, _stream, _torch, _dtype_code, Adapt, Sector
 
 N_FEAT = 32
+T_FLOOR = -4.0
+BAND = 2.0
+REST_FRAC = 0.1
 N_PARAM = 256 * 32 + 256 + 256 * 256 + 256 + 256 + 1
 
 
@@ -40,6 +52,24 @@ class MLP:
         out = np.empty(N_PARAM, dtype=np.float32)
         check(_lib.load().hyp_mlp_params(self._h, out.ctypes.data))
         return out
+
+    def state(self) -> np.ndarray:
+        """Parameters, Adam moments and step count (3 N_PARAM + 1 floats)."""
+        out = np.empty(3 * N_PARAM + 1, dtype=np.float32)
+        check(_lib.load().hyp_mlp_get_state(self._h, out.ctypes.data))
+        return out
+
+    def load_state(self, st):
+        st = np.ascontiguousarray(st, dtype=np.float32)
+        if st.size != 3 * N_PARAM + 1:
+            raise ValueError(f"expected {3 * N_PARAM + 1} floats")
+        check(_lib.load().hyp_mlp_set_state(self._h, st.ctypes.data))
+
+    def clone(self, max_rows=None) -> "MLP":
+        """An independent network with the same parameters and optimiser state."""
+        c = MLP(self.params(), self.max_rows if max_rows is None else max_rows)
+        c.load_state(self.state())
+        return c
 
     def grads(self) -> np.ndarray:
         out = np.empty(N_PARAM, dtype=np.float32)
@@ -64,12 +94,14 @@ class MLP:
                                              B, ctypes.c_float(lr), _dev_ptr(y, B, "y"), _stream()))
         return y
 
-    def rank(self, y, order=None):
+    def rank(self, y, base=None, order=None):
+        """Operator indices by descending y + base (base None: y)."""
         torch = _torch()
         n = y.shape[0]
         if order is None:
             order = torch.empty(n, dtype=torch.int32, device=y.device)
-        check(_lib.load().hyp_rank_scores(self._h, _dev_ptr(y, n, "y"), n, _dev_ptr(order, n, "order"),
+        bp = _dev_ptr(base, n, "base") if base is not None else None
+        check(_lib.load().hyp_rank_scores(self._h, _dev_ptr(y, n, "y"), bp, n, _dev_ptr(order, n, "order"),
                                           _stream()))
         return order
 
@@ -116,15 +148,20 @@ class FeatureState:
         db = int(round(sector.dim / _comb(sector.n_orb, sector.n_alpha)))
         self.work = torch.zeros(db * 17, dtype=torch.float64, device="cuda")
         self.X = torch.empty((self.n, N_FEAT), dtype=torch.int16, device="cuda")
+        self.base = torch.empty(self.n, dtype=torch.float32, device="cuda")
         self.gdev = torch.empty(self.n, dtype=torch.float64, device="cuda")
 
     def features(self, psi):
+        """Feature rows and base scores of the current state (from g_prev as
+        it stands before this iteration's exact gradients)."""
         L = _lib.load()
         check(L.hyp_occupations(self.sector.handle, _dtype_code(psi), _dev_ptr(psi, self.sector.dim, "psi"),
                                 _dev_ptr(self.occ, None), _dev_ptr(self.work, None), _stream()))
         check(L.hyp_features(_dev_ptr(self.stat, None), _dev_ptr(self.qidx, None), _dev_ptr(self.occ, None),
                              _dev_ptr(self.gprev, None), _dev_ptr(self.age, None), self.n,
                              _dev_ptr(self.X, None), _stream()))
+        check(L.hyp_screen_base(_dev_ptr(self.gprev, None), self.n, ctypes.c_float(T_FLOOR),
+                                _dev_ptr(self.base, None), _stream()))
         return self.X
 
     def update(self, g_host):
@@ -134,16 +171,18 @@ class FeatureState:
         check(_lib.load().hyp_screen_update(_dev_ptr(self.gdev, None), self.n, _dev_ptr(self.gprev, None),
                                             _dev_ptr(self.age, None), _stream()))
 
-    def rows(self, idx):
-        """(X rows, targets log10|g| + 1e-12) of the operators idx, from gdev."""
+    def rows(self, idx, t_floor=T_FLOOR, residual=True):
+        """(X rows, targets max(log10(|g| + 1e-12), t_floor) - base) of the
+        operators idx, from gdev (no base subtracted if residual is False)."""
         torch = _torch()
         idx_d = torch.from_numpy(np.ascontiguousarray(idx, dtype=np.int32)).cuda()
         m = idx_d.shape[0]
         Xo = torch.empty((m, N_FEAT), dtype=torch.int16, device="cuda")
         t = torch.empty(m, dtype=torch.float32, device="cuda")
         check(_lib.load().hyp_screen_batch(_dev_ptr(self.X, None), _dev_ptr(self.gdev, None),
-                                           _dev_ptr(idx_d, None), m, _dev_ptr(Xo, None), _dev_ptr(t, None),
-                                           _stream()))
+                                           _dev_ptr(idx_d, None), m, ctypes.c_float(t_floor),
+                                           _dev_ptr(self.base, None) if residual else None,
+                                           _dev_ptr(Xo, None), _dev_ptr(t, None), _stream()))
         return Xo, t
 
 
@@ -174,19 +213,26 @@ class Screen:
         self.psi = None
         self.log = []
 
-    def iterate(self, it: int) -> dict:
+    def iterate(self, it: int, shadow: bool = False) -> dict:
+        """One screened iteration.  shadow=True also runs the full sweep on
+        the same state first (not used for the selection) and reports its
+        largest |g| and whether the screened pick lies in its tie set."""
         torch = _torch()
         n = self.n
         full = (it % self.judge_every == 0) or n <= self.K + self.audit
         self.psi = self.adapt.state(self.psi)
         X = self.fs.features(self.psi)
         info = {"iteration": it, "judge": full, "fallback": False}
+        g_shadow = None
+        if shadow and not full:
+            self.adapt.gradients(None)
+            g_shadow = np.abs(self.adapt.last_gradients())
         if full:
             rec = self.adapt.gradients(None)
             cand = np.arange(n)
         else:
             y = self.mlp.forward(X)
-            order = self.mlp.rank(y).cpu().numpy()
+            order = self.mlp.rank(y, self.fs.base).cpu().numpy()
             top = order[: self.K]
             rest = order[self.K:]
             aud = rest[audit_ranks(rest.size, self.audit, self.seed, it)]
@@ -211,15 +257,39 @@ class Screen:
         rec2 = self.adapt.select_optimize()
         info.update(rec2)
         info["n_exact"] = int(np.count_nonzero(~np.isnan(g)))
+        if g_shadow is not None:
+            gm = float(g_shadow.max())
+            kstar = int(np.argmax(g_shadow))
+            info["shadow_gmax"] = gm
+            info["shadow_agree"] = bool(rec2["selected"] >= 0 and g_shadow[rec2["selected"]] >= gm * (1 - 1e-6))
+            info["shadow_argmax"] = kstar
+            info["shadow_in_candidates"] = bool(np.isin(kstar, cand))
+            if not full and not info["fallback"]:
+                info["shadow_rank"] = int(np.nonzero(order == kstar)[0][0])
+        elif full:
+            info["shadow_agree"] = True
         self.log.append(info)
         torch.cuda.synchronize()
         return info
 
 
-def collect_rows(adapt: Adapt, fs: FeatureState, n_iter: int):
+def training_rows(t, rng, band=BAND, rest_frac=REST_FRAC):
+    """Rows of one exact sweep kept for training: every operator whose target
+    lies within `band` decades of the sweep's largest, plus a uniform sample
+    of `rest_frac` of the others (at least one).  Sorted indices."""
+    t = np.asarray(t)
+    top = np.nonzero(t >= t.max() - band)[0]
+    rest = np.setdiff1d(np.arange(t.size), top)
+    m = min(rest.size, max(1, int(rest.size * rest_frac)))
+    pick = rng.choice(rest, m, replace=False) if m > 0 else np.zeros(0, dtype=np.int64)
+    return np.sort(np.concatenate([top, pick]))
+
+
+def collect_rows(adapt: Adapt, fs: FeatureState, n_iter: int, seed: int = 0, select: bool = True):
     """Plain ADAPT with full sweeps; after each sweep the feature rows (built
-    before the sweep) and the targets of every operator.  Returns host arrays
-    (X int16 bit patterns [rows][32], t float32 [rows])."""
+    before the sweep) and the floored log targets, thinned by training_rows
+    (all rows if select is False).  Returns host arrays (X int16 bit patterns
+    [rows][32], t float32 [rows])."""
     Xs, ts = [], []
     psi = None
     for it in range(n_iter):
@@ -229,8 +299,13 @@ def collect_rows(adapt: Adapt, fs: FeatureState, n_iter: int):
         g = adapt.last_gradients()
         fs.update(g)
         Xr, tr = fs.rows(np.arange(fs.n))
-        Xs.append(Xr.cpu().numpy())
-        ts.append(tr.cpu().numpy())
+        Xh, th = Xr.cpu().numpy(), tr.cpu().numpy()
+        if select:
+            absolute = th + fs.base.cpu().numpy()
+            keep = training_rows(absolute, np.random.default_rng([seed, it]))
+            Xh, th = Xh[keep], th[keep]
+        Xs.append(Xh)
+        ts.append(th)
         r2 = adapt.select_optimize()
         if r2["selected"] < 0:
             break

@@ -87,7 +87,8 @@ def test_hpsi_32q_benchmark_state_sampled_rows(hyp, prob):
     sig = H.apply(torch.from_numpy(psi_h).cuda())
     da = S.da
     rng = np.random.default_rng(3)
-    rows = [0, 1, S.dim - 1, S.dim - 2, 767, 768, 1535, 1536, da - 1, da, 6 * da + 12799, 12869 * da + 1]
+    rows = [0, 1, S.dim - 1, S.dim - 2, 511, 512, 767, 768, 1023, 1024, 1535, 1536, 12287, 12288,
+            da - 1, da, 6 * da + 12799, 12869 * da + 1]
     rows += rng.choice(S.dim, 36, replace=False).tolist()
     rows = np.unique(np.array(rows, dtype=np.int64))
     got = sig[torch.from_numpy(rows).cuda()].cpu().numpy()
