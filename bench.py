@@ -52,7 +52,7 @@ def kernel_flops(name, m):
         return 2.0 * dim * (sa * sb + sa + sb + 1), "alu"
     if name == "k_ss_apply":  # mean of the alpha- and the beta-row launch
         return 2.0 * dim * (1 + (sa + m["dda"] + sb + m["ddb"]) / 2), "alu"
-    if name == "k_tdens":
+    if name in ("k_tdens", "k_tdens_rows"):
         return 2.0 * dim * (sa + sb * (sa + 1)), "alu"
     if name == "rocblas_dgemm_gram_a":
         return 2.0 * m["da"] * m["da"] * m["db"], "mfma"
@@ -196,8 +196,8 @@ def main():
     hpsi_bytes = hpsi_gather_bytes(m)
     value = hpsi_bytes / (hpsi_ms * 1e-3) / 1e9
     sweep_kernels = ("k_pool_grad", "k_sum_chunks", "k_tdens", "k_tdens_reduce_ab", "k_tdens_reduce_a",
-                     "k_tdens_final", "k_gram_grad", "k_tdens_grad", "k_widen", "rocblas_dgemm_gram_a",
-                     "rocblas_dgemm_gram_b")
+                     "k_tdens_final", "k_tdens_rows", "k_tdens_rows_final", "k_eb_rows", "k_gram_grad",
+                     "k_tdens_grad", "k_widen", "rocblas_dgemm_gram_a", "rocblas_dgemm_gram_b")
     sweep_ms = sum(prof.get(k, (0.0, 0))[0] for k in sweep_kernels) / args.steps
 
     # dominant kernel of the step and its roofline

@@ -288,19 +288,21 @@ struct MixedArgs {
 //
 // One thread per alpha column.  Its (up to 64) alpha single excitations are
 // decoded once into registers as packed entries
-//   bits 0..13  rank of the target alpha string
-//   bit  14     alpha-beta sign (-1)^{popc(abJa & s)}
-//   bits 15..22 pair id * 2 + O (which orbital of the pair is occupied)
-//   bit  23     single-dressing sign (-1)^{popc(sJ & s)}
+//   bits 0..16  LDS byte offset of the source amplitude in the staged row
+//   bits 17..28 LDS byte offset of the coefficient s_fab[(pair*2 + O)*2 + sab],
+//               sab = alpha-beta sign (-1)^{popc(abJa & s)}, O = which orbital
+//               of the pair is occupied
+//   bit  29     single-dressing sign (-1)^{popc(sJ & s)}
 // and reused for every staged source row: the workgroup's own beta row (the
 // alpha singles' beta-occupation dressing and the alpha-beta diagonal), then
 // each beta-single source row (the beta singles' alpha-occupation dressing and
 // the alpha-beta doubles).  Coefficient tables with both signs pre-applied sit
-// in LDS, so one term is two LDS reads and one FMA.
+// in LDS, so one term is two LDS reads and one FMA.  Unused slots point at the
+// zero slot after the row.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  T* s_row = (T*)smem;  // [da]
+  T* s_row = (T*)smem;  // [da + 1]: the staged row and a zero slot
   __shared__ double s_fab[kMaxPairs * 4];   // [(pid*2+O)*2 + sign]
   __shared__ double s_srow[kMaxPairs * 4];  // [(pid*2+O)*2 + sign]
   __shared__ double s_dmix[kMaxOrb];
