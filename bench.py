@@ -109,6 +109,9 @@ def main():
                     help="FP32-storage vs FP64 error study over ITERS ADAPT iterations (JSON lines)")
     ap.add_argument("--adapt-compare", type=int, default=0, metavar="ITERS",
                     help="screened FP32 vs plain FP64 ADAPT iterations on the workload (JSON lines)")
+    ap.add_argument("--shadow", action="store_true",
+                    help="with --adapt-compare: also judge every screened iteration by a full sweep on its own "
+                         "state (diagnostic; the extra sweeps are not in the screened timings)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (hardware-counter calibration)")
     args = ap.parse_args()
@@ -138,7 +141,7 @@ def main():
         fp32_study(w, args.fp32_study)
         return
     if args.adapt_compare:
-        adapt_compare(w, args.adapt_compare)
+        adapt_compare(w, args.adapt_compare, args.shadow)
         return
     M, na, nb = w.n_orb, w.n_alpha, w.n_beta
     t0 = time.time()
@@ -190,6 +193,22 @@ def main():
     print(f"[bench] timed {args.steps} steps: {step_ms:.2f} ms/step", file=sys.stderr, flush=True)
     for k_, (ms, n) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
         print(f"[bench]   {k_:20s} {ms / max(n, 1):10.3f} ms/launch x {n}", file=sys.stderr)
+
+    # FP32 storage (FP64 accumulation) H psi on the same state, tuned for FP32
+    psi32 = psi.float()
+    sig32 = torch.empty_like(psi32)
+    threads32, _ = H.tune(psi32, reps=1)
+    hyp.hyp_apply_h(H, psi32, sig32)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(2):
+        hyp.hyp_apply_h(H, psi32, sig32)
+    e1.record()
+    torch.cuda.synchronize()
+    hpsi32_ms = e0.elapsed_time(e1) / 2
+    del psi32, sig32
+    print(f"[bench] H psi FP32 storage: {hpsi32_ms:.1f} ms ({threads32} threads)", file=sys.stderr, flush=True)
 
     hpsi_kernels = ("k_transpose", "k_ss_apply", "k_mixed")
     hpsi_ms = sum(prof.get(k, (0.0, 0))[0] for k in hpsi_kernels) / args.steps
@@ -247,6 +266,7 @@ def main():
                                f"{m['T']} Pauli terms, pool {m['pool']}",
                    "parallelism": "1 GPU"},
         "hpsi_ms": round(hpsi_ms, 3), "hpsi_threads": int(hpsi_threads),
+        "hpsi_fp32_ms": round(hpsi32_ms, 3), "hpsi_fp32_threads": int(threads32),
         "hpsi_frac_hbm_gather_model": round(value / HBM_PEAK_GBS, 4),
         "pool_grad_evals_per_s": round(m["pool"] / (sweep_ms * 1e-3), 1) if sweep_ms > 0 else None,
         "sweep_ms": round(sweep_ms, 3),
@@ -256,7 +276,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def adapt_compare(w, n_iter):
+def adapt_compare(w, n_iter, shadow=False):
     """The screen is trained on the GPU with the library's own kernels on
     exact sweeps of the 8-, 16- and 24-qubit workloads and the eight batch
     instances (floored residual targets, 16 epochs); then on the target
@@ -295,6 +315,11 @@ def adapt_compare(w, n_iter):
     cre, ann, cls = synth.canonical_pool(M)
     S = hyp.Sector(M, na, nb)
     H = hyp.Hamiltonian(S, x, z, c)
+    probe = torch.from_numpy(synth.random_state(S.dim, 7)).cuda()
+    t64, _ = H.tune(probe, reps=1)
+    t32, _ = H.tune(probe.float(), reps=1)
+    del probe
+    print(json.dumps({"hpsi_threads_fp64": t64, "hpsi_threads_fp32": t32}), flush=True)
     A64 = hyp.Adapt(H, cre, ann, max_iter=n_iter + 1)
     A32 = hyp.Adapt(H, cre, ann, dtype="f32", max_iter=n_iter + 1)
     stat, qidx = scr.static_features(M, cre, ann, cls, h, g)
@@ -304,19 +329,32 @@ def adapt_compare(w, n_iter):
         t1 = time.time()
         r64 = A64.iterate()
         t2 = time.time()
-        info = sc.iterate(it)
+        info = sc.iterate(it, shadow=shadow)
         t3 = time.time()
         print(json.dumps({"iteration": it, "plain_fp64": {"selected": r64["selected"], "E": r64["energy"],
                                                          "grad_ms": round(r64["grad_ms"], 1),
                                                          "opt_ms": round(r64["opt_ms"], 1),
+                                                         "n_evals": r64["n_evals"],
                                                          "iter_s": round(t2 - t1, 2)},
                           "screened_fp32": {"selected": info["selected"], "E": info["energy"],
                                             "judge": info["judge"], "fallback": info["fallback"],
                                             "n_exact": info["n_exact"], "grad_ms": round(info["grad_ms"], 1),
-                                            "opt_ms": round(info["opt_ms"], 1), "iter_s": round(t3 - t2, 2)},
+                                            "opt_ms": round(info["opt_ms"], 1), "n_evals": info["n_evals"],
+                                            "iter_s": round(t3 - t2, 2),
+                                            **({"shadow_agree": info.get("shadow_agree"),
+                                                "shadow_in_candidates": info.get("shadow_in_candidates"),
+                                                "shadow_rank": info.get("shadow_rank")} if shadow else {})},
                           "same_selection": r64["selected"] == info["selected"]}), flush=True)
+    # FP64 polish of the screened run's ansatz
+    ops, th = A32.ansatz()
+    Ap = hyp.Adapt(H, cre, ann, max_iter=n_iter + 1)
+    Ap.set_ansatz(ops, th)
+    t4 = time.time()
+    rp = Ap.optimize()
     print(json.dumps({"final_E_plain_fp64": A64.energy_fp64(), "final_E_screened_fp32_replayed_fp64": A32.energy_fp64(),
-                      "dE": A32.energy_fp64() - A64.energy_fp64()}), flush=True)
+                      "dE": A32.energy_fp64() - A64.energy_fp64(), "final_E_screened_polished_fp64": rp["energy"],
+                      "dE_polished": rp["energy"] - A64.energy_fp64(), "polish_s": round(time.time() - t4, 2),
+                      "polish_evals": rp["n_evals"]}), flush=True)
 
 
 def fp32_study(w, n_iter):

@@ -102,8 +102,9 @@ int hyp_ham_is_structured(hyp_ham h);
 /* Autotuner of the H psi tile shape (the mixed pass's workgroup width, one
  * thread per alpha column): times the candidates {128,...,1024} on this
  * Hamiltonian with reps applications each (HIP events on `stream`), keeps
- * the fastest for later hyp_apply_h calls on h and returns it.  Overwrites
- * sigma_dev.  A generic (non-structured) Hamiltonian returns 0 threads. */
+ * the fastest for later hyp_apply_h calls on h in that storage type (FP64
+ * and FP32 keep separate widths) and returns it.  Overwrites sigma_dev.  A
+ * generic (non-structured) Hamiltonian returns 0 threads. */
 hyp_status hyp_tune_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* sigma_dev,
                             int reps, void* stream, int* best_threads, double* best_ms);
 
@@ -233,6 +234,12 @@ hyp_status hyp_adapt_iterate(hyp_adapt a, const int32_t* cand, int64_t n_cand,
 hyp_status hyp_adapt_gradients(hyp_adapt a, const int32_t* cand, int64_t n_cand,
                                hyp_adapt_record* rec);
 hyp_status hyp_adapt_select_optimize(hyp_adapt a, hyp_adapt_record* rec);
+/* Re-optimises all parameters of the current ansatz (BFGS warm-started from
+ * the current theta) without selecting an operator; rec->selected = -1,
+ * energy_before / energy / n_evals / bfgs_iters / converged / grad_inf /
+ * opt_ms as for a selection.  Used to polish, in FP64, the parameters of an
+ * ansatz found by an FP32 run (hyp_adapt_set_ansatz first). */
+hyp_status hyp_adapt_optimize(hyp_adapt a, hyp_adapt_record* rec);
 /* Pool gradients of the last iteration (host, n = pool size; NaN where not computed). */
 hyp_status hyp_adapt_last_gradients(hyp_adapt a, double* grad, int64_t n);
 /* Current ansatz (pool indices, parameters); with cap < length only *n is set. */

@@ -219,7 +219,8 @@ class Adapt:
 
     dtype "f64" or "f32" (FP32 storage, FP64 accumulation).  Defaults follow
     the selection/optimiser readings: tie_tol 1e-9 (f64) / 1e-5 (f32),
-    BFGS gtol 1e-9 (f64) / 1e-6 (f32), early stop when max|g| < 1e-10.
+    BFGS gtol 1e-9 (f64) / 1e-5 (f32, the gradient's noise floor), early stop
+    when max|g| < 1e-10.
     """
 
     def __init__(self, ham: Hamiltonian, cre, ann, dtype: str = "f64", max_iter: int = 64,
@@ -234,7 +235,7 @@ class Adapt:
             pool[i].cre, pool[i].ann = int(c_), int(a_)
         o = _lib.AdaptOpts(max_iter=max_iter, max_bfgs=max_bfgs, use_graph=1 if use_graph else 0,
                            reserved=0, tie_tol=(1e-5 if f32 else 1e-9) if tie_tol is None else tie_tol,
-                           gtol=(1e-6 if f32 else 1e-9) if gtol is None else gtol,
+                           gtol=(1e-5 if f32 else 1e-9) if gtol is None else gtol,
                            gmax_stop=gmax_stop)
         h = ctypes.c_void_p()
         check(_lib.load().hyp_adapt_create(ham._h, HYP_F32 if f32 else HYP_F64, pool, self.n_pool,
@@ -265,6 +266,12 @@ class Adapt:
         rec = getattr(self, "_rec", None) or _lib.AdaptRecord()
         check(_lib.load().hyp_adapt_select_optimize(self._h, ctypes.byref(rec)))
         self._rec = None
+        return {f: getattr(rec, f) for f, _ in rec._fields_ if f != "reserved"}
+
+    def optimize(self) -> dict:
+        """hyp_adapt_optimize: re-optimise the current ansatz's parameters."""
+        rec = _lib.AdaptRecord()
+        check(_lib.load().hyp_adapt_optimize(self._h, ctypes.byref(rec)))
         return {f: getattr(rec, f) for f, _ in rec._fields_ if f != "reserved"}
 
     def last_gradients(self) -> np.ndarray:

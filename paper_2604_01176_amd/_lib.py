@@ -96,6 +96,7 @@ SIGNATURES = {
     "hyp_adapt_iterate": (_ci, [_vp, _vp, _i64, ctypes.POINTER(AdaptRecord)]),
     "hyp_adapt_gradients": (_ci, [_vp, _vp, _i64, ctypes.POINTER(AdaptRecord)]),
     "hyp_adapt_select_optimize": (_ci, [_vp, ctypes.POINTER(AdaptRecord)]),
+    "hyp_adapt_optimize": (_ci, [_vp, _vp]),
     "hyp_adapt_last_gradients": (_ci, [_vp, _vp, _i64]),
     "hyp_adapt_ansatz": (_ci, [_vp, _vp, _vp, _i64, ctypes.POINTER(_i64)]),
     "hyp_adapt_set_ansatz": (_ci, [_vp, _vp, _vp, _i64]),

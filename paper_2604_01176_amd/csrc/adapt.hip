@@ -193,12 +193,25 @@ struct LineResult {
   std::vector<double> g;
 };
 
+// Energy noise of the evaluation: FP32 storage rounds the state and every
+// product to FP32 (relative error about 1e-7 of E, measured), so sufficient
+// decrease is tested against that floor; FP64 evaluations are exact enough
+// for the plain test.
+static double energy_noise(const Adapt* A, double f) {
+  return A->dt == HYP_F32 ? 2e-7 * std::fabs(f) : 0.0;
+}
+
 // Strong-Wolfe line search (bracketing + zoom with safeguarded cubic
-// interpolation), c1 = 1e-4, c2 = 0.9.
+// interpolation), c1 = 1e-4, c2 = 0.9; with noisy (FP32) energies the
+// sufficient-decrease test is relaxed by the noise floor and the zoom is
+// capped, the best decreasing point being accepted when the curvature test
+// never holds.
 static hyp_status wolfe(Adapt* A, const std::vector<double>& x, double f0,
                         const std::vector<double>& g0, const std::vector<double>& p,
                         LineResult* out) {
   const double c1 = 1e-4, c2 = 0.9;
+  const double eps = energy_noise(A, f0);
+  const int max_zoom = eps > 0.0 ? 10 : 40;
   const size_t n = x.size();
   const double d0 = dotv(g0, p);
   std::vector<double> xt(n), gt(n);
@@ -217,7 +230,7 @@ static hyp_status wolfe(Adapt* A, const std::vector<double>& x, double f0,
     if (r != HYP_OK) return r;
     bool lo_is_prev = true;
     double alo, ahi, flo, fhi, dlo, dhi;
-    if (f > f0 + c1 * a * d0 || (it > 0 && f >= f_prev)) {
+    if (f > f0 + c1 * a * d0 + eps || (it > 0 && f >= f_prev)) {
       alo = a_prev; flo = f_prev; dlo = d_prev; ahi = a; fhi = f; dhi = d;
     } else if (std::fabs(d) <= -c2 * d0) {
       out->ok = true; out->alpha = a; out->f = f; out->g = gt;
@@ -232,7 +245,7 @@ static hyp_status wolfe(Adapt* A, const std::vector<double>& x, double f0,
     }
     (void)lo_is_prev;
     // zoom
-    for (int z = 0; z < 40; ++z) {
+    for (int z = 0; z < max_zoom; ++z) {
       // cubic interpolation between (alo, flo, dlo) and (ahi, fhi, dhi)
       double aj;
       {
@@ -251,7 +264,7 @@ static hyp_status wolfe(Adapt* A, const std::vector<double>& x, double f0,
       double fj, dj;
       hyp_status r2 = phi(aj, &fj, &dj);
       if (r2 != HYP_OK) return r2;
-      if (fj > f0 + c1 * aj * d0 || fj >= flo) {
+      if (fj > f0 + c1 * aj * d0 + eps || fj >= flo) {
         ahi = aj; fhi = fj; dhi = dj;
       } else {
         if (std::fabs(dj) <= -c2 * d0) {
@@ -266,7 +279,7 @@ static hyp_status wolfe(Adapt* A, const std::vector<double>& x, double f0,
       if (std::fabs(ahi - alo) < 1e-14 * std::max(1.0, std::fabs(alo))) break;
     }
     // accept the best sufficient-decrease point if the curvature test never held
-    if (flo < f0 + c1 * alo * d0 && alo > 0.0) {
+    if (alo > 0.0 && (flo < f0 + c1 * alo * d0 || (eps > 0.0 && flo < f0))) {
       double ff, dd;
       hyp_status r3 = phi(alo, &ff, &dd);
       if (r3 != HYP_OK) return r3;
@@ -286,7 +299,7 @@ static hyp_status bfgs(Adapt* A, std::vector<double>& x, double* fout, int* iter
   if (r != HYP_OK) return r;
   std::vector<double> Hi(n * n, 0.0);
   for (size_t i = 0; i < n; ++i) Hi[i * n + i] = 1.0;
-  int it = 0;
+  int it = 0, stall = 0;
   *conv = 0;
   for (; it < A->o.max_bfgs; ++it) {
     if (infnorm(g) <= A->o.gtol) {
@@ -332,6 +345,14 @@ static hyp_status bfgs(Adapt* A, std::vector<double>& x, double* fout, int* iter
     }
     if (std::fabs(fprev - f) <= 1e-16 * std::max(1.0, std::fabs(f)) && infnorm(g) <= 10 * A->o.gtol) {
       *conv = 1;
+      ++it;
+      break;
+    }
+    // noisy energies: three steps in a row that gain less than the noise
+    // floor end the optimisation
+    const double eps = energy_noise(A, f);
+    stall = (eps > 0.0 && fprev - f <= eps) ? stall + 1 : 0;
+    if (stall >= 3) {
       ++it;
       break;
     }
@@ -555,6 +576,42 @@ hyp_status hyp_adapt_iterate(hyp_adapt h, const int32_t* cand, int64_t n_cand, h
   hyp_status r = hyp_adapt_gradients(h, cand, n_cand, rec);
   if (r != HYP_OK) return r;
   return hyp_adapt_select_optimize(h, rec);
+}
+
+hyp_status hyp_adapt_optimize(hyp_adapt h, hyp_adapt_record* rec) {
+  if (!h || !rec) return fail(HYP_ERR_ARG, "hyp_adapt_optimize: NULL argument");
+  Adapt& A = h->a;
+  std::memset(rec, 0, sizeof(*rec));
+  rec->selected = -1;
+  auto t1 = std::chrono::steady_clock::now();
+  if (A.ops.empty()) {
+    hyp_status r = prepare_state(&A);
+    if (r != HYP_OK) return r;
+    HYP_HIP(hipMemcpyAsync(A.h_pin, A.d_scal, sizeof(double), hipMemcpyDeviceToHost, A.st));
+    HYP_HIP(hipStreamSynchronize(A.st));
+    rec->energy = rec->energy_before = A.h_pin[0];
+    rec->converged = 1;
+    return HYP_OK;
+  }
+  A.n_evals = 0;
+  std::vector<double> x = A.theta;
+  std::vector<double> g0(x.size());
+  double f0 = 0.0;
+  hyp_status r = evaluate(&A, x.data(), &f0, g0.data());
+  if (r != HYP_OK) return r;
+  rec->energy_before = f0;
+  double f = 0.0, ginf = 0.0;
+  int iters = 0, conv = 0;
+  r = bfgs(&A, x, &f, &iters, &conv, &ginf);
+  if (r != HYP_OK) return r;
+  A.theta = x;
+  rec->energy = f;
+  rec->n_evals = A.n_evals;
+  rec->bfgs_iters = iters;
+  rec->converged = conv;
+  rec->grad_inf = ginf;
+  rec->opt_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+  return HYP_OK;
 }
 
 hyp_status hyp_adapt_last_gradients(hyp_adapt h, double* out, int64_t n) {

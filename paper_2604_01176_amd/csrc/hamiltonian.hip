@@ -575,8 +575,12 @@ static hyp_status build_same_spin(Ham* Hm, HamWork* W, hipStream_t st) {
 }
 
 // threads per mixed-kernel workgroup: one per alpha column, at most 1024 (a
-// 16-wave workgroup leaves 128 registers per lane; the kernel needs about 105)
-static int pick_threads(int da) { return std::max(64, std::min(1024, (da + 63) / 64 * 64)); }
+// 16-wave workgroup leaves 128 registers per lane; the kernel needs about
+// 105).  FP32 rows take half the LDS, so two 512-wide workgroups fit on a CU
+// and one's row staging overlaps the other's products.
+static int pick_threads(int da, hyp_dtype dt) {
+  return std::max(64, std::min(dt == HYP_F32 ? 512 : 1024, (da + 63) / 64 * 64));
+}
 
 template <typename T>
 static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sigma,
@@ -626,7 +630,7 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   ma.arank = S->d_arank;
   ma.brank = S->d_brank;
   ma.H = Hm->dev;
-  const int nt = Hm->threads;
+  const int nt = Hm->threads[sizeof(T) == 4 ? 1 : 0];
   ma.nchunk = (da + nt - 1) / nt;
   // the row plus one zero slot (index da) that padded excitation entries read
   const size_t shm = ((size_t)(da + 1) * sizeof(T) + 15) & ~(size_t)15;
@@ -962,7 +966,8 @@ hyp_status hyp_build_hamiltonian(hyp_sector sh, const uint32_t* x_mask, const ui
     H.dev.wJ = (const uint32_t*)(b + o_wJ);
     H.dev.abJa = (const uint32_t*)(b + o_abJa);
     H.dev.abJb = (const uint32_t*)(b + o_abJb);
-    H.threads = pick_threads((int)S->da);
+    H.threads[0] = pick_threads((int)S->da, HYP_F64);
+    H.threads[1] = pick_threads((int)S->da, HYP_F32);
     // workspace: psi^T and the two same-spin partials
     e = hipMalloc(&hh->w.psi_t, (size_t)S->dim * 8);
     if (e == hipSuccess) e = hipMalloc(&hh->w.part_a, (size_t)S->dim * 8);
@@ -1023,11 +1028,12 @@ hyp_status hyp_tune_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* 
   HYP_HIP(hipEventCreate(&e0));
   HYP_HIP(hipEventCreate(&e1));
   double bms = 1e300;
-  int bt = H->threads;
+  const int ti = dtype == HYP_F32 ? 1 : 0;
+  int bt = H->threads[ti];
   hyp_status r = HYP_OK;
   for (int t : cand) {
     if (t > std::max(64, (da + 63) / 64 * 64) && t != cand[0]) continue;
-    H->threads = std::min(t, std::max(64, (da + 63) / 64 * 64));
+    H->threads[ti] = std::min(t, std::max(64, (da + 63) / 64 * 64));
     r = apply_h_internal(hh, dtype, psi, sigma, st);
     if (r != HYP_OK) break;
     HYP_HIP(hipEventRecord(e0, st));
@@ -1038,12 +1044,12 @@ hyp_status hyp_tune_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* 
     HYP_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (r == HYP_OK && ms / reps < bms) {
       bms = ms / reps;
-      bt = H->threads;
+      bt = H->threads[ti];
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  H->threads = bt;
+  H->threads[ti] = bt;
   if (r != HYP_OK) return r;
   *best_threads = bt;
   *best_ms = bms;

@@ -134,7 +134,7 @@ struct Ham {
   uint32_t* d_tz = nullptr;        // [T] z mask
   double* d_tc = nullptr;          // [T] c' = c (-1)^{n_Y/2}
   // launch tuning for the structured kernel
-  int threads = 0;
+  int threads[2] = {0, 0};  // mixed-pass workgroup width per storage type: [0] FP64, [1] FP32
 };
 
 hyp_status launch_dot(Sector* S, hyp_dtype dt, const void* a, const void* b, double* out,

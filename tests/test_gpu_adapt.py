@@ -148,8 +148,24 @@ def test_adapt_fp32_close_to_fp64(hyp):
     H = hyp.Hamiltonian(S, x, z, c)
     A64 = hyp.Adapt(H, cre, ann, max_iter=8)
     A32 = hyp.Adapt(H, cre, ann, dtype="f32", max_iter=8)
+    same = True
     for _ in range(6):
         r64 = A64.iterate()
         r32 = A32.iterate(None)
         assert r32["selected"] == r64["selected"] or r32["tie_count"] > 1
+        same &= r32["selected"] == r64["selected"]
+        assert r32["n_evals"] < 200  # the noise-aware line search does not churn
     assert abs(A32.energy_fp64() - A64.energy_fp64()) < 1e-6
+    # FP64 polish of the FP32 run's ansatz (hyp_adapt_optimize)
+    ops, th = A32.ansatz()
+    Ap = hyp.Adapt(H, cre, ann, max_iter=8)
+    Ap.set_ansatz(ops, th)
+    rp = Ap.optimize()
+    assert rp["selected"] == -1 and rp["converged"] == 1
+    assert rp["energy"] <= rp["energy_before"] + 1e-12
+    if same:
+        assert abs(rp["energy"] - A64.energy_fp64()) < 1e-9
+    prob = SectorProblem(w.n_orb, w.n_alpha, w.n_beta, x, z, c, cre, ann)
+    _, thp = Ap.ansatz()
+    e_o, _ = prob.energy_grad(list(ops), thp)
+    assert abs(rp["energy"] - e_o) < 1e-10
