@@ -306,7 +306,7 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   __shared__ double s_fab[kMaxPairs * 4];   // [(pid*2+O)*2 + sign]
   __shared__ double s_srow[kMaxPairs * 4];  // [(pid*2+O)*2 + sign]
   __shared__ double s_dmix[kMaxOrb];
-  __shared__ double s_bdress[kMaxOrb];
+  __shared__ double s_bdress[kMaxOrb + 1];  // per stage; [kMaxOrb] = 0 for padded reads
   __shared__ int2 s_stage[64];  // per beta single: (source rank, pair | O << 16 | signs << 17)
 
   const int M = a.M;
@@ -428,35 +428,63 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
                             pb | ((i == q) ? 1 << 16 : 0) | (int)(sgn_s << 17) | (int)(sgn_ab << 18));
   }
   __syncthreads();
+  // LDS byte offsets of s_bdress entries of this thread's occupied orbitals,
+  // padded with the zero entry, for the per-stage dressing sum
+  uint32_t occ_off[16];
+  {
+    const uint32_t zero = (uint32_t)((const char*)&s_bdress[kMaxOrb] - (const char*)s_bdress);
+    uint32_t o = s;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      occ_off[j] = o ? (uint32_t)(__ffs(o) - 1) * 8u : zero;
+      o &= o - 1;
+    }
+  }
+  if (tid == 0) s_bdress[kMaxOrb] = 0.0;
+  const int occ_groups = (__popc(s) + 7) >> 3;  // same for every thread
   for (int jb = 0; jb < nbs; ++jb) {
     // the entries are opaque to the optimiser here: otherwise it hoists the
     // 128 addresses derived from them out of the loop and spills
 #pragma unroll
     for (int x = 0; x < 64; ++x) asm volatile("" : "+v"(ex[x]));
     __syncthreads();
-    // the stage's coefficients and dressing are loaded in the same phase as
-    // the row, so their latencies overlap
+    // the stage's coefficient (alpha excitation tid) and dressing (orbital
+    // tid) are loaded first and stored after the row copy is issued, so one
+    // wait covers all three
     const int info = s_stage[jb].y;
     const int pb = info & 0xffff, Ob = (info >> 16) & 1;
-    for (int x = tid; x < kMaxPairs * 2; x += nt) {
+    double f_ld = 0.0, d_ld = 0.0;
+    if (tid < kMaxPairs * 2)
+      f_ld = H.abF[((size_t)(tid >> 1) * kMaxPairs + pb) * 4 + (tid & 1) * 2 + Ob];
+    if (tid < M) d_ld = H.sB[(size_t)((kMaxPairs + pb) * 2 + Ob) * 32 + tid];
+    stage_row_lds(s_row, psi + (int64_t)s_stage[jb].x * a.da, a.da * (int)sizeof(T), tid, nt);
+    asm volatile("" ::: "memory");
+    if (tid < kMaxPairs * 2) {
+      const double f = ((info >> 18) & 1) ? -f_ld : f_ld;
+      s_fab[2 * tid] = f;
+      s_fab[2 * tid + 1] = -f;
+    }
+    if (tid < M) s_bdress[tid] = ((info >> 17) & 1) ? -d_ld : d_ld;
+    for (int x = tid + nt; x < kMaxPairs * 2; x += nt) {  // only when nt < 240
       const int pa = x >> 1, Oa = x & 1;
       const double f0 = H.abF[((size_t)pa * kMaxPairs + pb) * 4 + Oa * 2 + Ob];
       const double f = ((info >> 18) & 1) ? -f0 : f0;
       s_fab[2 * x] = f;
       s_fab[2 * x + 1] = -f;
     }
-    if (tid < M) {
-      const double d = H.sB[(size_t)((kMaxPairs + pb) * 2 + Ob) * 32 + tid];
-      s_bdress[tid] = ((info >> 17) & 1) ? -d : d;
-    }
-    stage_row_lds(s_row, psi + (int64_t)s_stage[jb].x * a.da, a.da * (int)sizeof(T), tid, nt);
     __syncthreads();
     double dr = 0.0;
-    uint32_t o = s;
-    while (o) {
-      const int kk = __ffs(o) - 1;
-      o &= o - 1;
-      dr += s_bdress[kk];
+    {
+      const char* bd = (const char*)s_bdress;
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+        if (g < occ_groups) {
+          double v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = *(const double*)(bd + occ_off[g * 8 + j]);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) dr += v[j];
+        }
     }
     double sum = Acc<T>::prod(dr, s_row[live ? col : 0]);
 #pragma unroll

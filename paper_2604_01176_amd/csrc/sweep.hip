@@ -192,13 +192,15 @@ struct TRArgs {
   double* part;       // [n_eb + n_id][nchunk][kStageW]
 };
 
-// Source ranks of a string's alpha single excitations (colex ranks < 2^14),
-// two per register, in the enumeration order (occupied i ascending, then empty
-// e ascending); unused slots hold pad; *ns receives their number.
+// LDS byte offsets (source rank * element size) of a string's alpha single
+// excitations in the staged row, in the enumeration order (occupied i
+// ascending, then empty e ascending); unused slots hold pad; *ns receives
+// their number.
+template <typename T>
 __device__ inline void alpha_sources(uint32_t s, uint32_t amask, const RankTables* R, uint32_t pad,
-                                     uint32_t (&ex)[32], int* ns) {
+                                     uint32_t (&ex)[64], int* ns) {
 #pragma unroll
-  for (int x = 0; x < 32; ++x) ex[x] = pad | (pad << 16);
+  for (int x = 0; x < 64; ++x) ex[x] = pad;
   int n = 0;
   uint32_t occ = s;
   while (occ) {
@@ -209,11 +211,10 @@ __device__ inline void alpha_sources(uint32_t s, uint32_t amask, const RankTable
       const int e = __ffs(emp) - 1;
       emp &= emp - 1;
       const uint32_t t2 = s ^ (1u << i) ^ (1u << e);
-      const uint32_t r2 = (uint32_t)(R->lo[t2 & 255u] + R->hi[(t2 >> 8) & 255u]);
+      const uint32_t off = (uint32_t)(R->lo[t2 & 255u] + R->hi[(t2 >> 8) & 255u]) * (uint32_t)sizeof(T);
 #pragma unroll
-      for (int x = 0; x < 32; ++x)
-        if (2 * x == n) ex[x] = (ex[x] & 0xffff0000u) | r2;
-        else if (2 * x + 1 == n) ex[x] = (ex[x] & 0xffffu) | (r2 << 16);
+      for (int x = 0; x < 64; ++x)
+        if (x == n) ex[x] = off;
       ++n;
     }
   }
@@ -263,9 +264,9 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
   const bool live = col < a.da;
   const uint32_t s = live ? a.astr[col] : a.astr[0];
   // unused excitation slots read the zero slot s_row[da]
-  uint32_t ex[32];
+  uint32_t ex[64];
   int ns = 0;
-  alpha_sources(s, amask, a.arank, (uint32_t)a.da, ex, &ns);
+  alpha_sources<T>(s, amask, a.arank, (uint32_t)a.da * (uint32_t)sizeof(T), ex, &ns);
   double acc[64];
 #pragma unroll
   for (int x = 0; x < 64; ++x) acc[x] = 0.0;
@@ -290,25 +291,32 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
     __syncthreads();
     cur = nxt;
     if (live) {
-      // nsx (every string's excitation count) is a kernel argument, so the
-      // guard below is a uniform scalar branch
-      if (sizeof(T) == 4) {
+      // groups of eight slots, each behind one uniform guard (nsx is a
+      // kernel argument; slots past a string's excitations read the zero
+      // slot): a group is one basic block with eight LDS reads in flight,
+      // then their eight products
+      const double w = sb * (double)sv;
+      const char* rb = (const char*)s_row;
 #pragma unroll
-        for (int x = 0; x < 64; ++x)
-          if (x < a.nsx) {
-            const uint32_t r = (ex[x >> 1] >> ((x & 1) * 16)) & 0xffffu;
-            acc[x] += (double)((float)sv * (float)s_row[r]) * sb;
-          }
-        if (!ident) acc_id += (double)((float)sv * (float)s_row[col]) * sb;
-      } else {
-        const double w = sb * (double)sv;
+      for (int g8 = 0; g8 < 8; ++g8) {
+        if (g8 * 8 < a.nsx) {
+          T v[8];
 #pragma unroll
-        for (int x = 0; x < 64; ++x)
-          if (x < a.nsx) {
-            const uint32_t r = (ex[x >> 1] >> ((x & 1) * 16)) & 0xffffu;
-            acc[x] += w * (double)s_row[r];
+          for (int j = 0; j < 8; ++j) v[j] = *(const T*)(rb + ex[g8 * 8 + j]);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (sizeof(T) == 4)
+              acc[g8 * 8 + j] += (double)((float)sv * (float)v[j]) * sb;
+            else
+              acc[g8 * 8 + j] += w * (double)v[j];
           }
-        if (!ident) acc_id += w * (double)s_row[col];
+        }
+      }
+      if (!ident) {
+        if (sizeof(T) == 4)
+          acc_id += (double)((float)sv * (float)s_row[col]) * sb;
+        else
+          acc_id += w * (double)s_row[col];
       }
     }
   }

@@ -207,7 +207,8 @@ def test_rotation_errors(hyp):
         hyp.hyp_apply_excitation(S, 0b10, 0b10, 0.1, d)
 
 
-@pytest.mark.parametrize("M,na,nb", [(4, 2, 2), (5, 2, 3), (6, 3, 3), (8, 4, 4), (9, 5, 4), (3, 0, 2), (4, 4, 1)])
+@pytest.mark.parametrize("M,na,nb", [(4, 2, 2), (5, 2, 3), (6, 3, 3), (8, 4, 4), (9, 5, 4), (3, 0, 2), (4, 4, 1),
+                                     (7, 3, 2), (10, 4, 5), (2, 1, 1)])
 def test_pool_gradients_transition_values(hyp, M, na, nb):
     """The transition-value sweep (forced) against the oracle and the pair kernel."""
     S, H, (x, z, c) = _ham(hyp, M, na, nb)
