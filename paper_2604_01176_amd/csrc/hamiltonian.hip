@@ -53,6 +53,7 @@ template <>
 struct Acc<float> {
   // FP32 product, FP64 accumulation by the caller
   __device__ static inline double prod(double c, float v) { return (double)((float)c * v); }
+  __device__ static inline double prod(float c, float v) { return (double)(c * v); }
   __device__ static inline double load(const float* p) { return (double)*p; }
 };
 
@@ -289,7 +290,8 @@ struct MixedArgs {
 // One thread per alpha column.  Its (up to 64) alpha single excitations are
 // decoded once into registers as packed entries
 //   bits 0..16  LDS byte offset of the source amplitude in the staged row
-//   bits 17..28 LDS byte offset of the coefficient s_fab[(pair*2 + O)*2 + sab],
+//   bits 17..28 LDS byte offset of the coefficient s_fab[(pair*2 + O)*2 + sab]
+//               (storage-type elements),
 //               sab = alpha-beta sign (-1)^{popc(abJa & s)}, O = which orbital
 //               of the pair is occupied
 //   bit  29     single-dressing sign (-1)^{popc(sJ & s)}
@@ -303,7 +305,9 @@ template <typename T>
 __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* s_row = (T*)smem;  // [da + 1]: the staged row and a zero slot
-  __shared__ double s_fab[kMaxPairs * 4];   // [(pid*2+O)*2 + sign]
+  // [(pid*2+O)*2 + sign], in the storage type: the FP32 path multiplies in
+  // FP32 with the coefficient rounded to FP32 either way
+  __shared__ T s_fab[kMaxPairs * 4];
   __shared__ double s_srow[kMaxPairs * 4];  // [(pid*2+O)*2 + sign]
   __shared__ double s_dmix[kMaxOrb];
   __shared__ double s_bdress[kMaxOrb + 1];  // per stage; [kMaxOrb] = 0 for padded reads
@@ -372,8 +376,8 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
         // LDS byte offsets: the source amplitude (bits 0..16) and the
         // coefficient s_fab[(pair*2 + O)*2 + sab] (bits 17..28); bit 29 is
         // the sign of the singles' dressing
-        const uint32_t ent = (r2 * (uint32_t)sizeof(T)) | (((((uint32_t)pid * 2u + O) * 2u + sab) * 8u) << 17) |
-                             (ssg << 29);
+        const uint32_t ent = (r2 * (uint32_t)sizeof(T)) |
+                             (((((uint32_t)pid * 2u + O) * 2u + sab) * (uint32_t)sizeof(T)) << 17) | (ssg << 29);
 #pragma unroll
         for (int x = 0; x < 64; ++x)
           if (x == ns) ex[x] = ent;
@@ -400,7 +404,7 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
 #pragma unroll
     for (int x = 0; x < 64; ++x) {
       const uint32_t e = ex[x];
-      const int fi = (int)(((e >> 20) & 0x1feu) | ((e >> 29) & 1u));
+      const int fi = (int)(((((e >> 17) & 0xfffu) / (uint32_t)sizeof(T)) & ~1u) | ((e >> 29) & 1u));
       acc += Acc<T>::prod(s_srow[fi], *(const T*)((const char*)s_row + (e & 0x1ffffu)));
     }
     asm volatile("" : "+v"(acc));  // finish the products here, not after the table loop below
@@ -461,16 +465,16 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
     asm volatile("" ::: "memory");
     if (tid < kMaxPairs * 2) {
       const double f = ((info >> 18) & 1) ? -f_ld : f_ld;
-      s_fab[2 * tid] = f;
-      s_fab[2 * tid + 1] = -f;
+      s_fab[2 * tid] = (T)f;
+      s_fab[2 * tid + 1] = (T)(-f);
     }
     if (tid < M) s_bdress[tid] = ((info >> 17) & 1) ? -d_ld : d_ld;
     for (int x = tid + nt; x < kMaxPairs * 2; x += nt) {  // only when nt < 240
       const int pa = x >> 1, Oa = x & 1;
       const double f0 = H.abF[((size_t)pa * kMaxPairs + pb) * 4 + Oa * 2 + Ob];
       const double f = ((info >> 18) & 1) ? -f0 : f0;
-      s_fab[2 * x] = f;
-      s_fab[2 * x + 1] = -f;
+      s_fab[2 * x] = (T)f;
+      s_fab[2 * x + 1] = (T)(-f);
     }
     __syncthreads();
     double dr = 0.0;
@@ -490,7 +494,7 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
 #pragma unroll
     for (int x = 0; x < 64; ++x) {
       const uint32_t e2 = ex[x];
-      sum += Acc<T>::prod(*(const double*)((const char*)s_fab + ((e2 >> 17) & 0xfffu)),
+      sum += Acc<T>::prod(*(const T*)((const char*)s_fab + ((e2 >> 17) & 0xfffu)),
                           *(const T*)((const char*)s_row + (e2 & 0x1ffffu)));
     }
     acc += sum;
