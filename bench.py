@@ -109,6 +109,9 @@ def main():
                     help="FP32-storage vs FP64 error study over ITERS ADAPT iterations (JSON lines)")
     ap.add_argument("--adapt-compare", type=int, default=0, metavar="ITERS",
                     help="screened FP32 vs plain FP64 ADAPT iterations on the workload (JSON lines)")
+    ap.add_argument("--batch", action="store_true",
+                    help="full pool-gradient sweeps of the eight uneven batch instances: one persistent batched "
+                         "launch (autotuned tile) against per-instance sweeps (JSON line)")
     ap.add_argument("--shadow", action="store_true",
                     help="with --adapt-compare: also judge every screened iteration by a full sweep on its own "
                          "state (diagnostic; the extra sweeps are not in the screened timings)")
@@ -135,6 +138,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": n * 8, "bytes_written": n * 8, "copies": 3}))
+        return
+    if args.batch:
+        batch_bench()
         return
     w = synth.WORKLOADS[args.workload]
     if args.fp32_study:
@@ -355,6 +361,82 @@ def adapt_compare(w, n_iter, shadow=False):
                       "dE": A32.energy_fp64() - A64.energy_fp64(), "final_E_screened_polished_fp64": rp["energy"],
                       "dE_polished": rp["energy"] - A64.energy_fp64(), "polish_s": round(time.time() - t4, 2),
                       "polish_evals": rp["n_evals"]}), flush=True)
+
+
+def batch_bench(reps=5):
+    """Eight uneven instances (M = 8..12), each with its full pool on a random
+    state and its sigma: one persistent batched launch with the autotuned tile
+    against the per-instance sweeps (the library's automatic strategy), both
+    timed with HIP events on the library's stream; FP64."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2604_01176_amd as hyp
+
+    jobs, total = [], 0
+    for i, v in enumerate(synth.INSTANCES):
+        x, z, c, _, _ = synth.hamiltonian(v)
+        cre, ann, _ = synth.canonical_pool(v.n_orb)
+        S = hyp.Sector(v.n_orb, v.n_alpha, v.n_beta)
+        H = hyp.Hamiltonian(S, x, z, c)
+        psi = torch.from_numpy(synth.random_state(S.dim, 100 + i)).cuda()
+        sig = H.apply(psi)
+        ops = hyp.exc_tensor(cre, ann)
+        g = torch.empty(len(cre), dtype=torch.float64, device="cuda")
+        jobs.append((S, ops, psi, sig, g, H))
+        total += len(cre)
+    bj = [j[:5] for j in jobs]
+    tile, tune_ms = hyp.hyp_tune_pool_gradients(bj, reps=2)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_batched = timed(lambda: hyp.hyp_pool_gradients_batched(bj, tile))
+    g_batched = [j[4].clone() for j in jobs]
+
+    def per_instance():
+        for S, ops, psi, sig, g, _ in jobs:
+            hyp.hyp_pool_gradients(S, ops, psi, sig, g)
+    ms_single = timed(per_instance)
+    dev = max(float((a - j[4]).abs().max()) / max(1.0, float(j[4].abs().max())) for a, j in zip(g_batched, jobs))
+    try:
+        hyp.set_sweep_mode("pairs")
+        ms_fused_full = timed(lambda: hyp.hyp_pool_gradients_batched(bj, tile))
+    finally:
+        hyp.set_sweep_mode("auto")
+    # candidate subsets (768 per instance, the screen's K + audit): fused launch vs per-instance calls
+    rng = np.random.default_rng(5)
+    sub = []
+    for S, ops, psi, sig, g, _ in jobs:
+        k = torch.from_numpy(np.sort(rng.choice(ops.shape[0], min(768, ops.shape[0] // 5), replace=False))).cuda()
+        sub.append((S, ops.index_select(0, k).contiguous(), psi, sig,
+                    torch.empty(k.shape[0], dtype=torch.float64, device="cuda")))
+    n_sub = sum(j[1].shape[0] for j in sub)
+    tile_sub, _ = hyp.hyp_tune_pool_gradients(sub, reps=2)
+    ms_sub_fused = timed(lambda: hyp.hyp_pool_gradients_batched(sub, tile_sub))
+
+    def sub_single():
+        for S, ops, psi, sig, g in sub:
+            hyp.hyp_pool_gradients(S, ops, psi, sig, g)
+    ms_sub_single = timed(sub_single)
+    print(json.dumps({"instances": [f"M={v.n_orb} ({v.n_alpha},{v.n_beta})" for v in synth.INSTANCES],
+                      "full_pools": {"generators": total, "batched_ms": round(ms_batched, 3),
+                                     "batched_evals_per_s": round(total / (ms_batched * 1e-3), 1),
+                                     "per_instance_ms": round(ms_single, 3),
+                                     "fused_pair_launch_ms": round(ms_fused_full, 3), "tile": list(tile),
+                                     "max_rel_diff": dev},
+                      "candidate_subsets": {"generators": n_sub, "fused_ms": round(ms_sub_fused, 3),
+                                            "fused_evals_per_s": round(n_sub / (ms_sub_fused * 1e-3), 1),
+                                            "per_instance_ms": round(ms_sub_single, 3), "tile": list(tile_sub)}}),
+          flush=True)
 
 
 def fp32_study(w, n_iter):

@@ -150,14 +150,19 @@ hyp_status hyp_set_sweep_mode(int mode);
 hyp_status hyp_apply_excitation(hyp_sector s, hyp_dtype dtype, hyp_exc op, double theta,
                                 void* psi_dev, void* stream);
 
-/* Batched pool gradients: the jobs (up to 16 instances, possibly of
- * different sectors, one dtype) run in ONE persistent launch that drains a
- * device work queue of (instance, generator, beta-chunk) items, then one
- * fixed-order reduction per generator; results equal hyp_pool_gradients per
- * job up to summation order.  Excitations are validated on the host first
- * (device-to-host copy of every ops_dev array).  Uses a per-device library
- * scratch (grow-only): concurrent batched calls on one device race.
- * tile == NULL selects {256 threads, 16 chunks, 4 workgroups per CU}. */
+/* Batched pool gradients for up to 16 instances (possibly of different
+ * sectors, one dtype).  Jobs whose list covers at least a quarter of their
+ * sector's full pool take the transition-value sweep of hyp_pool_gradients
+ * (per instance, in order on `stream`: for full pools it is several times
+ * faster than any pair enumeration); the other jobs (candidate subsets) run
+ * in ONE persistent launch that drains a device work queue of (instance,
+ * generator, beta-chunk) items, then one fixed-order reduction per
+ * generator.  With hyp_set_sweep_mode(1) every job takes the persistent
+ * launch.  Results equal hyp_pool_gradients per job up to summation order.
+ * Excitations are validated on the host first (device-to-host copy of every
+ * ops_dev array).  Uses per-device library scratch (grow-only): concurrent
+ * batched calls on one device race.  tile (persistent launch only) == NULL
+ * selects {256 threads, 16 chunks, 4 workgroups per CU}. */
 typedef struct {
   hyp_sector sector;
   hyp_dtype dtype;
@@ -175,9 +180,10 @@ typedef struct {
 } hyp_sweep_tile;
 hyp_status hyp_pool_gradients_batched(const hyp_grad_job* jobs, int n_jobs,
                                       const hyp_sweep_tile* tile, void* stream);
-/* Autotuner: times every tile of {128,256,512} x {4,8,16,32} x {2,4,8} on
- * these jobs (reps launches each, HIP events on `stream`) and returns the
- * fastest and its mean time.  Overwrites the jobs' gradient outputs. */
+/* Autotuner of the persistent launch: times every tile of {128,256,512} x
+ * {4,8,16,32} x {2,4,8} with all jobs in that launch (reps launches each, HIP
+ * events on `stream`) and returns the fastest and its mean time.  Overwrites
+ * the jobs' gradient outputs. */
 hyp_status hyp_tune_pool_gradients(const hyp_grad_job* jobs, int n_jobs, int reps,
                                    hyp_sweep_tile* best, double* best_ms, void* stream);
 

@@ -348,7 +348,21 @@ hyp_status hyp_pool_gradients_batched(const hyp_grad_job* jobs, int n_jobs, cons
   if (r != HYP_OK) return r;
   hyp_sweep_tile t = tile ? *tile : hyp_sweep_tile{256, 16, 4, 0};
   if (!tile_ok(t)) return fail(HYP_ERR_ARG, "batched gradients: bad tile");
-  return launch_batched(jobs, n_jobs, dt, t, (hipStream_t)stream);
+  hipStream_t st = (hipStream_t)stream;
+  // full pools: the transition-value sweep per instance; subsets: one fused launch
+  std::vector<hyp_grad_job> rest;
+  for (int i = 0; i < n_jobs; ++i) {
+    Sector* S = sector_of(jobs[i].sector);
+    if (prefer_full_sweep(S, jobs[i].n_ops)) {
+      r = launch_pool_gradients(S, dt, jobs[i].ops_dev, jobs[i].n_ops, jobs[i].psi_dev, jobs[i].sigma_dev,
+                                jobs[i].grad_dev, st);
+      if (r != HYP_OK) return r;
+    } else {
+      rest.push_back(jobs[i]);
+    }
+  }
+  if (rest.empty()) return HYP_OK;
+  return launch_batched(rest.data(), (int)rest.size(), dt, t, st);
 }
 
 hyp_status hyp_tune_pool_gradients(const hyp_grad_job* jobs, int n_jobs, int reps,

@@ -404,6 +404,10 @@ hyp_status launch_pool_gradients(Sector* S, hyp_dtype dt, const hyp_exc* ops, in
   return launch_pool_grad<float>(S, ops, n_ops, psi, sig, grad, st);
 }
 
+bool prefer_full_sweep(const Sector* S, int64_t n_ops) {
+  return g_sweep_mode != 1 && n_ops * 4 >= full_pool_size(S->M);
+}
+
 hyp_status set_sweep_mode(int mode) {
   if (mode < 0 || mode > 3) return fail(HYP_ERR_ARG, "hyp_set_sweep_mode: mode must be 0, 1, 2 or 3");
   g_sweep_mode = mode;

@@ -33,27 +33,42 @@ def instances(hyp):
     return out
 
 
-def test_batched_equals_single_and_oracle(hyp, instances):
-    jobs, refs = [], []
-    for d in instances:
-        g = torch.empty(len(d["cre"]), dtype=torch.float64, device="cuda")
-        jobs.append((d["S"], d["ops"], d["psi"], d["sig"], g))
-        refs.append(hyp.hyp_pool_gradients(d["S"], d["ops"], d["psi"], d["sig"]).cpu().numpy())
-    for tile in [None, (128, 4, 2), (512, 32, 8), (64, 1, 1)]:
-        hyp.hyp_pool_gradients_batched(jobs, tile)
-        torch.cuda.synchronize()
-        for (S, ops, psi, sig, g), ref in zip(jobs, refs):
-            got = g.cpu().numpy()
-            assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+@pytest.mark.parametrize("route", ["full", "subset", "pairs"])
+def test_batched_equals_single_and_oracle(hyp, instances, route):
+    """Full pools (transition-value sweeps per instance), candidate subsets
+    (the fused persistent launch) and full pools forced through the fused
+    launch, against per-instance calls and the oracle."""
+    jobs, refs, subsets = [], [], []
+    rng0 = np.random.default_rng(11)
+    try:
+        if route == "pairs":
+            hyp.set_sweep_mode("pairs")
+        for d in instances:
+            n = len(d["cre"])
+            k = np.sort(rng0.choice(n, n // 7, replace=False)) if route == "subset" else np.arange(n)
+            subsets.append(k)
+            ops = hyp.exc_tensor(d["cre"][k], d["ann"][k])
+            g = torch.empty(len(k), dtype=torch.float64, device="cuda")
+            jobs.append((d["S"], ops, d["psi"], d["sig"], g))
+            refs.append(hyp.hyp_pool_gradients(d["S"], ops, d["psi"], d["sig"]).cpu().numpy())
+        for tile in [None, (128, 4, 2), (512, 32, 8), (64, 1, 1)]:
+            hyp.hyp_pool_gradients_batched(jobs, tile)
+            torch.cuda.synchronize()
+            for (S, ops, psi, sig, g), ref in zip(jobs, refs):
+                got = g.cpu().numpy()
+                assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    finally:
+        hyp.set_sweep_mode("auto")
     # oracle on a sample of generators of every instance
     rng = np.random.default_rng(2)
-    for d, (S, ops, psi, sig, g) in zip(instances, jobs):
+    for d, sub, (S, ops, psi, sig, g) in zip(instances, subsets, jobs):
         w = d["w"]
-        k = rng.choice(len(d["cre"]), 6, replace=False)
+        j = rng.choice(len(sub), 6, replace=False)
+        k = sub[j]
         sig_h = d["sig"].cpu().numpy()
         ref = oracle.pool_gradients(w.n_orb, w.n_alpha, w.n_beta, d["cre"][k], d["ann"][k],
                                     d["psi_h"], sig_h)
-        got = g.cpu().numpy()[k]
+        got = g.cpu().numpy()[j]
         assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
 
 
