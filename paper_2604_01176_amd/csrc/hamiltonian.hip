@@ -289,9 +289,9 @@ struct MixedArgs {
 //
 // One thread per alpha column.  Its (up to 64) alpha single excitations are
 // decoded once into registers as packed entries
-//   bits 0..16  LDS byte offset of the source amplitude in the staged row
-//   bits 17..28 LDS byte offset of the coefficient s_fab[(pair*2 + O)*2 + sab]
-//               (storage-type elements),
+//   bits 0..16  LDS address of the source amplitude in the staged row
+//   bits 17..28 byte offset of the coefficient s_fab[(pair*2 + O)*2 + sab]
+//               (storage-type elements; the table is at LDS address 0),
 //               sab = alpha-beta sign (-1)^{popc(abJa & s)}, O = which orbital
 //               of the pair is occupied
 //   bit  29     single-dressing sign (-1)^{popc(sJ & s)}
@@ -301,17 +301,30 @@ struct MixedArgs {
 // the alpha-beta doubles).  Coefficient tables with both signs pre-applied sit
 // in LDS, so one term is two LDS reads and one FMA.  Unused slots point at the
 // zero slot after the row.
+// static LDS of k_mixed in one object, coefficient table first: it sits at
+// LDS address 0, so the coefficient offsets packed in the entries are
+// absolute LDS addresses
+template <typename T>
+struct MixedLds {
+  // [(pid*2+O)*2 + sign], in the storage type: the FP32 path multiplies in
+  // FP32 with the coefficient rounded to FP32 either way
+  T fab[kMaxPairs * 4];
+  double srow[kMaxPairs * 4];  // [(pid*2+O)*2 + sign]
+  double dmix[kMaxOrb];
+  double bdress[kMaxOrb + 1];  // per stage; [kMaxOrb] = 0 for padded reads
+  int2 stage[64];              // per beta single: (source rank, pair | O << 16 | signs << 17)
+};
+
 template <typename T>
 __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* s_row = (T*)smem;  // [da + 1]: the staged row and a zero slot
-  // [(pid*2+O)*2 + sign], in the storage type: the FP32 path multiplies in
-  // FP32 with the coefficient rounded to FP32 either way
-  __shared__ T s_fab[kMaxPairs * 4];
-  __shared__ double s_srow[kMaxPairs * 4];  // [(pid*2+O)*2 + sign]
-  __shared__ double s_dmix[kMaxOrb];
-  __shared__ double s_bdress[kMaxOrb + 1];  // per stage; [kMaxOrb] = 0 for padded reads
-  __shared__ int2 s_stage[64];  // per beta single: (source rank, pair | O << 16 | signs << 17)
+  __shared__ MixedLds<T> L;
+  T* const s_fab = L.fab;
+  double* const s_srow = L.srow;
+  double* const s_dmix = L.dmix;
+  double* const s_bdress = L.bdress;
+  int2* const s_stage = L.stage;
 
   const int M = a.M;
   const uint32_t amask = (1u << M) - 1u;
@@ -352,9 +365,11 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   // packed excitation entries of this thread's alpha string; slots past the
   // string's excitations point at the zero slot s_row[da] (coefficient 0), so
   // the product loops run all 64 slots without predication
+  const uint32_t rbase = lds_addr(s_row);  // LDS address of the staged row (below 2^17 with it)
+  const uint32_t fbase = lds_addr(s_fab);  // 0: first static LDS object
   uint32_t ex[64];
 #pragma unroll
-  for (int x = 0; x < 64; ++x) ex[x] = (uint32_t)a.da * (uint32_t)sizeof(T);
+  for (int x = 0; x < 64; ++x) ex[x] = rbase + (uint32_t)a.da * (uint32_t)sizeof(T);
   int ns = 0;
   {
     const RankTables* R = a.arank;
@@ -376,7 +391,7 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
         // LDS byte offsets: the source amplitude (bits 0..16) and the
         // coefficient s_fab[(pair*2 + O)*2 + sab] (bits 17..28); bit 29 is
         // the sign of the singles' dressing
-        const uint32_t ent = (r2 * (uint32_t)sizeof(T)) |
+        const uint32_t ent = (rbase + r2 * (uint32_t)sizeof(T)) |
                              (((((uint32_t)pid * 2u + O) * 2u + sab) * (uint32_t)sizeof(T)) << 17) | (ssg << 29);
 #pragma unroll
         for (int x = 0; x < 64; ++x)
@@ -405,7 +420,7 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
     for (int x = 0; x < 64; ++x) {
       const uint32_t e = ex[x];
       const int fi = (int)(((((e >> 17) & 0xfffu) / (uint32_t)sizeof(T)) & ~1u) | ((e >> 29) & 1u));
-      acc += Acc<T>::prod(s_srow[fi], *(const T*)((const char*)s_row + (e & 0x1ffffu)));
+      acc += Acc<T>::prod(s_srow[fi], lds_load<T>(e & 0x1ffffu));
     }
     asm volatile("" : "+v"(acc));  // finish the products here, not after the table loop below
   }
@@ -432,15 +447,16 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
                             pb | ((i == q) ? 1 << 16 : 0) | (int)(sgn_s << 17) | (int)(sgn_ab << 18));
   }
   __syncthreads();
-  // LDS byte offsets of s_bdress entries of this thread's occupied orbitals,
+  // LDS addresses of s_bdress entries of this thread's occupied orbitals,
   // padded with the zero entry, for the per-stage dressing sum
   uint32_t occ_off[16];
   {
-    const uint32_t zero = (uint32_t)((const char*)&s_bdress[kMaxOrb] - (const char*)s_bdress);
+    const uint32_t dbase = lds_addr(s_bdress);
+    const uint32_t zero = lds_addr(&s_bdress[kMaxOrb]);
     uint32_t o = s;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      occ_off[j] = o ? (uint32_t)(__ffs(o) - 1) * 8u : zero;
+      occ_off[j] = o ? dbase + (uint32_t)(__ffs(o) - 1) * 8u : zero;
       o &= o - 1;
     }
   }
@@ -479,13 +495,12 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
     __syncthreads();
     double dr = 0.0;
     {
-      const char* bd = (const char*)s_bdress;
 #pragma unroll
       for (int g = 0; g < 2; ++g)
         if (g < occ_groups) {
           double v[8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = *(const double*)(bd + occ_off[g * 8 + j]);
+          for (int j = 0; j < 8; ++j) v[j] = lds_load<double>(occ_off[g * 8 + j]);
 #pragma unroll
           for (int j = 0; j < 8; ++j) dr += v[j];
         }
@@ -494,8 +509,7 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
 #pragma unroll
     for (int x = 0; x < 64; ++x) {
       const uint32_t e2 = ex[x];
-      sum += Acc<T>::prod(*(const T*)((const char*)s_fab + ((e2 >> 17) & 0xfffu)),
-                          *(const T*)((const char*)s_row + (e2 & 0x1ffffu)));
+      sum += Acc<T>::prod(lds_load<T>(fbase + ((e2 >> 17) & 0xfffu)), lds_load<T>(e2 & 0x1ffffu));
     }
     acc += sum;
     asm volatile("" : "+v"(acc));

@@ -191,6 +191,16 @@ __device__ inline void stage_row_lds(void* dst, const void* src, int nbytes, int
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// LDS byte address of a __shared__ object, and a load from such an address
+// (the address goes straight into the ds_read, no base arithmetic per access)
+__device__ inline uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char*)p;
+}
+template <typename T>
+__device__ inline T lds_load(uint32_t a) {
+  return *(const __attribute__((address_space(3))) T*)(uintptr_t)a;
+}
+
 // shared entry points between translation units
 Sector* sector_of(hyp_sector h);
 Ham* ham_of(hyp_ham h);

@@ -266,7 +266,11 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
   // unused excitation slots read the zero slot s_row[da]
   uint32_t ex[64];
   int ns = 0;
+  // absolute LDS addresses: base of the staged row plus the source offset
+  const uint32_t rbase = lds_addr(s_row);
   alpha_sources<T>(s, amask, a.arank, (uint32_t)a.da * (uint32_t)sizeof(T), ex, &ns);
+#pragma unroll
+  for (int x = 0; x < 64; ++x) ex[x] += rbase;
   double acc[64];
 #pragma unroll
   for (int x = 0; x < 64; ++x) acc[x] = 0.0;
@@ -296,13 +300,12 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
       // slot): a group is one basic block with eight LDS reads in flight,
       // then their eight products
       const double w = sb * (double)sv;
-      const char* rb = (const char*)s_row;
 #pragma unroll
       for (int g8 = 0; g8 < 8; ++g8) {
         if (g8 * 8 < a.nsx) {
           T v[8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = *(const T*)(rb + ex[g8 * 8 + j]);
+          for (int j = 0; j < 8; ++j) v[j] = lds_load<T>(ex[g8 * 8 + j]);
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
             if (sizeof(T) == 4)
