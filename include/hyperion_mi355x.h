@@ -115,6 +115,22 @@ hyp_status hyp_tune_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, voi
 hyp_status hyp_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* sigma_dev,
                        void* stream);
 
+/* Support skipping in hyp_apply_h (on = 1, the default; 0 = off).  The
+ * product is the sparse matrix times a sparse vector of "Sparse State-Vector
+ * Emulation": only amplitudes in the support of psi feed sigma.  With it on,
+ * each structured hyp_apply_h records which beta rows and alpha columns of psi
+ * hold a nonzero amplitude (while transposing psi), restricts the same-spin
+ * matrices to source rows in that support, drops mixed-pass source rows
+ * outside it, and reduces an output row with no source row in the support to
+ * its same-spin partials.  Results equal the dense evaluation up to summation
+ * order; near the Hartree-Fock state (early ADAPT iterations) the product
+ * costs a small fraction of the dense one; for a dense psi the extra work is
+ * a flag clear, two list compactions and the flag writes.  Device-side
+ * decisions only (no host synchronisation), so the product can be captured
+ * in a HIP graph either way.  Process-wide setting; HYP_ERR_ARG unless on is
+ * 0 or 1.  The generic kernel always evaluates densely. */
+hyp_status hyp_set_support_skip(int on);
+
 /* *out_dev = <a|b> = sum_i a_i b_i with FP64 accumulation (the sparse inner
  * product / expectation value of "General Framework for Variational
  * Algorithms", E = <psi|H psi>).  out_dev: one device double.  Scratch. */

@@ -193,6 +193,11 @@ def set_sweep_mode(mode: str = "auto"):
     check(_lib.load().hyp_set_sweep_mode({"auto": 0, "pairs": 1, "tdens": 2, "tdens_bins": 3}[mode]))
 
 
+def set_support_skip(on: bool = True):
+    """hyp_set_support_skip: restrict H psi to psi's row and column support."""
+    check(_lib.load().hyp_set_support_skip(1 if on else 0))
+
+
 def profile_enable(on: bool = True):
     check(_lib.load().hyp_profile_enable(1 if on else 0))
 

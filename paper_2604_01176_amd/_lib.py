@@ -74,6 +74,7 @@ SIGNATURES = {
     "hyp_pool_gradients": (_ci, [_vp, _ci, _vp, _i64, _vp, _vp, _vp, _vp]),
     "hyp_apply_excitation": (_ci, [_vp, _ci, HypExc, _d, _vp, _vp]),
     "hyp_set_sweep_mode": (_ci, [_ci]),
+    "hyp_set_support_skip": (_ci, [_ci]),
     "hyp_pool_gradients_batched": (_ci, [_vp, _ci, _vp, _vp]),
     "hyp_tune_pool_gradients": (_ci, [_vp, _ci, _ci, ctypes.POINTER(SweepTile), ctypes.POINTER(_d), _vp]),
     "hyp_mlp_create": (_ci, [_vp, _i64, ctypes.POINTER(_vp)]),
@@ -119,6 +120,12 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise ImportError(
                 f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded; loaded the other way round, torch finds no HIP device
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)

@@ -65,21 +65,66 @@ __device__ inline double flip(double v, uint32_t odd) {
 
 // ---------------------------------------------------------------- transpose
 
+// in[rows][cols] -> out[cols][rows], 64x64 tiles through LDS.  With row_nz
+// and col_nz (cleared beforehand) it also records the support of `in` at
+// row and column granularity: a wave that sees a nonzero amplitude of a row
+// (input phase) or of a column (output phase) sets that row's or column's
+// flag to 1.
 template <typename T>
-__global__ void k_transpose(const T* __restrict__ in, T* __restrict__ out, int rows, int cols) {
-  // in[rows][cols] -> out[cols][rows], 64x64 tiles through LDS
+__global__ void k_transpose(const T* __restrict__ in, T* __restrict__ out, int rows, int cols,
+                            uint32_t* __restrict__ row_nz, uint32_t* __restrict__ col_nz) {
   __shared__ T tile[64][65];
   int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
   int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 256 threads: 4 rows per pass
   for (int r = ty; r < 64; r += 4) {
     int rr = r0 + r, cc = c0 + tx;
-    if (rr < rows && cc < cols) tile[r][tx] = in[(int64_t)rr * cols + cc];
+    T v = T(0);
+    if (rr < rows && cc < cols) tile[r][tx] = v = in[(int64_t)rr * cols + cc];
+    if (row_nz && __ballot(v != T(0)) && tx == 0) row_nz[rr] = 1u;
   }
   __syncthreads();
   for (int c = ty; c < 64; c += 4) {
     int cc = c0 + c, rr = r0 + tx;
-    if (rr < rows && cc < cols) out[(int64_t)cc * rows + rr] = tile[tx][c];
+    T v = T(0);
+    if (rr < rows && cc < cols) out[(int64_t)cc * rows + rr] = v = tile[tx][c];
+    if (col_nz && __ballot(v != T(0)) && tx == 0) col_nz[cc] = 1u;
   }
+}
+
+__global__ void k_clear_u32(uint32_t* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// Support-restricted copy of a same-spin matrix: row r keeps, in order, the
+// entries whose source row has a nonzero flag; c_n[r] = their count.  One
+// wave per row.
+__global__ void __launch_bounds__(256) k_ss_compact(const int* __restrict__ rank, const double* __restrict__ coef,
+                                                    int nent, int nrow, const uint32_t* __restrict__ src_nz,
+                                                    int* __restrict__ c_rank, double* __restrict__ c_coef,
+                                                    int* __restrict__ c_n) {
+  const int row = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (row >= nrow) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t base = (int64_t)row * nent;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int n = 0;
+  for (int e0 = 0; e0 < nent; e0 += 64) {
+    const int e = e0 + lane;
+    int r = 0;
+    bool keep = false;
+    if (e < nent) {
+      r = rank[base + e];
+      keep = src_nz[r] != 0u;
+    }
+    const uint64_t m = __ballot(keep);
+    if (keep) {
+      const int64_t pos = base + n + __popcll(m & below);
+      c_rank[pos] = r;
+      c_coef[pos] = coef[base + e];
+    }
+    n += __popcll(m);
+  }
+  if (lane == 0) c_n[row] = n;
 }
 
 // ---------------------------------------------------------------- same-spin rows
@@ -223,6 +268,7 @@ struct SSApplyArgs {
   double* out;              // [nrow][ncol] FP64 partial
   const int* list_rank;
   const double* list_coef;
+  const int* list_n;        // per-row entry counts (support-restricted lists), or null: nent each
   int nent, nrow, ncol;
   int ntiles, nrb;          // 64-column tiles, 4-row blocks
 };
@@ -248,10 +294,11 @@ __global__ void __launch_bounds__(256) k_ss_apply(SSApplyArgs a) {
   const int* __restrict__ rk = a.list_rank + (int64_t)row * a.nent;
   const double* __restrict__ cf = a.list_coef + (int64_t)row * a.nent;
   const T* __restrict__ in = (const T*)a.in;
+  const int nent = a.list_n ? __builtin_amdgcn_readfirstlane(a.list_n[row]) : a.nent;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   int e = 0;
   // eight independent loads in flight per wave
-  for (; e + 8 <= a.nent; e += 8) {
+  for (; e + 8 <= nent; e += 8) {
     T v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -261,7 +308,7 @@ __global__ void __launch_bounds__(256) k_ss_apply(SSApplyArgs a) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u & 3] += Acc<T>::prod(cf[e + u], v[u]);
   }
-  for (; e < a.nent; ++e) {
+  for (; e < nent; ++e) {
     const int r = __builtin_amdgcn_readfirstlane(rk[e]);
     acc[0] += Acc<T>::prod(cf[e], in[(int64_t)r * a.ncol + colc]);
   }
@@ -282,6 +329,7 @@ struct MixedArgs {
   const RankTables* arank;
   const RankTables* brank;
   int nchunk;             // column chunks per beta row
+  const uint32_t* row_nz; // support flags of psi's beta rows, or null (every row taken)
   HamDev H;
 };
 
@@ -313,6 +361,8 @@ struct MixedLds {
   double dmix[kMaxOrb];
   double bdress[kMaxOrb + 1];  // per stage; [kMaxOrb] = 0 for padded reads
   int2 stage[64];              // per beta single: (source rank, pair | O << 16 | signs << 17)
+  int nstage;                  // stages kept (source rows in psi's support)
+  int own;                     // the workgroup's own beta row is in psi's support
 };
 
 template <typename T>
@@ -339,6 +389,53 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   const int col = chunk * nt + tid;
   const bool live = col < a.da;
   const uint32_t s = live ? a.astr[col] : a.astr[0];
+
+  // Beta-single source rows (stages).  Per stage: the source row's rank, the
+  // pair and orientation of the beta excitation and its two signs, tabulated
+  // once per workgroup so no dependent lookup precedes a stage's row loads.
+  // Rows outside psi's support contribute nothing and are dropped (wave 0,
+  // order kept); N_b (M - N_b) <= 64 stages.
+  const int nbemp = M - a.nb;
+  const int nbs = a.nb * nbemp;
+  if (tid < 64) {
+    const int jb = tid;
+    bool keep = false;
+    int2 ent = make_int2(0, 0);
+    if (jb < nbs) {
+      const int io = jb / nbemp, ie = jb % nbemp;
+      uint32_t occ = bs, emp = ~bs & amask;
+      for (int j = 0; j < io; ++j) occ &= occ - 1;
+      for (int j = 0; j < ie; ++j) emp &= emp - 1;
+      const int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
+      const int p = min(i, e), q = max(i, e);
+      const int pb = pair_id(p, q);
+      const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
+      const uint32_t jsb = H.sJ[kMaxPairs + pb] >> M;
+      const uint32_t sgn_s = __popc(jsb & bs) & 1u;
+      const uint32_t sgn_ab = __popc((H.abJb[pb] >> M) & bs) & 1u;
+      const int r2 = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
+      ent = make_int2(r2, pb | ((i == q) ? 1 << 16 : 0) | (int)(sgn_s << 17) | (int)(sgn_ab << 18));
+      keep = !a.row_nz || a.row_nz[r2] != 0u;
+    }
+    const uint64_t m = __ballot(keep);
+    const uint64_t below = (jb == 0) ? 0ull : (~0ull >> (64 - jb));
+    if (keep) s_stage[__popcll(m & below)] = ent;
+    if (jb == 0) {
+      L.nstage = __popcll(m);
+      L.own = (!a.row_nz || a.row_nz[brow] != 0u) ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  const int nst = L.nstage;
+  const bool own = L.own != 0;
+  if (nst == 0 && !own) {
+    // no source row in psi's support: only the same-spin partials remain
+    if (live) {
+      const double v = a.pb[(int64_t)brow * a.da + col] + a.pa_t[(int64_t)col * a.db + brow];
+      ((T*)a.sigma)[(int64_t)brow * a.da + col] = (T)v;
+    }
+    return;
+  }
 
   for (int k = tid; k < M; k += nt) {
     double v = 0.0;  // alpha orbital k against the occupied beta orbitals (diagonal)
@@ -402,12 +499,11 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   }
   const T* psi = (const T*)a.psi;
   if (tid == 0) s_row[a.da] = T(0);
-  stage_row_lds(s_row, psi + (int64_t)brow * a.da, a.da * (int)sizeof(T), tid, nt);
-  __syncthreads();
-
   double acc = 0.0;
   // (1) own row: alpha-beta diagonal and alpha singles' beta dressing
-  {
+  if (own) {
+    stage_row_lds(s_row, psi + (int64_t)brow * a.da, a.da * (int)sizeof(T), tid, nt);
+    __syncthreads();
     double v = 0.0;
     uint32_t o = s;
     while (o) {
@@ -425,28 +521,7 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
     asm volatile("" : "+v"(acc));  // finish the products here, not after the table loop below
   }
 
-  // (2) beta-single source rows.  Per stage jb: the source row's rank, the
-  // pair and orientation of the beta excitation and its two signs are
-  // tabulated once per workgroup, so no dependent lookup precedes a stage's
-  // row loads.
-  const int nbemp = M - a.nb;
-  const int nbs = a.nb * nbemp;
-  for (int jb = tid; jb < nbs; jb += nt) {
-    const int io = jb / nbemp, ie = jb % nbemp;
-    uint32_t occ = bs, emp = ~bs & amask;
-    for (int j = 0; j < io; ++j) occ &= occ - 1;
-    for (int j = 0; j < ie; ++j) emp &= emp - 1;
-    const int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
-    const int p = min(i, e), q = max(i, e);
-    const int pb = pair_id(p, q);
-    const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
-    const uint32_t jsb = H.sJ[kMaxPairs + pb] >> M;
-    const uint32_t sgn_s = __popc(jsb & bs) & 1u;
-    const uint32_t sgn_ab = __popc((H.abJb[pb] >> M) & bs) & 1u;
-    s_stage[jb] = make_int2(a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u],
-                            pb | ((i == q) ? 1 << 16 : 0) | (int)(sgn_s << 17) | (int)(sgn_ab << 18));
-  }
-  __syncthreads();
+  // (2) the kept beta-single source rows
   // LDS addresses of s_bdress entries of this thread's occupied orbitals,
   // padded with the zero entry, for the per-stage dressing sum
   uint32_t occ_off[16];
@@ -462,7 +537,7 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   }
   if (tid == 0) s_bdress[kMaxOrb] = 0.0;
   const int occ_groups = (__popc(s) + 7) >> 3;  // same for every thread
-  for (int jb = 0; jb < nbs; ++jb) {
+  for (int jb = 0; jb < nst; ++jb) {
     // the entries are opaque to the optimiser here: otherwise it hoists the
     // 128 addresses derived from them out of the loop and spills
 #pragma unroll
@@ -575,7 +650,18 @@ struct HamWork {
   int* b_rank = nullptr;
   double* b_coef = nullptr;
   int b_nent = 0;
+  // support skipping: row flags of psi ([db] beta rows, then [da] alpha
+  // columns) and the support-restricted copies of the same-spin matrices
+  uint32_t* nz = nullptr;
+  int* ca_rank = nullptr;
+  double* ca_coef = nullptr;
+  int* ca_n = nullptr;
+  int* cb_rank = nullptr;
+  double* cb_coef = nullptr;
+  int* cb_n = nullptr;
 };
+
+static int g_support_skip = 1;  // process-wide: restrict H psi to psi's row and column support
 
 static int same_spin_entries(int M, int N) {
   const int s = N * (M - N);
@@ -592,6 +678,12 @@ static hyp_status build_same_spin(Ham* Hm, HamWork* W, hipStream_t st) {
   HYP_HIP(hipMalloc(&W->a_coef, sizeof(double) * S->da * W->a_nent));
   HYP_HIP(hipMalloc(&W->b_rank, sizeof(int) * S->db * W->b_nent));
   HYP_HIP(hipMalloc(&W->b_coef, sizeof(double) * S->db * W->b_nent));
+  HYP_HIP(hipMalloc(&W->ca_rank, sizeof(int) * S->da * W->a_nent));
+  HYP_HIP(hipMalloc(&W->ca_coef, sizeof(double) * S->da * W->a_nent));
+  HYP_HIP(hipMalloc(&W->ca_n, sizeof(int) * S->da));
+  HYP_HIP(hipMalloc(&W->cb_rank, sizeof(int) * S->db * W->b_nent));
+  HYP_HIP(hipMalloc(&W->cb_coef, sizeof(double) * S->db * W->b_nent));
+  HYP_HIP(hipMalloc(&W->cb_n, sizeof(int) * S->db));
   SameSpinArgs sa;
   sa.H = Hm->dev;
   sa.M = S->M;
@@ -633,15 +725,32 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
                                  hipStream_t st) {
   Sector* S = Hm->sec;
   const int da = (int)S->da, db = (int)S->db;
-  // psi^T for the alpha-row pass
+  const bool skip = g_support_skip != 0;
+  uint32_t* nz_b = skip ? W->nz : nullptr;       // beta rows of psi
+  uint32_t* nz_a = skip ? W->nz + db : nullptr;  // alpha columns of psi (rows of psi^T)
+  if (skip) {
+    const int n = da + db;
+    HYP_LAUNCH("k_clear_u32", k_clear_u32, dim3((unsigned)std::min(1024, (n + 255) / 256)), dim3(256), 0, st,
+               W->nz, n);
+  }
+  // psi^T for the alpha-row pass, and psi's row and column support
   dim3 tg((da + 63) / 64, (db + 63) / 64);
-  HYP_LAUNCH("k_transpose", k_transpose<T>, tg, dim3(256), 0, st, (const T*)psi, (T*)W->psi_t, db, da);
+  HYP_LAUNCH("k_transpose", k_transpose<T>, tg, dim3(256), 0, st, (const T*)psi, (T*)W->psi_t, db, da, nz_b,
+             nz_a);
+  if (skip) {
+    // same-spin matrices restricted to source rows in the support
+    HYP_LAUNCH("k_ss_compact", k_ss_compact, dim3((unsigned)((da + 3) / 4)), dim3(256), 0, st, W->a_rank,
+               W->a_coef, W->a_nent, da, nz_a, W->ca_rank, W->ca_coef, W->ca_n);
+    HYP_LAUNCH("k_ss_compact", k_ss_compact, dim3((unsigned)((db + 3) / 4)), dim3(256), 0, st, W->b_rank,
+               W->b_coef, W->b_nent, db, nz_b, W->cb_rank, W->cb_coef, W->cb_n);
+  }
   // alpha rows (over psi^T): rows = alpha strings, columns = beta strings
   SSApplyArgs sa;
   sa.in = W->psi_t;
   sa.out = W->part_a;
-  sa.list_rank = W->a_rank;
-  sa.list_coef = W->a_coef;
+  sa.list_rank = skip ? W->ca_rank : W->a_rank;
+  sa.list_coef = skip ? W->ca_coef : W->a_coef;
+  sa.list_n = skip ? W->ca_n : nullptr;
   sa.nent = W->a_nent;
   sa.nrow = da;
   sa.ncol = db;
@@ -652,8 +761,9 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   // beta rows (over psi), the constant (identity) term folded into their diagonal
   sa.in = psi;
   sa.out = W->part_b;
-  sa.list_rank = W->b_rank;
-  sa.list_coef = W->b_coef;
+  sa.list_rank = skip ? W->cb_rank : W->b_rank;
+  sa.list_coef = skip ? W->cb_coef : W->b_coef;
+  sa.list_n = skip ? W->cb_n : nullptr;
   sa.nent = W->b_nent;
   sa.nrow = db;
   sa.ncol = da;
@@ -676,6 +786,7 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   ma.arank = S->d_arank;
   ma.brank = S->d_brank;
   ma.H = Hm->dev;
+  ma.row_nz = nz_b;
   const int nt = Hm->threads[sizeof(T) == 4 ? 1 : 0];
   ma.nchunk = (da + nt - 1) / nt;
   // the row plus one zero slot (index da) that padded excitation entries read
@@ -1018,6 +1129,7 @@ hyp_status hyp_build_hamiltonian(hyp_sector sh, const uint32_t* x_mask, const ui
     e = hipMalloc(&hh->w.psi_t, (size_t)S->dim * 8);
     if (e == hipSuccess) e = hipMalloc(&hh->w.part_a, (size_t)S->dim * 8);
     if (e == hipSuccess) e = hipMalloc(&hh->w.part_b, (size_t)S->dim * 8);
+    if (e == hipSuccess) e = hipMalloc(&hh->w.nz, sizeof(uint32_t) * (size_t)(S->da + S->db));
     if (e != hipSuccess) return cleanup_fail(e, "hyp_build_hamiltonian: workspace");
     hyp_status rb = build_same_spin(&H, &hh->w, st);
     if (rb != HYP_OK) {
@@ -1047,6 +1159,13 @@ hyp_status hyp_ham_destroy(hyp_ham hh) {
   (void)hipFree(hh->w.a_coef);
   (void)hipFree(hh->w.b_rank);
   (void)hipFree(hh->w.b_coef);
+  (void)hipFree(hh->w.nz);
+  (void)hipFree(hh->w.ca_rank);
+  (void)hipFree(hh->w.ca_coef);
+  (void)hipFree(hh->w.ca_n);
+  (void)hipFree(hh->w.cb_rank);
+  (void)hipFree(hh->w.cb_coef);
+  (void)hipFree(hh->w.cb_n);
   delete hh;
   return HYP_OK;
 }
@@ -1099,6 +1218,12 @@ hyp_status hyp_tune_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* 
   if (r != HYP_OK) return r;
   *best_threads = bt;
   *best_ms = bms;
+  return HYP_OK;
+}
+
+hyp_status hyp_set_support_skip(int on) {
+  if (on != 0 && on != 1) return fail(HYP_ERR_ARG, "hyp_set_support_skip: on must be 0 or 1");
+  g_support_skip = on;
   return HYP_OK;
 }
 
