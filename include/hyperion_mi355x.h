@@ -115,20 +115,28 @@ hyp_status hyp_tune_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, voi
 hyp_status hyp_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* sigma_dev,
                        void* stream);
 
-/* Support skipping in hyp_apply_h (on = 1, the default; 0 = off).  The
- * product is the sparse matrix times a sparse vector of "Sparse State-Vector
- * Emulation": only amplitudes in the support of psi feed sigma.  With it on,
- * each structured hyp_apply_h records which beta rows and alpha columns of psi
- * hold a nonzero amplitude (while transposing psi), restricts the same-spin
- * matrices to source rows in that support, drops mixed-pass source rows
- * outside it, and reduces an output row with no source row in the support to
- * its same-spin partials.  Results equal the dense evaluation up to summation
- * order; near the Hartree-Fock state (early ADAPT iterations) the product
- * costs a small fraction of the dense one; for a dense psi the extra work is
- * a flag clear, two list compactions and the flag writes.  Device-side
- * decisions only (no host synchronisation), so the product can be captured
- * in a HIP graph either way.  Process-wide setting; HYP_ERR_ARG unless on is
- * 0 or 1.  The generic kernel always evaluates densely. */
+/* Support skipping in hyp_apply_h and in the transition-value sweep of
+ * hyp_pool_gradients (on = 1, the default; 0 = off).  The product is the
+ * sparse matrix times a sparse vector of "Sparse State-Vector Emulation":
+ * only amplitudes in the support of psi feed sigma, and only they enter the
+ * gradients (T(tau) = sum_D s sigma[tau D] psi[D]).
+ * hyp_apply_h (structured kernel): records which beta rows and alpha columns
+ * of psi hold a nonzero amplitude (while transposing psi), restricts the
+ * same-spin matrices to source rows in that support, drops mixed-pass source
+ * rows outside it, and reduces an output row with no source row in the
+ * support to its same-spin partials.  Device-side decisions only (no host
+ * synchronisation), so the product can be captured in a HIP graph either
+ * way.  The generic kernel always evaluates densely.
+ * hyp_pool_gradients (modes 0 and 2): the row pairs and identity slices of
+ * the transition values keep only source rows in psi's support; a Gram sum
+ * over at most half of its range (beta rows for G_a, alpha columns for G_b)
+ * runs on gathered rows or columns.  The call then waits on the host for the
+ * support scan of psi (two counts), not for the kernels queued after it.
+ * Results equal the dense evaluation up to summation order.  Near the
+ * Hartree-Fock state (early ADAPT iterations) both cost a small fraction of
+ * the dense ones; for a dense psi the extra work is a support scan, list
+ * compactions and flag writes.  Process-wide setting; HYP_ERR_ARG unless on
+ * is 0 or 1. */
 hyp_status hyp_set_support_skip(int on);
 
 /* *out_dev = <a|b> = sum_i a_i b_i with FP64 accumulation (the sparse inner

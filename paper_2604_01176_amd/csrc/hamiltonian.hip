@@ -1238,6 +1238,7 @@ hyp_status hyp_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* sigma
 
 namespace hyp {
 Ham* ham_of(hyp_ham h) { return h ? &h->h : nullptr; }
+bool support_skip() { return g_support_skip != 0; }
 
 hyp_status apply_h_internal(hyp_ham hh, hyp_dtype dtype, const void* psi, void* sigma,
                             hipStream_t st) {

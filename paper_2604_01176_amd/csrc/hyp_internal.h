@@ -210,6 +210,8 @@ hyp_status pair_scratch(Sector* S, size_t n_doubles, double** out);
 hyp_status apply_h_internal(hyp_ham h, hyp_dtype dt, const void* psi, void* sigma, hipStream_t st);
 // true when hyp_pool_gradients takes the transition-value sweep for this list
 bool prefer_full_sweep(const Sector* S, int64_t n_ops);
+// process-wide support-skipping switch (hyp_set_support_skip)
+bool support_skip();
 hyp_status launch_pool_gradients(Sector* S, hyp_dtype dt, const hyp_exc* ops_dev, int64_t n_ops,
                                  const void* psi, const void* sig, double* grad, hipStream_t st);
 hyp_status launch_rotate(Sector* S, hyp_dtype dt, hyp_exc op, double theta,

@@ -190,6 +190,12 @@ struct TRArgs {
   int nsx;            // alpha single excitations of every string, N_a (M - N_a)
   int n_eb, n_id, nchunk;
   double* part;       // [n_eb + n_id][nchunk][kStageW]
+  // support skipping (null: every row): row pairs kept per beta excitation
+  // (rows then holds the kept pairs first, in order), and the ordered list
+  // of psi's nonzero rows with its length, split over the identity slices
+  const int* rcount;
+  const int* idrows;
+  const int* n_idrows;
 };
 
 // LDS byte offsets (source rank * element size) of a string's alpha single
@@ -277,16 +283,25 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
   double acc_id = 0.0;
   const bool ident = slot >= a.n_eb;
   const int row0 = ident ? (slot - a.n_eb) * a.Kid : 0;
-  const int nrows = ident ? min(a.Kid, a.db - row0) : a.K;
+  int nrows;
+  if (ident)
+    nrows = a.idrows ? max(0, min(a.Kid, *a.n_idrows - row0)) : min(a.Kid, a.db - row0);
+  else
+    nrows = a.rcount ? a.rcount[slot] : a.K;
   const T* psi = (const T*)a.psi;
   const T* sig = (const T*)a.sig;
   if (tid == 0) s_row[a.da] = T(0);
   const int2* rl = a.rows + (int64_t)(ident ? 0 : slot) * a.K;
+  auto pair_at = [&](int k) -> int2 {
+    if (!ident) return rl[k];
+    const int r = a.idrows ? a.idrows[row0 + k] : row0 + k;
+    return make_int2(r, r);
+  };
   // the row pair of the next iteration is read one iteration ahead, so its
   // latency is off the path to the staging loads
-  int2 cur = ident ? make_int2(row0, row0) : (nrows > 0 ? rl[0] : make_int2(0, 0));
+  int2 cur = nrows > 0 ? pair_at(0) : make_int2(0, 0);
   for (int k = 0; k < nrows; ++k) {
-    const int2 nxt = (k + 1 < nrows) ? (ident ? make_int2(row0 + k + 1, row0 + k + 1) : rl[k + 1]) : cur;
+    const int2 nxt = (k + 1 < nrows) ? pair_at(k + 1) : cur;
     const int src = cur.x, tgt = cur.y & 0x7fffffff;
     const double sb = cur.y < 0 ? -1.0 : 1.0;
     __syncthreads();
@@ -613,6 +628,116 @@ __global__ void k_gram_grad(const hyp_exc* ops, int M, int na, int nb, const dou
   if (threadIdx.x == 0) grad[k] = 2.0 * (red[0] + red[1] + red[2] + red[3]);
 }
 
+// ---------------------------------------------------------------- support
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// Row and column support of m[rows][cols] (flags cleared beforehand): 64x64
+// tiles, a wave per row of the tile (ballot), each lane keeps its column's
+// flag over the tile's rows.
+template <typename T>
+__global__ void __launch_bounds__(256) k_support(const T* __restrict__ m, int rows, int cols,
+                                                 uint32_t* __restrict__ row_nz, uint32_t* __restrict__ col_nz) {
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int cc = c0 + tx;
+  bool cany = false;
+  for (int r = ty; r < 64; r += 4) {
+    const int rr = r0 + r;
+    bool nz = false;
+    if (rr < rows && cc < cols) nz = m[(int64_t)rr * cols + cc] != T(0);
+    cany |= nz;
+    if (__ballot(nz) && tx == 0) row_nz[rr] = 1u;
+  }
+  if (cany) col_nz[cc] = 1u;
+}
+
+// Ordered list of the indices i < n with flag[i] != 0, and its length: one
+// workgroup of 1024 threads, 1024 flags per round.
+__global__ void __launch_bounds__(1024) k_list_nz(const uint32_t* __restrict__ flag, int n, int* __restrict__ list,
+                                                  int* __restrict__ count) {
+  __shared__ int s_wc[16];
+  __shared__ int s_base;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < n; b0 += 1024) {
+    const int i = b0 + tid;
+    const bool f = i < n && flag[i] != 0u;
+    const uint64_t m = __ballot(f);
+    if (lane == 0) s_wc[w] = __popcll(m);
+    __syncthreads();
+    int off = s_base;
+    for (int j = 0; j < w; ++j) off += s_wc[j];
+    if (f) list[off + __popcll(m & below)] = i;
+    __syncthreads();
+    if (tid == 0) {
+      int t = 0;
+      for (int j = 0; j < 16; ++j) t += s_wc[j];
+      s_base += t;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *count = s_base;
+}
+
+// Row pairs of each beta excitation whose source row is in psi's support,
+// in order, at the front of the excitation's K slots; rcount[eb] their
+// number.  One wave per beta excitation.
+__global__ void __launch_bounds__(256) k_rows_compact(const int2* __restrict__ rows, int n_eb, int K,
+                                                      const uint32_t* __restrict__ row_nz,
+                                                      int2* __restrict__ crows, int* __restrict__ rcount) {
+  const int eb = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (eb >= n_eb) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t base = (int64_t)eb * K;
+  int n = 0;
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    const int k = k0 + lane;
+    int2 rp = make_int2(0, 0);
+    bool keep = false;
+    if (k < K) {
+      rp = rows[base + k];
+      keep = row_nz[rp.x] != 0u;
+    }
+    const uint64_t m = __ballot(keep);
+    if (keep) crows[base + n + __popcll(m & below)] = rp;
+    n += __popcll(m);
+  }
+  if (lane == 0) rcount[eb] = n;
+}
+
+// dst[i][c] = src[list[i]][c] (whole rows, widened to FP64)
+template <typename T>
+__global__ void k_gather_rows(const T* __restrict__ src, const int* __restrict__ list, int n, int cols,
+                              double* __restrict__ dst) {
+  const int64_t tot = (int64_t)n * cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols, c = i - r * cols;
+    dst[i] = (double)src[(int64_t)list[r] * cols + c];
+  }
+}
+
+// dst[r][j] = src[r][list[j]] (selected columns of every row, widened)
+template <typename T>
+__global__ void k_gather_cols(const T* __restrict__ src, const int* __restrict__ list, int n, int rows, int cols,
+                              double* __restrict__ dst) {
+  const int64_t tot = (int64_t)rows * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / n, j = i - r * n;
+    dst[i] = (double)src[r * cols + list[j]];
+  }
+}
+
+__global__ void k_zero_f64(double* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
 __global__ void k_widen(const float* a, int64_t n, double* b) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = (double)a[i];
@@ -633,6 +758,18 @@ struct TScratch {
   size_t rows_cap = 0;
   double* rpart = nullptr; // partials of the row-batched kernel
   size_t rpart_cap = 0;
+  hipEvent_t cnt_ready = nullptr;
+  // support skipping: flags and ordered lists of psi's nonzero beta rows
+  // and alpha columns, their two lengths (device and pinned host), and the
+  // kept row pairs of each beta excitation
+  uint32_t* nz = nullptr;
+  int* lists = nullptr;
+  size_t nz_cap = 0;
+  int* cnt = nullptr;
+  int* hcnt = nullptr;
+  int2* crows = nullptr;
+  int* rcount = nullptr;
+  size_t crows_cap = 0;
 };
 TScratch g_ts[64];
 }  // namespace
@@ -656,7 +793,7 @@ static int64_t binom64(int m, int k) {
 // Transition values of singles and alpha-beta doubles (Ta, Tb, Tab) by the
 // row-batched kernel.
 static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* psi, const void* sig,
-                             double* Ta, double* Tb, double* Tab, hipStream_t st) {
+                             double* Ta, double* Tb, double* Tab, bool skip, hipStream_t st) {
   TRArgs a;
   a.psi = psi;
   a.sig = sig;
@@ -688,6 +825,32 @@ static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* 
     ts.rows_nb = S->nb;
   }
   a.rows = ts.rows;
+  a.rcount = nullptr;
+  a.idrows = nullptr;
+  a.n_idrows = nullptr;
+  if (skip) {
+    // row pairs whose source row is in psi's support (flags ts.nz, beta rows
+    // first), and the identity slices over the ordered list of those rows
+    if (rows_need > ts.crows_cap) {
+      HYP_HIP(hipDeviceSynchronize());
+      if (ts.crows) HYP_HIP(hipFree(ts.crows));
+      if (ts.rcount) HYP_HIP(hipFree(ts.rcount));
+      ts.crows = nullptr;
+      ts.rcount = nullptr;
+      ts.crows_cap = 0;
+      HYP_HIP(hipMalloc(&ts.crows, rows_need * sizeof(int2)));
+      HYP_HIP(hipMalloc(&ts.rcount, (size_t)a.n_eb * sizeof(int)));
+      ts.crows_cap = rows_need;
+    }
+    if (rows_need > 0) {
+      HYP_LAUNCH("k_rows_compact", k_rows_compact, dim3((unsigned)((a.n_eb + 3) / 4)), dim3(256), 0, st, ts.rows,
+                 a.n_eb, a.K, ts.nz, ts.crows, ts.rcount);
+      a.rows = ts.crows;
+      a.rcount = ts.rcount;
+    }
+    a.idrows = ts.lists;
+    a.n_idrows = ts.cnt;
+  }
   const size_t pneed = (size_t)(a.n_eb + a.n_id) * a.nchunk * kStageW;
   if (pneed > ts.rpart_cap) {
     HYP_HIP(hipDeviceSynchronize());
@@ -744,8 +907,45 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
   double* Ta = ts.T;
   double* Tb = ts.T + kBins;
   double* Tab = ts.T + 2 * kBins;
+  const int64_t da = S->da, db = S->db;
+  // support skipping: only amplitudes in psi's support enter T(tau) = sum_D
+  // s sigma[tau D] psi[D], so the row pairs and Gram sums are restricted to
+  // psi's nonzero beta rows and alpha columns
+  const bool skip = support_skip() && !bins;
+  if (skip) {
+    const size_t nneed = (size_t)(da + db);
+    if (nneed > ts.nz_cap) {
+      HYP_HIP(hipDeviceSynchronize());
+      if (ts.nz) HYP_HIP(hipFree(ts.nz));
+      if (ts.lists) HYP_HIP(hipFree(ts.lists));
+      ts.nz = nullptr;
+      ts.lists = nullptr;
+      ts.nz_cap = 0;
+      HYP_HIP(hipMalloc(&ts.nz, nneed * sizeof(uint32_t)));
+      HYP_HIP(hipMalloc(&ts.lists, nneed * sizeof(int)));
+      ts.nz_cap = nneed;
+    }
+    if (!ts.cnt) {
+      HYP_HIP(hipMalloc(&ts.cnt, 2 * sizeof(int)));
+      HYP_HIP(hipHostMalloc((void**)&ts.hcnt, 2 * sizeof(int), hipHostMallocDefault));
+      HYP_HIP(hipEventCreateWithFlags(&ts.cnt_ready, hipEventDisableTiming));
+    }
+    HYP_LAUNCH("k_zero_u32", k_zero_u32, dim3((unsigned)std::min<int64_t>(1024, (da + db + 255) / 256)), dim3(256),
+               0, st, ts.nz, (int)(da + db));
+    dim3 tg((unsigned)((da + 63) / 64), (unsigned)((db + 63) / 64));
+    if (dt == HYP_F64)
+      HYP_LAUNCH("k_support", k_support<double>, tg, dim3(256), 0, st, (const double*)psi, (int)db, (int)da, ts.nz,
+                 ts.nz + db);
+    else
+      HYP_LAUNCH("k_support", k_support<float>, tg, dim3(256), 0, st, (const float*)psi, (int)db, (int)da, ts.nz,
+                 ts.nz + db);
+    HYP_LAUNCH("k_list_nz", k_list_nz, dim3(1), dim3(1024), 0, st, ts.nz, (int)db, ts.lists, ts.cnt);
+    HYP_LAUNCH("k_list_nz", k_list_nz, dim3(1), dim3(1024), 0, st, ts.nz + db, (int)da, ts.lists + db, ts.cnt + 1);
+    HYP_HIP(hipMemcpyAsync(ts.hcnt, ts.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HYP_HIP(hipEventRecord(ts.cnt_ready, st));
+  }
   if (!bins) {
-    hyp_status r = tdens_rows(S, dt, ts, psi, sig, Ta, Tb, Tab, st);
+    hyp_status r = tdens_rows(S, dt, ts, psi, sig, Ta, Tb, Tab, skip, st);
     if (r != HYP_OK) return r;
   } else {
   const size_t need = tdens_bytes(S);
@@ -791,8 +991,7 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
              red_ab, red_a, Ta, Tb, Tab);
   }
   // same-spin doubles: Gram matrices on the matrix cores, then the gather
-  const int64_t da = S->da, db = S->db;
-  const size_t gneed = (size_t)(da * da + db * db) + (dt == HYP_F32 ? 2 * (size_t)S->dim : 0);
+  const size_t gneed = (size_t)(da * da + db * db) + ((dt == HYP_F32 || skip) ? 2 * (size_t)S->dim : 0);
   if (gneed > ts.gram_cap) {
     HYP_HIP(hipDeviceSynchronize());
     if (ts.gram) HYP_HIP(hipFree(ts.gram));
@@ -805,34 +1004,116 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
     return fail(HYP_ERR_HIP, "rocblas_create_handle failed");
   double* Ga = ts.gram;
   double* Gb = Ga + da * da;
-  const double* X = (const double*)psi;
-  const double* Y = (const double*)sig;
-  if (dt == HYP_F32) {
-    double* xw = Gb + db * db;
-    double* yw = xw + S->dim;
-    HYP_LAUNCH("k_widen", k_widen, dim3(4096), dim3(256), 0, st, (const float*)psi, S->dim, xw);
-    HYP_LAUNCH("k_widen", k_widen, dim3(4096), dim3(256), 0, st, (const float*)sig, S->dim, yw);
-    X = xw;
-    Y = yw;
+  double* work = Gb + db * db;  // 2 dim doubles: widened or gathered operands
+  // support sizes (the host waits for the support scan only, not for the
+  // transition-value kernel queued after it); a Gram sum over at most half
+  // of its range takes gathered operands
+  int64_t nR = db, nC = da;
+  if (skip) {
+    HYP_HIP(hipEventSynchronize(ts.cnt_ready));
+    nR = ts.hcnt[0];
+    nC = ts.hcnt[1];
   }
+  const bool gat_a = skip && 2 * nR <= db, gat_b = skip && 2 * nC <= da;
+  bool widened = false;
+  auto dense_ops = [&](const double** X, const double** Y) -> hyp_status {
+    if (dt == HYP_F64) {
+      *X = (const double*)psi;
+      *Y = (const double*)sig;
+      return HYP_OK;
+    }
+    if (!widened) {
+      HYP_LAUNCH("k_widen", k_widen, dim3(4096), dim3(256), 0, st, (const float*)psi, S->dim, work);
+      HYP_LAUNCH("k_widen", k_widen, dim3(4096), dim3(256), 0, st, (const float*)sig, S->dim, work + S->dim);
+      widened = true;
+    }
+    *X = work;
+    *Y = work + S->dim;
+    return HYP_OK;
+  };
   if (rocblas_set_stream(ts.blas, st) != rocblas_status_success)
     return fail(HYP_ERR_HIP, "rocblas_set_stream failed");
   const double one = 1.0, zero = 0.0;
   // column-major view: sigma, psi are D_a x D_b with leading dimension D_a
-  // G_a = Y X^T (D_a x D_a), G_b = Y^T X (D_b x D_b)
-  rocblas_status bs;
+  // G_a = Y X^T (D_a x D_a, sum over beta rows), G_b = Y^T X (D_b x D_b, sum
+  // over alpha columns)
+  rocblas_status bs = rocblas_status_success;
   {
+    const double *X, *Y;
+    int64_t K = db;
+    if (gat_a) {
+      // the support's beta rows of psi and sigma, gathered (and widened)
+      widened = false;
+      double* xr = work;
+      double* yr = work + nR * da;
+      const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (nR * da + 255) / 256));
+      if (nR > 0) {
+        if (dt == HYP_F64) {
+          HYP_LAUNCH("k_gather_rows", k_gather_rows<double>, dim3(g), dim3(256), 0, st, (const double*)psi,
+                     ts.lists, (int)nR, (int)da, xr);
+          HYP_LAUNCH("k_gather_rows", k_gather_rows<double>, dim3(g), dim3(256), 0, st, (const double*)sig,
+                     ts.lists, (int)nR, (int)da, yr);
+        } else {
+          HYP_LAUNCH("k_gather_rows", k_gather_rows<float>, dim3(g), dim3(256), 0, st, (const float*)psi, ts.lists,
+                     (int)nR, (int)da, xr);
+          HYP_LAUNCH("k_gather_rows", k_gather_rows<float>, dim3(g), dim3(256), 0, st, (const float*)sig, ts.lists,
+                     (int)nR, (int)da, yr);
+        }
+      }
+      X = xr;
+      Y = yr;
+      K = nR;
+    } else {
+      hyp_status r = dense_ops(&X, &Y);
+      if (r != HYP_OK) return r;
+    }
     ProfScope ps_("rocblas_dgemm_gram_a", st);
-    bs = rocblas_dgemm(ts.blas, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)da,
-                       (rocblas_int)da, (rocblas_int)db, &one, Y, (rocblas_int)da, X, (rocblas_int)da, &zero,
-                       Ga, (rocblas_int)da);
+    if (K == 0)
+      HYP_LAUNCH("k_zero_f64", k_zero_f64, dim3(4096), dim3(256), 0, st, Ga, da * da);
+    else
+      bs = rocblas_dgemm(ts.blas, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)da,
+                         (rocblas_int)da, (rocblas_int)K, &one, Y, (rocblas_int)da, X, (rocblas_int)da, &zero, Ga,
+                         (rocblas_int)da);
   }
   if (bs != rocblas_status_success) return fail(HYP_ERR_HIP, "rocblas_dgemm (alpha Gram) failed");
   {
+    const double *X, *Y;
+    int64_t K = da, ld = da;
+    if (gat_b) {
+      // the support's alpha columns of every row, gathered (and widened):
+      // column-major nC x D_b
+      widened = false;
+      double* xc = work;
+      double* yc = work + nC * db;
+      const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (nC * db + 255) / 256));
+      if (nC > 0) {
+        if (dt == HYP_F64) {
+          HYP_LAUNCH("k_gather_cols", k_gather_cols<double>, dim3(g), dim3(256), 0, st, (const double*)psi,
+                     ts.lists + db, (int)nC, (int)db, (int)da, xc);
+          HYP_LAUNCH("k_gather_cols", k_gather_cols<double>, dim3(g), dim3(256), 0, st, (const double*)sig,
+                     ts.lists + db, (int)nC, (int)db, (int)da, yc);
+        } else {
+          HYP_LAUNCH("k_gather_cols", k_gather_cols<float>, dim3(g), dim3(256), 0, st, (const float*)psi,
+                     ts.lists + db, (int)nC, (int)db, (int)da, xc);
+          HYP_LAUNCH("k_gather_cols", k_gather_cols<float>, dim3(g), dim3(256), 0, st, (const float*)sig,
+                     ts.lists + db, (int)nC, (int)db, (int)da, yc);
+        }
+      }
+      X = xc;
+      Y = yc;
+      K = nC;
+      ld = std::max<int64_t>(1, nC);
+    } else {
+      hyp_status r = dense_ops(&X, &Y);
+      if (r != HYP_OK) return r;
+    }
     ProfScope ps_("rocblas_dgemm_gram_b", st);
-    bs = rocblas_dgemm(ts.blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)db,
-                       (rocblas_int)db, (rocblas_int)da, &one, Y, (rocblas_int)da, X, (rocblas_int)da, &zero,
-                       Gb, (rocblas_int)db);
+    if (K == 0)
+      HYP_LAUNCH("k_zero_f64", k_zero_f64, dim3(4096), dim3(256), 0, st, Gb, db * db);
+    else
+      bs = rocblas_dgemm(ts.blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)db,
+                         (rocblas_int)db, (rocblas_int)K, &one, Y, (rocblas_int)ld, X, (rocblas_int)ld, &zero, Gb,
+                         (rocblas_int)db);
   }
   if (bs != rocblas_status_success) return fail(HYP_ERR_HIP, "rocblas_dgemm (beta Gram) failed");
   HYP_LAUNCH("k_gram_grad", k_gram_grad, dim3((unsigned)n_ops), dim3(256), 0, st, ops, S->M, S->na, S->nb, Ga, da,

@@ -164,3 +164,89 @@ def test_support_skip_32q_near_hartree_fock(hyp):
     assert np.linalg.norm(outs[True] - ref) <= 1e-12 * nref
     assert np.linalg.norm(outs[False] - ref) <= 1e-12 * nref
     assert times[True] < times[False]
+
+
+# ------------------------------------------------------------- gradient sweep
+
+GCASES = [(4, 2, 2), (5, 2, 3), (6, 3, 3), (8, 4, 4), (9, 5, 4), (3, 0, 2), (4, 4, 1), (7, 3, 2), (10, 4, 5),
+          (2, 1, 1)]
+
+
+@pytest.mark.parametrize("M,na,nb", GCASES)
+def test_sweep_support_skip(hyp, M, na, nb):
+    """Transition-value sweep restricted to psi's support (row pairs, identity
+    slices and both Gram sums) against the oracle, FP64 and FP32, and against
+    the unrestricted sweep."""
+    h, g = synth.integrals(M, 300 + M)
+    x, z, c = synth.jw_pauli_list(h, g)
+    S = hyp.Sector(M, na, nb)
+    cre, ann, _ = synth.canonical_pool(M)
+    ops = hyp.exc_tensor(cre, ann)
+    try:
+        hyp.set_sweep_mode("tdens")
+        for name, psi in _states(M, na, nb, S.da, S.db).items():
+            sig = oracle.apply_h(M, na, nb, x, z, c, psi)
+            ref = oracle.pool_gradients(M, na, nb, cre, ann, psi, sig)
+            got = {}
+            for on in (True, False):
+                hyp.set_support_skip(on)
+                got[on] = (hyp.hyp_pool_gradients(S, ops, _dev(psi), _dev(sig)).cpu().numpy(),
+                           hyp.hyp_pool_gradients(S, ops, _dev(psi, torch.float32),
+                                                  _dev(sig, torch.float32)).cpu().numpy())
+            hyp.set_support_skip(True)
+            if name == "zero":
+                assert all(np.all(v == 0.0) for pair in got.values() for v in pair), name
+                continue
+            scale = max(1.0, np.abs(ref).max())
+            for on, (g64, g32) in got.items():
+                assert np.abs(g64 - ref).max() <= 1e-12 * scale, (name, on)
+                assert np.abs(g32 - ref).max() <= 1e-5 * scale, (name, on)
+            assert np.abs(got[True][0] - got[False][0]).max() <= 1e-13 * scale, name
+    finally:
+        hyp.set_support_skip(True)
+        hyp.set_sweep_mode("auto")
+
+
+def test_sweep_support_skip_32q_near_hartree_fock(hyp):
+    """32-qubit sector (8, 8), the near-Hartree-Fock state of the H psi test:
+    all 39,960 gradients with skipping on against the unrestricted sweep, a
+    sample against the oracle, and both timed."""
+    w = synth.WORKLOADS["h16_32q"]
+    M, na, nb = w.n_orb, w.n_alpha, w.n_beta
+    x, z, c, _, _ = synth.hamiltonian(w)
+    S = hyp.Sector(M, na, nb)
+    cre, ann, _ = synth.canonical_pool(M)
+    ops = hyp.exc_tensor(cre, ann)
+    hf = synth.hf_bits(M, na, nb)
+    bits = [hf] + [(hf & ~a) | cr for cr, a in _hf_exciting_ops(M, na, nb, 24, seed=3)]
+    idx = np.unique(oracle.rank(M, na, nb, np.array(bits, dtype=np.uint32)))
+    rng = np.random.default_rng(11)
+    val = rng.standard_normal(idx.size)
+    val /= math.sqrt(float(val @ val))
+    sig = oracle.apply_h_sparse(M, na, nb, x, z, c, idx, val)
+    psi_h = np.zeros(S.dim)
+    psi_h[idx] = val
+    d_psi, d_sig = _dev(psi_h), _dev(sig)
+    times, outs = {}, {}
+    try:
+        for on in (True, False):
+            hyp.set_support_skip(on)
+            out = hyp.hyp_pool_gradients(S, ops, d_psi, d_sig)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                hyp.hyp_pool_gradients(S, ops, d_psi, d_sig, out)
+            torch.cuda.synchronize()
+            times[on] = (time.perf_counter() - t0) / 2 * 1e3
+            outs[on] = out.cpu().numpy()
+    finally:
+        hyp.set_support_skip(True)
+    print(f"[support] 32q full sweep near Hartree-Fock: skipping {times[True]:.2f} ms, "
+          f"dense {times[False]:.2f} ms", flush=True)
+    scale = max(1.0, np.abs(outs[False]).max())
+    assert np.abs(outs[True] - outs[False]).max() <= 1e-13 * scale
+    k = np.random.default_rng(5).choice(len(cre), 8, replace=False)
+    k = np.concatenate([k, [int(np.argmax(np.abs(outs[True])))]])
+    ref = oracle.pool_gradients(M, na, nb, cre[k], ann[k], psi_h, sig)
+    assert np.abs(outs[True][k] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    assert times[True] < times[False]
