@@ -109,6 +109,8 @@ def main():
                     help="FP32-storage vs FP64 error study over ITERS ADAPT iterations (JSON lines)")
     ap.add_argument("--adapt-compare", type=int, default=0, metavar="ITERS",
                     help="screened FP32 vs plain FP64 ADAPT iterations on the workload (JSON lines)")
+    ap.add_argument("--adapt-early", type=int, default=0, metavar="ITERS",
+                    help="plain FP64 ADAPT from Hartree-Fock, support skipping on, then off")
     ap.add_argument("--batch", action="store_true",
                     help="full pool-gradient sweeps of the eight uneven batch instances: one persistent batched "
                          "launch (autotuned tile) against per-instance sweeps (JSON line)")
@@ -148,6 +150,9 @@ def main():
         return
     if args.adapt_compare:
         adapt_compare(w, args.adapt_compare, args.shadow)
+        return
+    if args.adapt_early:
+        adapt_early(w, args.adapt_early)
         return
     M, na, nb = w.n_orb, w.n_alpha, w.n_beta
     t0 = time.time()
@@ -216,13 +221,48 @@ def main():
     del psi32, sig32
     print(f"[bench] H psi FP32 storage: {hpsi32_ms:.1f} ms ({threads32} threads)", file=sys.stderr, flush=True)
 
-    hpsi_kernels = ("k_transpose", "k_ss_apply", "k_mixed")
+    # support skipping near Hartree-Fock (an early-ADAPT state: HF and 24
+    # determinants one pool excitation away), H psi and the full sweep,
+    # skipping on against off
+    bits = synth.near_hf_bits(M, na, nb, 24, seed=3)
+    nidx = np.unique(S.rank(bits))
+    rng_s = np.random.default_rng(11)
+    nval = rng_s.standard_normal(nidx.size)
+    nval /= np.sqrt(nval @ nval)
+    psi_n = torch.zeros(S.dim, dtype=torch.float64, device="cuda")
+    psi_n[torch.from_numpy(nidx).cuda()] = torch.from_numpy(nval).cuda()
+    sig_n = torch.empty_like(psi_n)
+    sup = {"state": f"Hartree-Fock + {nidx.size - 1} determinants one excitation away"}
+    for on in (True, False):
+        hyp.set_support_skip(on)
+        hyp.hyp_apply_h(H, psi_n, sig_n)
+        hyp.hyp_pool_gradients(S, ops, psi_n, sig_n, grad)
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        for _ in range(2):
+            hyp.hyp_apply_h(H, psi_n, sig_n)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        for _ in range(2):
+            hyp.hyp_pool_gradients(S, ops, psi_n, sig_n, grad)
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        tag = "skip" if on else "dense"
+        sup[f"hpsi_ms_{tag}"] = round((t_b - t_a) / 2 * 1e3, 3)
+        sup[f"sweep_ms_{tag}"] = round((t_c - t_b) / 2 * 1e3, 3)
+    hyp.set_support_skip(True)
+    del psi_n, sig_n
+    print(f"[bench] near Hartree-Fock: {sup}", file=sys.stderr, flush=True)
+
+    hpsi_kernels = ("k_clear_u32", "k_transpose", "k_ss_compact", "k_ss_apply", "k_mixed")
     hpsi_ms = sum(prof.get(k, (0.0, 0))[0] for k in hpsi_kernels) / args.steps
     hpsi_bytes = hpsi_gather_bytes(m)
     value = hpsi_bytes / (hpsi_ms * 1e-3) / 1e9
     sweep_kernels = ("k_pool_grad", "k_sum_chunks", "k_tdens", "k_tdens_reduce_ab", "k_tdens_reduce_a",
                      "k_tdens_final", "k_tdens_rows", "k_tdens_rows_final", "k_eb_rows", "k_gram_grad",
-                     "k_tdens_grad", "k_widen", "rocblas_dgemm_gram_a", "rocblas_dgemm_gram_b")
+                     "k_tdens_grad", "k_widen", "rocblas_dgemm_gram_a", "rocblas_dgemm_gram_b",
+                     "k_zero_u32", "k_support", "k_list_nz", "k_rows_compact", "k_gather_rows", "k_gather_cols",
+                     "k_zero_f64")
     sweep_ms = sum(prof.get(k, (0.0, 0))[0] for k in sweep_kernels) / args.steps
 
     # dominant kernel of the step and its roofline
@@ -276,10 +316,48 @@ def main():
         "hpsi_frac_hbm_gather_model": round(value / HBM_PEAK_GBS, 4),
         "pool_grad_evals_per_s": round(m["pool"] / (sweep_ms * 1e-3), 1) if sweep_ms > 0 else None,
         "sweep_ms": round(sweep_ms, 3),
+        "support_skip_near_hf": sup,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def adapt_early(w, n_iter):
+    """Plain FP64 ADAPT iterations from Hartree-Fock (full sweep + BFGS),
+    with support skipping on and then off: per-iteration wall time, its
+    gradient and optimiser phases, and the selections (which must agree)."""
+    import torch
+    import synth
+    import paper_2604_01176_amd as hyp
+
+    M, na, nb = w.n_orb, w.n_alpha, w.n_beta
+    x, z, c, _, _ = synth.hamiltonian(w)
+    cre, ann, _ = synth.canonical_pool(M)
+    S = hyp.Sector(M, na, nb)
+    H = hyp.Hamiltonian(S, x, z, c)
+    probe = torch.from_numpy(synth.random_state(S.dim, 7)).cuda()
+    H.tune(probe, reps=1)
+    del probe
+    runs = {}
+    for on in (True, False):
+        hyp.set_support_skip(on)
+        A = hyp.Adapt(H, cre, ann, max_iter=n_iter + 1)
+        rec = []
+        for it in range(n_iter):
+            torch.cuda.synchronize()
+            t1 = time.time()
+            r = A.iterate()
+            t2 = time.time()
+            rec.append(r)
+            print(json.dumps({"support_skip": on, "iteration": it, "selected": r["selected"], "E": r["energy"],
+                              "grad_ms": round(r["grad_ms"], 1), "opt_ms": round(r["opt_ms"], 1),
+                              "n_evals": r["n_evals"], "iter_s": round(t2 - t1, 3)}), flush=True)
+        runs[on] = rec
+    hyp.set_support_skip(True)
+    same = [a["selected"] == b["selected"] for a, b in zip(runs[True], runs[False])]
+    print(json.dumps({"same_selections": same,
+                      "dE_final": runs[True][-1]["energy"] - runs[False][-1]["energy"]}), flush=True)
 
 
 def adapt_compare(w, n_iter, shadow=False):

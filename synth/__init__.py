@@ -256,6 +256,19 @@ def hf_bits(n_orb: int, n_alpha: int, n_beta: int) -> int:
     return ((1 << n_alpha) - 1) | (((1 << n_beta) - 1) << n_orb)
 
 
+def near_hf_bits(n_orb: int, n_alpha: int, n_beta: int, n_exc: int = 24, seed: int = 3) -> np.ndarray:
+    """Bitstrings of an early-ADAPT support: the Hartree-Fock determinant and
+    n_exc determinants reached from it by one pool excitation (occupied
+    orbitals annihilated, empty ones created), drawn at random (seeded)."""
+    cre, ann, _ = canonical_pool(n_orb)
+    hf = hf_bits(n_orb, n_alpha, n_beta)
+    ok = [i for i in range(cre.size) if (int(ann[i]) & hf) == int(ann[i]) and (int(cre[i]) & hf) == 0]
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(ok), size=min(n_exc, len(ok)), replace=False)
+    bits = [hf] + [(hf & ~int(ann[ok[i]])) | int(cre[ok[i]]) for i in pick]
+    return np.array(bits, dtype=np.uint32)
+
+
 def sparse_state(dim: int, d_alpha: int, n_random: int = 64, seed: int = 21):
     """Sparse sector vector as (sorted indices, values), norm 1: the 16
     lowest alpha ranks with the lowest beta string, the 16 lowest beta ranks

@@ -134,9 +134,7 @@ def test_support_skip_32q_near_hartree_fock(hyp):
     x, z, c, _, _ = synth.hamiltonian(w)
     S = hyp.Sector(M, na, nb)
     H = hyp.Hamiltonian(S, x, z, c)
-    hf = synth.hf_bits(M, na, nb)
-    bits = [hf] + [(hf & ~a) | cr for cr, a in _hf_exciting_ops(M, na, nb, 24, seed=3)]
-    idx = np.unique(oracle.rank(M, na, nb, np.array(bits, dtype=np.uint32)))
+    idx = np.unique(oracle.rank(M, na, nb, synth.near_hf_bits(M, na, nb, 24, seed=3)))
     assert idx.min() >= 0
     rng = np.random.default_rng(11)
     val = rng.standard_normal(idx.size)
@@ -217,9 +215,7 @@ def test_sweep_support_skip_32q_near_hartree_fock(hyp):
     S = hyp.Sector(M, na, nb)
     cre, ann, _ = synth.canonical_pool(M)
     ops = hyp.exc_tensor(cre, ann)
-    hf = synth.hf_bits(M, na, nb)
-    bits = [hf] + [(hf & ~a) | cr for cr, a in _hf_exciting_ops(M, na, nb, 24, seed=3)]
-    idx = np.unique(oracle.rank(M, na, nb, np.array(bits, dtype=np.uint32)))
+    idx = np.unique(oracle.rank(M, na, nb, synth.near_hf_bits(M, na, nb, 24, seed=3)))
     rng = np.random.default_rng(11)
     val = rng.standard_normal(idx.size)
     val /= math.sqrt(float(val @ val))
