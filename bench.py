@@ -71,11 +71,24 @@ def roofline(name, ms, m):
             "ms_per_launch": round(ms, 3)}
 
 
-def source_digest():
+# source file of each kernel whose counters are committed
+KERNEL_SOURCES = {"k_mixed": "hamiltonian.hip", "k_ss_apply": "hamiltonian.hip", "k_transpose": "hamiltonian.hip",
+                  "k_tdens_rows": "sweep.hip", "k_tdens_rows_final": "sweep.hip", "k_gram_grad": "sweep.hip",
+                  "k_rotate": "pool.hip", "k_dot_partial_f64": "sector.hip"}
+
+
+def source_digest(kernel=None):
+    """Digest of a kernel's source file and the shared header (all sources
+    when kernel is None or unknown)."""
     import glob
     import hashlib
+    csrc = os.path.join(ROOT, "paper_2604_01176_amd", "csrc")
+    if kernel in KERNEL_SOURCES:
+        files = [os.path.join(csrc, KERNEL_SOURCES[kernel]), os.path.join(csrc, "hyp_internal.h")]
+    else:
+        files = sorted(glob.glob(os.path.join(csrc, "*")))
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_01176_amd", "csrc", "*"))):
+    for f in files:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -84,16 +97,16 @@ def source_digest():
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when there is none or the kernel sources changed since it was taken."""
+    when there is none or the kernel's source changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("source_digest") != source_digest():
-        return None
     k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+    if k is None or k.get("source_digest") != source_digest(kernel):
+        return None
+    return k.get("hbm_bytes_per_launch")
 
 
 def main():
@@ -254,6 +267,14 @@ def main():
     del psi_n, sig_n
     print(f"[bench] near Hartree-Fock: {sup}", file=sys.stderr, flush=True)
 
+    # device-side Jordan-Wigner assembly of the workload's integrals
+    _, _, _, h_int, g_int = synth.hamiltonian(w)
+    hyp.hyp_assemble_pauli(h_int, g_int)
+    torch.cuda.synchronize()
+    t_a = time.perf_counter()
+    n_asm = hyp.hyp_assemble_pauli(h_int, g_int)[0].size
+    asm = {"terms": int(n_asm), "device_ms": round((time.perf_counter() - t_a) * 1e3, 2)}
+
     hpsi_kernels = ("k_clear_u32", "k_transpose", "k_ss_compact", "k_ss_apply", "k_mixed")
     hpsi_ms = sum(prof.get(k, (0.0, 0))[0] for k in hpsi_kernels) / args.steps
     hpsi_bytes = hpsi_gather_bytes(m)
@@ -290,6 +311,10 @@ def main():
         oracle.apply_h(M, na, nb, x, z, c, psi_h, out_idx=idx)
         dt = time.time() - t
         row_bytes = (m["conn"] + 1) * 8
+        from oracle import jw
+        t_j = time.time()
+        jw.jw_pauli_list(h_int, g_int)
+        asm["oracle_s"] = round(time.time() - t_j, 2)
         cpu = {"value": round(n_rows * row_bytes / dt / 1e9, 4), "unit": "GB/s",
                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
                "kind": "oracle",
@@ -317,6 +342,7 @@ def main():
         "pool_grad_evals_per_s": round(m["pool"] / (sweep_ms * 1e-3), 1) if sweep_ms > 0 else None,
         "sweep_ms": round(sweep_ms, 3),
         "support_skip_near_hf": sup,
+        "pauli_assembly": asm,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -96,6 +96,34 @@ hyp_status hyp_build_hamiltonian(hyp_sector s, const uint32_t* x_mask, const uin
                                  const double* coeff, int64_t n_terms, void* stream,
                                  hyp_ham* out);
 hyp_status hyp_ham_destroy(hyp_ham h);
+
+/* Device-side Hamiltonian assembly ("Sparse State-Vector Emulation": the
+ * Hamiltonian is assembled on the GPU by summing the contributions of the
+ * individual fermionic operators after the qubit mapping).  From the
+ * molecular integrals h_dev [M][M] and g_dev [M][M][M][M] (device FP64,
+ * chemist's notation, row-major) and the constant e_core:
+ *   H = e_core + sum_{pq s} h_pq a+_{ps} a_{qs}
+ *     + 1/2 sum_{pqrs, s t} g_pqrs a+_{ps} a+_{rt} a_{st} a_{qs},
+ * Jordan-Wigner with spin orbital p + s M on qubit p + s M (blocked spin
+ * order), as a Pauli list sum_t c_t P(x_t, z_t) (P with Y where both bits are
+ * set), equal strings merged (double-double sums; residues below 1e-14 of a
+ * string's summed magnitudes are exact cancellations and dropped), sorted by
+ * (x, z), i.e. grouped by X mask.  Writes min(n, cap) terms to the device
+ * arrays x_dev, z_dev, c_dev and n to *n_terms (host); cap = 0 with NULL
+ * outputs only counts.  HYP_ERR_ARG for M outside [1, 16] or cap < n (after
+ * writing *n_terms); HYP_ERR_NONREAL when an imaginary part survives (h or g
+ * not real-symmetric).  Synchronous on `stream`; scratch is allocated and
+ * freed inside (about 40 bytes per expansion slot, 4.2 M slots at M = 16). */
+hyp_status hyp_assemble_pauli(int n_orb, const double* h_dev, const double* g_dev, double e_core,
+                              uint32_t* x_dev, uint32_t* z_dev, double* c_dev, int64_t cap,
+                              int64_t* n_terms, void* stream);
+
+/* hyp_assemble_pauli followed by hyp_build_hamiltonian on its list (the
+ * X-group fold of the build runs on the host from the downloaded table).
+ * n_orb must equal the sector's M.  Synchronous on `stream`. */
+hyp_status hyp_build_hamiltonian_integrals(hyp_sector s, int n_orb, const double* h_dev,
+                                           const double* g_dev, double e_core, void* stream,
+                                           hyp_ham* out);
 /* 1 if the structured kernel serves this Hamiltonian, 0 if the generic one, -1 on NULL. */
 int hyp_ham_is_structured(hyp_ham h);
 

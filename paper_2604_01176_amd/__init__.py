@@ -95,7 +95,12 @@ class Sector:
 class Hamiltonian:
     """hyp_ham: X-grouped Pauli table uploaded for one sector."""
 
-    def __init__(self, sector: Sector, x, z, c):
+    def __init__(self, sector: Sector, x, z, c, *, _handle=None):
+        if _handle is not None:
+            self._h = _handle
+            self.sector = sector
+            self.structured = bool(_lib.load().hyp_ham_is_structured(_handle))
+            return
         x = np.ascontiguousarray(x, dtype=np.uint32)
         z = np.ascontiguousarray(z, dtype=np.uint32)
         c = np.ascontiguousarray(c, dtype=np.float64)
@@ -107,6 +112,19 @@ class Hamiltonian:
         self._h = h
         self.sector = sector
         self.structured = bool(_lib.load().hyp_ham_is_structured(h))
+
+    @classmethod
+    def from_integrals(cls, sector: Sector, h, g, e_core: float = 0.0):
+        """hyp_build_hamiltonian_integrals: Jordan-Wigner assembly of the
+        integrals on the device, then the common build."""
+        torch = _torch()
+        M = sector.n_orb
+        hd = torch.as_tensor(np.ascontiguousarray(h, dtype=np.float64)).reshape(M, M).cuda()
+        gd = torch.as_tensor(np.ascontiguousarray(g, dtype=np.float64)).reshape(M, M, M, M).cuda()
+        hh = ctypes.c_void_p()
+        check(_lib.load().hyp_build_hamiltonian_integrals(sector.handle, M, hd.data_ptr(), gd.data_ptr(),
+                                                          float(e_core), _stream(), ctypes.byref(hh)))
+        return cls(sector, None, None, None, _handle=hh)
 
     def apply(self, psi, out=None):
         """sigma = H psi (hyp_apply_h)."""
@@ -135,6 +153,27 @@ class Hamiltonian:
             self.close()
         except Exception:
             pass
+
+
+def hyp_assemble_pauli(h, g, e_core: float = 0.0):
+    """Device-side Jordan-Wigner assembly of the integrals (hyp_assemble_pauli):
+    (x, z, c) as host numpy arrays, sorted by (x, z)."""
+    torch = _torch()
+    M = int(np.asarray(h).shape[0])
+    hd = torch.as_tensor(np.ascontiguousarray(h, dtype=np.float64)).cuda()
+    gd = torch.as_tensor(np.ascontiguousarray(g, dtype=np.float64)).cuda()
+    n = ctypes.c_int64()
+    L = _lib.load()
+    check(L.hyp_assemble_pauli(M, hd.data_ptr(), gd.data_ptr(), float(e_core), None, None, None, 0,
+                               ctypes.byref(n), _stream()))
+    k = max(1, n.value)
+    x = torch.empty(k, dtype=torch.int32, device="cuda")
+    z = torch.empty(k, dtype=torch.int32, device="cuda")
+    c = torch.empty(k, dtype=torch.float64, device="cuda")
+    check(L.hyp_assemble_pauli(M, hd.data_ptr(), gd.data_ptr(), float(e_core), x.data_ptr(), z.data_ptr(),
+                               c.data_ptr(), k, ctypes.byref(n), _stream()))
+    m = n.value
+    return (x[:m].cpu().numpy().view(np.uint32), z[:m].cpu().numpy().view(np.uint32), c[:m].cpu().numpy())
 
 
 def hyp_apply_h(ham: Hamiltonian, psi, sigma):

@@ -67,6 +67,8 @@ SIGNATURES = {
     "hyp_sector_unrank": (_ci, [_vp, _vp, _i64, _vp]),
     "hyp_build_hamiltonian": (_ci, [_vp, _vp, _vp, _vp, _i64, _vp, ctypes.POINTER(_vp)]),
     "hyp_ham_destroy": (_ci, [_vp]),
+    "hyp_assemble_pauli": (_ci, [_ci, _vp, _vp, _d, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp]),
+    "hyp_build_hamiltonian_integrals": (_ci, [_vp, _ci, _vp, _vp, _d, _vp, ctypes.POINTER(_vp)]),
     "hyp_ham_is_structured": (_ci, [_vp]),
     "hyp_apply_h": (_ci, [_vp, _ci, _vp, _vp, _vp]),
     "hyp_tune_apply_h": (_ci, [_vp, _ci, _vp, _vp, _ci, _vp, ctypes.POINTER(_ci), ctypes.POINTER(_d)]),

@@ -5,6 +5,7 @@ import math
 import os
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 import scipy.linalg as sla
 
@@ -98,6 +99,31 @@ def test_pauli_list_equals_fermionic_hamiltonian(M):
     assert abs(Hf - Hp).max() < 1e-13
     # real symmetric
     assert abs(Hf.imag).max() == 0 and abs(Hf - Hf.T).max() < 1e-13
+
+
+@pytest.mark.parametrize("M", [1, 2, 3])
+def test_oracle_jw_equals_fermionic_hamiltonian(M):
+    """The oracle's own Jordan-Wigner expansion (complex Pauli algebra) gives
+    the dense second-quantised matrix built from explicit ladder matrices,
+    including the constant."""
+    from oracle import jw
+    h, g = synth.integrals(M, 77 + M)
+    x, z, c = jw.jw_pauli_list(h, g, e_core=-0.75)
+    n = 2 * M
+    Hf = brute.fermion_hamiltonian(h, g) + (-0.75) * sp.identity(1 << n)
+    Hp = brute.pauli_sum(x, z, c, n)
+    assert abs(Hf - Hp).max() < 1e-13
+
+
+def test_oracle_jw_nonreal_and_trivial():
+    from oracle import jw
+    h, g = synth.integrals(2, 3)
+    h2 = h.copy()
+    h2[0, 1] += 0.25  # h not symmetric: imaginary strings survive
+    with pytest.raises(ArithmeticError):
+        jw.jw_pauli_list(h2, g)
+    x, z, c = jw.jw_pauli_list(np.zeros((2, 2)), np.zeros((2, 2, 2, 2)), e_core=1.5)
+    assert list(x) == [0] and list(z) == [0] and list(c) == [1.5]
 
 
 @pytest.mark.parametrize("M", [3, 4, 5, 6, 8, 12])
