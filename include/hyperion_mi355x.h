@@ -196,6 +196,19 @@ hyp_status hyp_pool_gradients(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_
  * Process-wide setting. */
 hyp_status hyp_set_sweep_mode(int mode);
 
+/* Kind of the pool generators (the paper's ADAPT-VQE description names the
+ * qubit-excitation-based, QEB, pool as an example): 0 fermionic excitations
+ * (default), 1 qubit excitations.  Both take the same (cre, ann) masks; a
+ * qubit excitation is the product of qubit raising and lowering operators
+ * without the Jordan-Wigner parity strings, so tau|D> = |tau D> with sign +1
+ * wherever a fermionic excitation would carry (-1)^parity.  Applies to
+ * hyp_pool_gradients, hyp_pool_gradients_batched, hyp_apply_excitation and
+ * the ADAPT engine for calls made after it (an ADAPT object's captured
+ * evaluation graph keeps the kind in force when it was captured; it is
+ * recaptured whenever the ansatz grows).  Process-wide; HYP_ERR_ARG unless
+ * kind is 0 or 1. */
+hyp_status hyp_set_pool_kind(int kind);
+
 /* psi <- exp(theta A) psi in place (the exponentiated fermionic operator):
  * on every pair (D, D' = tau D, sign s) psi_D <- cos psi_D - s sin psi_D',
  * psi_D' <- s sin psi_D + cos psi_D'; other amplitudes unchanged. */

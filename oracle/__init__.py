@@ -72,6 +72,8 @@ def lib():
         L.orc_pool_gradients.argtypes = [ci, ci, ci, i64, u32p, u32p, f64p, f64p, f64p]
         L.orc_apply_generator.argtypes = [ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, f64p, f64p]
         L.orc_rotate.argtypes = [ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, f64p]
+        L.orc_set_qubit_excitations.restype = None
+        L.orc_set_qubit_excitations.argtypes = [ci]
         L.orc_pair_count.restype = i64
         L.orc_pair_count.argtypes = [ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32]
         L.orc_occupations.argtypes = [ci, ci, ci, f64p, f64p]
@@ -155,6 +157,19 @@ def energy(M, na, nb, x, z, c, psi):
     """E = <psi|H|psi> / <psi|psi>."""
     s = apply_h(M, na, nb, x, z, c, psi)
     return dot(psi, s) / dot(psi, psi)
+
+
+class qubit_excitations:
+    """Context: the excitation functions below act as qubit excitations
+    (QEB: no Jordan-Wigner parity, every sign +1) inside the block."""
+
+    def __enter__(self):
+        lib().orc_set_qubit_excitations(1)
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_qubit_excitations(0)
+        return False
 
 
 def apply_tau(cre, ann, b):

@@ -142,6 +142,22 @@ def generator_matrix(cre: int, ann: int, n: int):
     return tau - tau.conj().T
 
 
+def qubit_generator_matrix(cre: int, ann: int, n: int):
+    """A = tau - tau^dagger for a qubit excitation (the QEB pool):
+    tau = prod_c sigma^+_c prod_a sigma^-_a with no Jordan-Wigner strings,
+    sigma^- = |0><1| on the qubit (empties an occupied orbital)."""
+    mats = []
+    for q in range(n):
+        if (cre >> q) & 1:
+            mats.append(SM.T.copy())
+        elif (ann >> q) & 1:
+            mats.append(SM)
+        else:
+            mats.append(I2)
+    tau = _kron_list(mats)
+    return tau - tau.conj().T
+
+
 # ---------------------------------------------------------------------------
 # sector-level twins (NumPy, vectorised over determinants)
 # ---------------------------------------------------------------------------

@@ -185,10 +185,19 @@ double orc_dot(int64_t n, const double *a, const double *b) {
 /* ------------------------------------------------------------ excitations */
 
 /*
+ * Generator kind: 0 fermionic excitations (default), 1 qubit excitations
+ * (the QEB pool of the paper's ADAPT-VQE description): the qubit operators
+ * sigma^+ / sigma^- carry no Jordan-Wigner parity string, so every sign is +1.
+ */
+static int orc_qubit_exc = 0;
+void orc_set_qubit_excitations(int on) { orc_qubit_exc = on ? 1 : 0; }
+
+/*
  * tau = a+_{c1} a+_{c2} a_{a2} a_{a1}  (c1 < c2, a1 < a2)  or  a+_c a_a,
  * applied to the basis state b right to left; each ladder operator on qubit
- * q contributes (-1)^{popc(current & (2^q - 1))}.  Returns 0 if tau b = 0,
- * else the sign, and the target in *out.
+ * q contributes (-1)^{popc(current & (2^q - 1))} (fermionic kind; +1 for
+ * qubit excitations).  Returns 0 if tau b = 0, else the sign, and the
+ * target in *out.
  */
 int orc_apply_tau(uint32_t cre, uint32_t ann, uint32_t b, uint32_t *out) {
     int cq[2], aq[2], nc = 0, nan_ = 0;
@@ -209,7 +218,7 @@ int orc_apply_tau(uint32_t cre, uint32_t ann, uint32_t b, uint32_t *out) {
         uint32_t bit = 1u << qs[i];
         int occ = (cur & bit) != 0;
         if (cr[i] ? occ : !occ) return 0;
-        if (popc32(cur & (bit - 1u)) & 1) sign = -sign;
+        if (!orc_qubit_exc && (popc32(cur & (bit - 1u)) & 1)) sign = -sign;
         cur ^= bit;
     }
     *out = cur;

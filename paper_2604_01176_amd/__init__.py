@@ -232,6 +232,11 @@ def set_sweep_mode(mode: str = "auto"):
     check(_lib.load().hyp_set_sweep_mode({"auto": 0, "pairs": 1, "tdens": 2, "tdens_bins": 3}[mode]))
 
 
+def set_pool_kind(kind: str = "fermionic"):
+    """hyp_set_pool_kind: "fermionic" or "qubit" (QEB) excitations."""
+    check(_lib.load().hyp_set_pool_kind({"fermionic": 0, "qubit": 1}[kind]))
+
+
 def set_support_skip(on: bool = True):
     """hyp_set_support_skip: restrict H psi to psi's row and column support."""
     check(_lib.load().hyp_set_support_skip(1 if on else 0))

@@ -77,6 +77,7 @@ SIGNATURES = {
     "hyp_apply_excitation": (_ci, [_vp, _ci, HypExc, _d, _vp, _vp]),
     "hyp_set_sweep_mode": (_ci, [_ci]),
     "hyp_set_support_skip": (_ci, [_ci]),
+    "hyp_set_pool_kind": (_ci, [_ci]),
     "hyp_pool_gradients_batched": (_ci, [_vp, _ci, _vp, _vp]),
     "hyp_tune_pool_gradients": (_ci, [_vp, _ci, _ci, ctypes.POINTER(SweepTile), ctypes.POINTER(_d), _vp]),
     "hyp_mlp_create": (_ci, [_vp, _i64, ctypes.POINTER(_vp)]),

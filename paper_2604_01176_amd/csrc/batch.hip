@@ -131,7 +131,7 @@ __global__ void k_pool_grad_persistent(BatchArgs a) {
         uint32_t Js = bpart_string(pa, i);
         uint32_t Is = Js ^ pa.am ^ pa.cm;
         lst[i] = (uint32_t)brank(S.arank, Js) | ((uint32_t)brank(S.arank, Is) << 14) |
-                 ((uint32_t)bpart_sign(pa.cm, pa.am, Js) << 28);
+                 ((uint32_t)(bpart_sign(pa.cm, pa.am, Js) & S.fsign) << 28);
       }
     __syncthreads();
     const int nA = a_id ? S.da : pa.count;
@@ -150,7 +150,7 @@ __global__ void k_pool_grad_persistent(BatchArgs a) {
         uint32_t Ib = Jb ^ pb.am ^ pb.cm;
         rJb = brank(S.brank, Jb);
         rIb = brank(S.brank, Ib);
-        sb = bpart_sign(pb.cm, pb.am, Jb);
+        sb = bpart_sign(pb.cm, pb.am, Jb) & S.fsign;
       }
       const int64_t oJ = (int64_t)rJb * S.da, oI = (int64_t)rIb * S.da;
       double rs = 0.0;

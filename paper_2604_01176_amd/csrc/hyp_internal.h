@@ -60,7 +60,11 @@ struct SectorDev {
   const uint32_t* bstr;   // [db]
   const RankTables* arank;  // device copies
   const RankTables* brank;
+  int fsign;              // 1: fermionic excitation signs; 0: qubit excitations (every sign +1)
 };
+
+// Process-wide generator kind (hyp_set_pool_kind): 0 fermionic, 1 qubit excitations.
+int pool_kind();
 
 struct Sector {
   int M = 0, na = 0, nb = 0;
@@ -79,6 +83,7 @@ struct Sector {
     SectorDev s;
     s.M = M; s.na = na; s.nb = nb; s.da = (int)da; s.db = (int)db; s.dim = dim;
     s.astr = d_astr; s.bstr = d_bstr; s.arank = d_arank; s.brank = d_brank;
+    s.fsign = pool_kind() == 0 ? 1 : 0;
     return s;
   }
 };

@@ -107,7 +107,7 @@ __device__ inline void build_alpha_list(const PairCtx& c, const SectorDev& S, ui
   for (int i = threadIdx.x; i < c.pa.count; i += blockDim.x) {
     uint32_t J = part_string(c.pa, i);
     uint32_t I = J ^ c.pa.am ^ c.pa.cm;
-    int sg = part_sign(c.pa.cm, c.pa.am, J);
+    int sg = part_sign(c.pa.cm, c.pa.am, J) & S.fsign;
     lst[i] = (uint32_t)rank_of(S.arank, J) | ((uint32_t)rank_of(S.arank, I) << 14) | ((uint32_t)sg << 28);
   }
 }
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pool_grad(SectorDev S, const h
       uint32_t Ib = Jb ^ c.pb.am ^ c.pb.cm;
       rJb = rank_of(S.brank, Jb);
       rIb = rank_of(S.brank, Ib);
-      sb = part_sign(c.pb.cm, c.pb.am, Jb);
+      sb = part_sign(c.pb.cm, c.pb.am, Jb) & S.fsign;
     }
     const int64_t oJ = (int64_t)rJb * S.da, oI = (int64_t)rIb * S.da;
     double rs = 0.0;
@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(kPairThreads) k_rotate(SectorDev S, hyp_exc op
       uint32_t Ib = Jb ^ c.pb.am ^ c.pb.cm;
       rJb = rank_of(S.brank, Jb);
       rIb = rank_of(S.brank, Ib);
-      sb = part_sign(c.pb.cm, c.pb.am, Jb);
+      sb = part_sign(c.pb.cm, c.pb.am, Jb) & S.fsign;
     }
     const int64_t oJ = (int64_t)rJb * S.da, oI = (int64_t)rIb * S.da;
     for (int t = threadIdx.x; t < nA; t += blockDim.x) {
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(kPairThreads) k_adjoint_step(SectorDev S, hyp_
       uint32_t Ib = Jb ^ c.pb.am ^ c.pb.cm;
       rJb = rank_of(S.brank, Jb);
       rIb = rank_of(S.brank, Ib);
-      sb = part_sign(c.pb.cm, c.pb.am, Jb);
+      sb = part_sign(c.pb.cm, c.pb.am, Jb) & S.fsign;
     }
     const int64_t oJ = (int64_t)rJb * S.da, oI = (int64_t)rIb * S.da;
     for (int t = threadIdx.x; t < nA; t += blockDim.x) {
@@ -374,6 +374,9 @@ static hyp_status launch_pool_grad(Sector* S, const hyp_exc* ops, int64_t n_ops,
 }
 
 static int g_sweep_mode = 0;  // 0 automatic, 1 pairs, 2 transition values, 3 per-stage bins
+static int g_pool_kind = 0;   // 0 fermionic excitations, 1 qubit excitations
+
+int pool_kind() { return g_pool_kind; }
 
 static int64_t full_pool_size(int M) {
   auto C = [](int64_t m, int64_t k) {
@@ -473,6 +476,12 @@ using namespace hyp;
 extern "C" {
 
 hyp_status hyp_set_sweep_mode(int mode) { return set_sweep_mode(mode); }
+
+hyp_status hyp_set_pool_kind(int kind) {
+  if (kind != 0 && kind != 1) return fail(HYP_ERR_ARG, "hyp_set_pool_kind: kind must be 0 or 1");
+  g_pool_kind = kind;
+  return HYP_OK;
+}
 
 hyp_status hyp_pool_gradients(hyp_sector sh, hyp_dtype dtype, const hyp_exc* ops, int64_t n_ops,
                               const void* psi, const void* sigma, double* grad, void* stream) {

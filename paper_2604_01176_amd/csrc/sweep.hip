@@ -49,6 +49,7 @@ struct TArgs {
   const RankTables* brank;
   int nchunk, nstage;   // nstage = 1 + N_b (M - N_b)
   double* part;         // [db][nchunk][nstage][kStageW]
+  int fsign;            // 1 fermionic signs, 0 qubit excitations (all +1)
 };
 
 template <typename T>
@@ -94,7 +95,7 @@ __global__ void __launch_bounds__(768) k_tdens(TArgs a) {
         const int p = min(i, e), q = max(i, e);
         const uint32_t t2 = s ^ (1u << i) ^ (1u << e);
         const uint32_t r2 = (uint32_t)(a.arank->lo[t2 & 255u] + a.arank->hi[(t2 >> 8) & 255u]);
-        const uint32_t sg = __popc(betw(p, q) & s) & 1u;
+        const uint32_t sg = __popc(betw(p, q) & s) & (uint32_t)a.fsign;
         const uint32_t bin = (uint32_t)(q * (q - 1) / 2 + p) * 2u + (i == q ? 1u : 0u);
         const uint32_t ent = r2 | (sg << 14) | (bin << 15);
         int pos = ns + rot;
@@ -122,7 +123,7 @@ __global__ void __launch_bounds__(768) k_tdens(TArgs a) {
       const int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
       const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
       src = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
-      sb = (__popc(betw(min(i, e), max(i, e)) & bs) & 1) ? -1.0 : 1.0;
+      sb = (__popc(betw(min(i, e), max(i, e)) & bs) & a.fsign) ? -1.0 : 1.0;
     }
     for (int x = tid; x < 12 * kBins; x += nt) s_wbin[x / kBins][x % kBins] = 0.0;
     const T* srow = psi + (int64_t)src * a.da;
@@ -196,6 +197,7 @@ struct TRArgs {
   const int* rcount;
   const int* idrows;
   const int* n_idrows;
+  int fsign;          // 1 fermionic signs, 0 qubit excitations (all +1)
 };
 
 // LDS byte offsets (source rank * element size) of a string's alpha single
@@ -351,6 +353,7 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
     for (int x = 0; x < 16; ++x) bins[x] = 0u;
     uint64_t signs = 0;
     alpha_bins(s, amask, bins, &signs);
+    if (!a.fsign) signs = 0;
 #pragma unroll
     for (int x = 0; x < 64; ++x) {
       if (x < ns) {
@@ -401,7 +404,7 @@ __global__ void k_tdens_rows_final(const double* part, int n_eb, int n_id, int n
 // (source row, target row | sign << 31) of every ordered beta single
 // excitation eb = (created ci, annihilated ae): source rows hold ae and not
 // ci, in colex order over the other orbitals.  One thread per (eb, k).
-__global__ void k_eb_rows(int M, int nb, int n_eb, int K, const RankTables* brank, int2* rows) {
+__global__ void k_eb_rows(int M, int nb, int n_eb, int K, const RankTables* brank, int fsign, int2* rows) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)n_eb * K) return;
   const int eb = (int)(i / K), k = (int)(i % K);
@@ -427,7 +430,7 @@ __global__ void k_eb_rows(int M, int nb, int n_eb, int K, const RankTables* bran
     f ^= low;
   }
   const uint32_t tgt = src ^ (1u << ci) ^ (1u << ae);
-  const uint32_t sg = __popc(betw(p, q) & src) & 1u;
+  const uint32_t sg = __popc(betw(p, q) & src) & (uint32_t)fsign;
   const int rs = brank->lo[src & 255u] + brank->hi[(src >> 8) & 255u];
   const int rt = brank->lo[tgt & 255u] + brank->hi[(tgt >> 8) & 255u];
   rows[i] = make_int2(rs, (int)((uint32_t)rt | (sg << 31)));
@@ -597,7 +600,7 @@ __device__ inline int gram_sign(uint32_t cm, uint32_t am, uint32_t s) {
 // (G column-major: G(I, J) at G[I + J * D]); other generators are skipped.
 __global__ void k_gram_grad(const hyp_exc* ops, int M, int na, int nb, const double* Ga, int64_t da,
                             const double* Gb, int64_t db, const RankTables* arank, const RankTables* brank,
-                            double* grad) {
+                            int fsign, double* grad) {
   __shared__ double red[4];
   const int64_t k = blockIdx.x;
   const uint32_t m = (1u << M) - 1u;
@@ -620,7 +623,7 @@ __global__ void k_gram_grad(const hyp_exc* ops, int M, int na, int nb, const dou
     const int64_t rj = R->lo[J & 255u] + R->hi[(J >> 8) & 255u];
     const int64_t ri = R->lo[I & 255u] + R->hi[(I >> 8) & 255u];
     const double v = G[ri + rj * D] - G[rj + ri * D];
-    acc += gram_sign(cm, am, J) ? -v : v;
+    acc += (gram_sign(cm, am, J) & fsign) ? -v : v;
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -754,7 +757,7 @@ struct TScratch {
   double* gram = nullptr;  // G_a | G_b | widened psi | widened sigma
   size_t gram_cap = 0;
   int2* rows = nullptr;    // beta excitation row pairs of the row-batched kernel
-  int rows_M = -1, rows_nb = -1;
+  int rows_M = -1, rows_nb = -1, rows_fsign = -1;
   size_t rows_cap = 0;
   double* rpart = nullptr; // partials of the row-batched kernel
   size_t rpart_cap = 0;
@@ -810,7 +813,8 @@ static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* 
   const int nt = std::max(64, std::min(512, (a.da + 63) / 64 * 64));
   a.nchunk = (a.da + nt - 1) / nt;
   const size_t rows_need = (size_t)a.n_eb * a.K;
-  if (rows_need > 0 && (ts.rows_M != S->M || ts.rows_nb != S->nb)) {
+  a.fsign = pool_kind() == 0 ? 1 : 0;
+  if (rows_need > 0 && (ts.rows_M != S->M || ts.rows_nb != S->nb || ts.rows_fsign != a.fsign)) {
     if (rows_need > ts.rows_cap) {
       HYP_HIP(hipDeviceSynchronize());
       if (ts.rows) HYP_HIP(hipFree(ts.rows));
@@ -820,9 +824,10 @@ static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* 
       ts.rows_cap = rows_need;
     }
     HYP_LAUNCH("k_eb_rows", k_eb_rows, dim3((unsigned)((rows_need + 255) / 256)), dim3(256), 0, st, S->M, S->nb,
-               a.n_eb, a.K, S->d_brank, ts.rows);
+               a.n_eb, a.K, S->d_brank, a.fsign, ts.rows);
     ts.rows_M = S->M;
     ts.rows_nb = S->nb;
+    ts.rows_fsign = a.fsign;
   }
   a.rows = ts.rows;
   a.rcount = nullptr;
@@ -972,6 +977,7 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
   a.nchunk = (a.da + nt - 1) / nt;
   a.nstage = 1 + a.nb * (a.M - a.nb);
   a.part = ts.part;
+  a.fsign = pool_kind() == 0 ? 1 : 0;
   const size_t shm = (size_t)a.da * (dt == HYP_F64 ? 8 : 4);
   const int64_t nblk = (int64_t)8 * ((a.db + 7) / 8) * a.nchunk;
   if (dt == HYP_F64) {
@@ -1117,7 +1123,7 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
   }
   if (bs != rocblas_status_success) return fail(HYP_ERR_HIP, "rocblas_dgemm (beta Gram) failed");
   HYP_LAUNCH("k_gram_grad", k_gram_grad, dim3((unsigned)n_ops), dim3(256), 0, st, ops, S->M, S->na, S->nb, Ga, da,
-             Gb, db, S->d_arank, S->d_brank, grad);
+             Gb, db, S->d_arank, S->d_brank, pool_kind() == 0 ? 1 : 0, grad);
   HYP_LAUNCH("k_tdens_grad", k_tdens_grad, dim3((unsigned)((n_ops + 255) / 256)), dim3(256), 0, st, ops, n_ops,
              S->M, Ta, Tb, Tab, grad);
   HYP_HIP(hipGetLastError());

@@ -1,0 +1,143 @@
+"""GPU parity of the qubit-excitation (QEB) pool: the same (cre, ann)
+generators acting without Jordan-Wigner parity (every pair sign +1).
+Gradients in every sweep strategy and both storage types, rotations, the
+batched sweep and the ADAPT loop against the oracle run with qubit
+excitations (oracle.qubit_excitations, pinned to Kronecker-product
+sigma^+/sigma^- matrices)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle.adapt import SectorProblem, run_adapt
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hyp():
+    import paper_2604_01176_amd as hyp
+    yield hyp
+    hyp.set_pool_kind("fermionic")
+
+
+def _dev(v, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(v)).to("cuda", dtype)
+
+
+def _ham(hyp, M, na, nb, seed):
+    h, g = synth.integrals(M, seed)
+    x, z, c = synth.jw_pauli_list(h, g)
+    S = hyp.Sector(M, na, nb)
+    return S, hyp.Hamiltonian(S, x, z, c), (x, z, c)
+
+
+@pytest.mark.parametrize("M,na,nb", [(4, 2, 2), (5, 2, 3), (6, 3, 3), (8, 4, 4), (3, 0, 2), (4, 4, 1), (7, 3, 2),
+                                     (2, 1, 1)])
+def test_qeb_gradients_all_strategies(hyp, M, na, nb):
+    S, H, (x, z, c) = _ham(hyp, M, na, nb, 700 + M)
+    cre, ann, _ = synth.canonical_pool(M)
+    psi = synth.random_state(S.dim, 23)
+    sig = oracle.apply_h(M, na, nb, x, z, c, psi)
+    with oracle.qubit_excitations():
+        ref = oracle.pool_gradients(M, na, nb, cre, ann, psi, sig)
+    fer = oracle.pool_gradients(M, na, nb, cre, ann, psi, sig)
+    ops = hyp.exc_tensor(cre, ann)
+    scale = max(1.0, np.abs(ref).max())
+    try:
+        hyp.set_pool_kind("qubit")
+        for mode in ("tdens", "tdens_bins", "pairs"):
+            hyp.set_sweep_mode(mode)
+            g = hyp.hyp_pool_gradients(S, ops, _dev(psi), _dev(sig)).cpu().numpy()
+            g32 = hyp.hyp_pool_gradients(S, ops, _dev(psi, torch.float32), _dev(sig, torch.float32)).cpu().numpy()
+            assert np.abs(g - ref).max() <= 1e-12 * scale, mode
+            assert np.abs(g32 - ref).max() <= 1e-5 * scale, mode
+    finally:
+        hyp.set_sweep_mode("auto")
+        hyp.set_pool_kind("fermionic")
+    # the kinds really differ (parity signs matter for some generators), and
+    # the fermionic setting is restored
+    if (M, na, nb) not in {(4, 4, 1), (2, 1, 1)}:  # sectors with no parity to differ by
+        assert np.abs(fer - ref).max() > 1e-6
+    g = hyp.hyp_pool_gradients(S, ops, _dev(psi), _dev(sig)).cpu().numpy()
+    assert np.abs(g - fer).max() <= 1e-12 * max(1.0, np.abs(fer).max())
+
+
+@pytest.mark.parametrize("M,na,nb", [(4, 2, 2), (6, 3, 3), (8, 4, 4)])
+def test_qeb_rotations(hyp, M, na, nb):
+    S = hyp.Sector(M, na, nb)
+    cre, ann, _ = synth.canonical_pool(M)
+    rng = np.random.default_rng(M)
+    psi = synth.random_state(S.dim, 3)
+    ref = psi.copy()
+    d = _dev(psi)
+    try:
+        hyp.set_pool_kind("qubit")
+        for k in rng.choice(cre.size, size=12, replace=False):
+            th = float(rng.uniform(-1, 1))
+            with oracle.qubit_excitations():
+                ref = oracle.rotate(M, na, nb, cre[k], ann[k], th, ref)
+            hyp.hyp_apply_excitation(S, int(cre[k]), int(ann[k]), th, d)
+    finally:
+        hyp.set_pool_kind("fermionic")
+    assert np.abs(d.cpu().numpy() - ref).max() <= 1e-13
+
+
+def test_qeb_batched(hyp):
+    """Four instances: full pools (transition values) and candidate subsets
+    (fused persistent launch) with qubit excitations against the oracle."""
+    jobs, refs = [], []
+    for i, (M, na, nb) in enumerate([(4, 2, 2), (5, 2, 3), (6, 3, 3), (6, 2, 3)]):
+        S, H, (x, z, c) = _ham(hyp, M, na, nb, 800 + i)
+        cre, ann, _ = synth.canonical_pool(M)
+        if i % 2:
+            k = np.random.default_rng(i).choice(cre.size, size=cre.size // 5, replace=False)
+            cre, ann = cre[k], ann[k]
+        psi = synth.random_state(S.dim, 40 + i)
+        sig = oracle.apply_h(M, na, nb, x, z, c, psi)
+        with oracle.qubit_excitations():
+            refs.append(oracle.pool_gradients(M, na, nb, cre, ann, psi, sig))
+        g = torch.empty(cre.size, dtype=torch.float64, device="cuda")
+        jobs.append((S, hyp.exc_tensor(cre, ann), _dev(psi), _dev(sig), g))
+    try:
+        hyp.set_pool_kind("qubit")
+        hyp.hyp_pool_gradients_batched(jobs)
+        torch.cuda.synchronize()
+    finally:
+        hyp.set_pool_kind("fermionic")
+    for (S, ops, psi, sig, g), ref in zip(jobs, refs):
+        assert np.abs(g.cpu().numpy() - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_qeb_adapt_16q(hyp):
+    """ADAPT-VQE with the QEB pool on the 16-qubit workload, 12 iterations,
+    against the oracle loop run with qubit excitations (teacher-forced inside
+    exact ties, as in the fermionic ADAPT tests)."""
+    w = synth.WORKLOADS["h8_16q"]
+    x, z, c, h, g = synth.hamiltonian(w)
+    cre, ann, _ = synth.canonical_pool(w.n_orb)
+    S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    n_iter = 12
+    try:
+        hyp.set_pool_kind("qubit")
+        A = hyp.Adapt(H, cre, ann, max_iter=n_iter + 1)
+        recs = [A.iterate() for _ in range(n_iter)]
+    finally:
+        hyp.set_pool_kind("fermionic")
+    sel = [r["selected"] for r in recs]
+    assert min(sel) >= 0
+    prob = SectorProblem(w.n_orb, w.n_alpha, w.n_beta, x, z, c, cre, ann)
+
+    def force(it, gvec, own):
+        k = sel[it]
+        assert abs(gvec[k]) >= float(np.abs(gvec).max()) * (1 - 1e-6) - 1e-7, (it, k, own)
+        return k
+
+    with oracle.qubit_excitations():
+        log = run_adapt(prob, n_iter, force=force)
+    assert log.selected == sel
+    e_gpu = np.array([r["energy"] for r in recs])
+    assert np.abs(e_gpu - np.array(log.energies)).max() < 1e-9
+    assert np.all(np.diff(e_gpu) <= 1e-10)

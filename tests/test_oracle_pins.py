@@ -424,3 +424,43 @@ def test_dense_sector_problem_equals_plain():
     basis = brute.sector_basis(w.n_orb, w.n_alpha, w.n_beta)
     efci = brute.fci(brute.sector_matrix(brute.fermion_hamiltonian(h, g), basis))
     assert np.all(np.diff(l2.energies) <= 1e-12) and min(l2.energies) >= efci - 1e-10
+
+
+@pytest.mark.parametrize("M,na,nb", [(3, 1, 2), (4, 2, 2)])
+def test_qubit_excitations_equal_kron_matrices(M, na, nb):
+    """Qubit-excitation (QEB) generators of the oracle, pair by pair, equal the
+    sector block of the Kronecker-product matrix prod sigma^+ prod sigma^- -
+    h.c.; the fermionic generators differ from them only in signs."""
+    n = 2 * M
+    basis = brute.sector_basis(M, na, nb)
+    cre, ann, _ = synth.canonical_pool(M)
+    rng = np.random.default_rng(M)
+    pick = rng.choice(cre.size, size=min(24, cre.size), replace=False)
+    dim = len(basis)
+    for k in pick:
+        Aq = brute.sector_matrix(brute.qubit_generator_matrix(int(cre[k]), int(ann[k]), n), basis).real
+        Af = brute.sector_matrix(brute.generator_matrix(int(cre[k]), int(ann[k]), n), basis).real
+        with oracle.qubit_excitations():
+            cols = np.stack([oracle.apply_generator(M, na, nb, cre[k], ann[k], np.eye(dim)[j]) for j in range(dim)], 1)
+        assert np.array_equal(cols, Aq), k
+        assert np.array_equal(np.abs(Aq), np.abs(Af)), k
+    # the context restores the fermionic kind
+    e = np.eye(dim)[0]
+    k = int(pick[0])
+    assert np.array_equal(oracle.apply_generator(M, na, nb, cre[k], ann[k], e),
+                          brute.sector_matrix(brute.generator_matrix(int(cre[k]), int(ann[k]), n), basis).real[:, 0])
+
+
+def test_qubit_single_pauli_form():
+    """A QEB single on qubits (a, c) is (i/2)(X_a Y_c - Y_a X_c) up to the
+    orientation sign of the generator (the textbook form of the qubit single
+    excitation, a real antisymmetric matrix): checked densely on four qubits."""
+    n = 4
+    for a, c in [(0, 1), (0, 3), (1, 2)]:
+        A = brute.qubit_generator_matrix(1 << c, 1 << a, n).toarray()
+        x = (1 << a) | (1 << c)
+        P1 = brute.pauli_kron(x, 1 << c, n).toarray()  # X_a Y_c
+        P2 = brute.pauli_kron(x, 1 << a, n).toarray()  # Y_a X_c
+        B = 0.5j * (P1 - P2)
+        assert np.allclose(A, B, atol=1e-15) or np.allclose(A, -B, atol=1e-15)
+        assert np.allclose(A, -A.T.conj())
