@@ -124,6 +124,8 @@ def main():
                     help="screened FP32 vs plain FP64 ADAPT iterations on the workload (JSON lines)")
     ap.add_argument("--adapt-early", type=int, default=0, metavar="ITERS",
                     help="plain FP64 ADAPT from Hartree-Fock, support skipping on, then off")
+    ap.add_argument("--csr", action="store_true",
+                    help="materialised CSR SpMV against the matrix-free product (24- and 28-qubit workloads)")
     ap.add_argument("--batch", action="store_true",
                     help="full pool-gradient sweeps of the eight uneven batch instances: one persistent batched "
                          "launch (autotuned tile) against per-instance sweeps (JSON line)")
@@ -156,6 +158,9 @@ def main():
         return
     if args.batch:
         batch_bench()
+        return
+    if args.csr:
+        csr_bench()
         return
     w = synth.WORKLOADS[args.workload]
     if args.fp32_study:
@@ -465,6 +470,47 @@ def adapt_compare(w, n_iter, shadow=False):
                       "dE": A32.energy_fp64() - A64.energy_fp64(), "final_E_screened_polished_fp64": rp["energy"],
                       "dE_polished": rp["energy"] - A64.energy_fp64(), "polish_s": round(time.time() - t4, 2),
                       "polish_evals": rp["n_evals"]}), flush=True)
+
+
+def csr_bench(reps=5):
+    """The paper's storage (the sector Hamiltonian materialised in CSR)
+    against the matrix-free product on the same state: build time, SpMV and
+    H psi times (HIP events), bytes; the 28-qubit CSR is refused for memory."""
+    import torch
+    import synth
+    import paper_2604_01176_amd as hyp
+
+    for name in ("h12_24q", "h14_28q"):
+        w = synth.WORKLOADS[name]
+        x, z, c, _, _ = synth.hamiltonian(w)
+        S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+        H = hyp.Hamiltonian(S, x, z, c)
+        psi = torch.from_numpy(synth.random_state(S.dim, 7)).cuda()
+        out = {"workload": name, "dim": S.dim}
+        try:
+            t0 = time.perf_counter()
+            A = hyp.CsrMatrix(H)
+            out["build_s"] = round(time.perf_counter() - t0, 3)
+        except hyp.HypError as e:
+            out["csr"] = f"refused: {e}"
+            print(json.dumps(out), flush=True)
+            continue
+        out["nnz"] = A.nnz
+        out["csr_gb"] = round(A.nnz * 12 / 1e9, 2)
+        y1, y2 = A.apply(psi), H.apply(psi)
+        for tag, fn in (("csr_spmv_ms", lambda: A.apply(psi, y1)), ("matrix_free_ms", lambda: H.apply(psi, y2))):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out[tag] = round(e0.elapsed_time(e1) / reps, 3)
+        out["csr_stream_gbs"] = round(A.nnz * 12 / (out["csr_spmv_ms"] * 1e-3) / 1e9, 1)
+        out["max_rel_diff"] = float((y1 - y2).norm() / y2.norm())
+        print(json.dumps(out), flush=True)
+        A.close()
 
 
 def batch_bench(reps=5):

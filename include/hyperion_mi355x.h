@@ -167,6 +167,28 @@ hyp_status hyp_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* si
  * is 0 or 1. */
 hyp_status hyp_set_support_skip(int on);
 
+/* Materialised sector Hamiltonian in CSR form, the paper's storage of H
+ * ("Sparse State-Vector Emulation", Table 1 gives its size), kept as a
+ * comparison for the matrix-free product.  Every row holds the same L
+ * entries (diagonal; alpha singles and doubles; beta singles and doubles;
+ * alpha-beta doubles; each column once, in that order): row_ptr[d] = d L,
+ * int32 columns, FP64 values, all in device memory owned by the library.
+ * hyp_csr_build: from a structured Hamiltonian (HYP_ERR_UNSUPPORTED for the
+ * generic kind); HYP_ERR_NOMEM, with the byte count in hyp_last_error(),
+ * when 12 bytes per nonzero plus the row pointers do not fit in free device
+ * memory with a 2 GiB margin (24 qubits: 18.6 GB; 28 qubits would need
+ * 478 GB).  Synchronous on `stream`.
+ * hyp_csr_apply: sigma = H psi, one wave per row, FP64 accumulation (HYP_F32:
+ * FP32 storage and products).  psi and sigma must not alias.
+ * hyp_csr_export: synchronous copy to host arrays of dim + 1, nnz and nnz
+ * elements.  hyp_csr_nnz: -1 for NULL. */
+typedef struct hyp_csr_s* hyp_csr;
+hyp_status hyp_csr_build(hyp_ham h, void* stream, hyp_csr* out);
+hyp_status hyp_csr_apply(hyp_csr m, hyp_dtype dtype, const void* psi_dev, void* sigma_dev, void* stream);
+hyp_status hyp_csr_export(hyp_csr m, int64_t* row_ptr, int32_t* col, double* val);
+int64_t hyp_csr_nnz(hyp_csr m);
+hyp_status hyp_csr_destroy(hyp_csr m);
+
 /* *out_dev = <a|b> = sum_i a_i b_i with FP64 accumulation (the sparse inner
  * product / expectation value of "General Framework for Variational
  * Algorithms", E = <psi|H psi>).  out_dev: one device double.  Scratch. */

@@ -155,6 +155,44 @@ class Hamiltonian:
             pass
 
 
+class CsrMatrix:
+    """hyp_csr: the sector Hamiltonian materialised in CSR form (comparison
+    for the matrix-free product)."""
+
+    def __init__(self, ham: Hamiltonian):
+        m = ctypes.c_void_p()
+        check(_lib.load().hyp_csr_build(ham._h, _stream(), ctypes.byref(m)))
+        self._m = m
+        self.dim = ham.sector.dim
+        self.nnz = int(_lib.load().hyp_csr_nnz(m))
+
+    def apply(self, psi, out=None):
+        if out is None:
+            out = _torch().empty_like(psi)
+        check(_lib.load().hyp_csr_apply(self._m, _dtype_code(psi), _dev_ptr(psi, self.dim, "psi"),
+                                        _dev_ptr(out, self.dim, "sigma"), _stream()))
+        return out
+
+    def export(self):
+        """(row_ptr, col, val) host arrays."""
+        rp = np.empty(self.dim + 1, dtype=np.int64)
+        col = np.empty(self.nnz, dtype=np.int32)
+        val = np.empty(self.nnz, dtype=np.float64)
+        check(_lib.load().hyp_csr_export(self._m, rp.ctypes.data, col.ctypes.data, val.ctypes.data))
+        return rp, col, val
+
+    def close(self):
+        if getattr(self, "_m", None):
+            _lib.load().hyp_csr_destroy(self._m)
+            self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def hyp_assemble_pauli(h, g, e_core: float = 0.0):
     """Device-side Jordan-Wigner assembly of the integrals (hyp_assemble_pauli):
     (x, z, c) as host numpy arrays, sorted by (x, z)."""

@@ -78,6 +78,11 @@ SIGNATURES = {
     "hyp_set_sweep_mode": (_ci, [_ci]),
     "hyp_set_support_skip": (_ci, [_ci]),
     "hyp_set_pool_kind": (_ci, [_ci]),
+    "hyp_csr_build": (_ci, [_vp, _vp, ctypes.POINTER(_vp)]),
+    "hyp_csr_apply": (_ci, [_vp, _ci, _vp, _vp, _vp]),
+    "hyp_csr_export": (_ci, [_vp, _vp, _vp, _vp]),
+    "hyp_csr_nnz": (_i64, [_vp]),
+    "hyp_csr_destroy": (_ci, [_vp]),
     "hyp_pool_gradients_batched": (_ci, [_vp, _ci, _vp, _vp]),
     "hyp_tune_pool_gradients": (_ci, [_vp, _ci, _ci, ctypes.POINTER(SweepTile), ctypes.POINTER(_d), _vp]),
     "hyp_mlp_create": (_ci, [_vp, _i64, ctypes.POINTER(_vp)]),

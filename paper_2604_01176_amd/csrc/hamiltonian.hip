@@ -639,27 +639,6 @@ __global__ void k_generic(GenericArgs a) {
 
 // ---------------------------------------------------------------- launch
 
-struct HamWork {
-  void* psi_t = nullptr;      // transposed psi, storage size of the largest dtype (8 B)
-  double* part_a = nullptr;   // [da][db]
-  double* part_b = nullptr;   // [db][da]
-  // same-spin string-space matrices (built once per Hamiltonian)
-  int* a_rank = nullptr;
-  double* a_coef = nullptr;
-  int a_nent = 0;
-  int* b_rank = nullptr;
-  double* b_coef = nullptr;
-  int b_nent = 0;
-  // support skipping: row flags of psi ([db] beta rows, then [da] alpha
-  // columns) and the support-restricted copies of the same-spin matrices
-  uint32_t* nz = nullptr;
-  int* ca_rank = nullptr;
-  double* ca_coef = nullptr;
-  int* ca_n = nullptr;
-  int* cb_rank = nullptr;
-  double* cb_coef = nullptr;
-  int* cb_n = nullptr;
-};
 
 static int g_support_skip = 1;  // process-wide: restrict H psi to psi's row and column support
 
@@ -1238,6 +1217,7 @@ hyp_status hyp_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* sigma
 
 namespace hyp {
 Ham* ham_of(hyp_ham h) { return h ? &h->h : nullptr; }
+HamWork* work_of(hyp_ham h) { return h ? &h->w : nullptr; }
 bool support_skip() { return g_support_skip != 0; }
 
 hyp_status apply_h_internal(hyp_ham hh, hyp_dtype dtype, const void* psi, void* sigma,

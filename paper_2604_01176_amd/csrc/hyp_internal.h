@@ -209,6 +209,30 @@ __device__ inline T lds_load(uint32_t a) {
 // shared entry points between translation units
 Sector* sector_of(hyp_sector h);
 Ham* ham_of(hyp_ham h);
+
+// Workspace and string-space matrices of a structured Hamiltonian.
+struct HamWork {
+  void* psi_t = nullptr;      // transposed psi, storage size of the largest dtype (8 B)
+  double* part_a = nullptr;   // [da][db]
+  double* part_b = nullptr;   // [db][da]
+  // same-spin string-space matrices (built once per Hamiltonian)
+  int* a_rank = nullptr;
+  double* a_coef = nullptr;
+  int a_nent = 0;
+  int* b_rank = nullptr;
+  double* b_coef = nullptr;
+  int b_nent = 0;
+  // support skipping: row flags of psi ([db] beta rows, then [da] alpha
+  // columns) and the support-restricted copies of the same-spin matrices
+  uint32_t* nz = nullptr;
+  int* ca_rank = nullptr;
+  double* ca_coef = nullptr;
+  int* ca_n = nullptr;
+  int* cb_rank = nullptr;
+  double* cb_coef = nullptr;
+  int* cb_n = nullptr;
+};
+HamWork* work_of(hyp_ham h);
 hyp_status ensure_binom();
 hyp_status validate_exc(const Sector* S, hyp_exc op);
 hyp_status pair_scratch(Sector* S, size_t n_doubles, double** out);
