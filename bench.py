@@ -118,6 +118,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle leg (0 disables it)")
     ap.add_argument("--no-sweep", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the near-Hartree-Fock and assembly measurements (profiling runs: keeps every "
+                         "launch of the step's kernels at the benchmark state)")
     ap.add_argument("--fp32-study", type=int, default=0, metavar="ITERS",
                     help="FP32-storage vs FP64 error study over ITERS ADAPT iterations (JSON lines)")
     ap.add_argument("--adapt-compare", type=int, default=0, metavar="ITERS",
@@ -242,6 +245,87 @@ def main():
     # support skipping near Hartree-Fock (an early-ADAPT state: HF and 24
     # determinants one pool excitation away), H psi and the full sweep,
     # skipping on against off
+    sup, asm = None, None
+    if not args.no_extras:
+        sup, asm = extras(hyp, torch, np, synth, S, H, ops, grad, w, M, na, nb)
+
+    hpsi_kernels = ("k_clear_u32", "k_transpose", "k_ss_compact", "k_ss_apply", "k_mixed")
+    hpsi_ms = sum(prof.get(k, (0.0, 0))[0] for k in hpsi_kernels) / args.steps
+    hpsi_bytes = hpsi_gather_bytes(m)
+    value = hpsi_bytes / (hpsi_ms * 1e-3) / 1e9
+    sweep_kernels = ("k_pool_grad", "k_sum_chunks", "k_tdens", "k_tdens_reduce_ab", "k_tdens_reduce_a",
+                     "k_tdens_final", "k_tdens_rows", "k_tdens_rows_final", "k_eb_rows", "k_gram_grad",
+                     "k_tdens_grad", "k_widen", "rocblas_dgemm_gram_a", "rocblas_dgemm_gram_b",
+                     "k_zero_u32", "k_support", "k_list_nz", "k_rows_compact", "k_gather_rows", "k_gather_cols",
+                     "k_zero_f64")
+    sweep_ms = sum(prof.get(k, (0.0, 0))[0] for k in sweep_kernels) / args.steps
+
+    # dominant kernel of the step and its roofline
+    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    dom_ms = prof[dom][0] / prof[dom][1]
+    roof = roofline(dom, dom_ms, m)
+    roof["traffic"] = measured_traffic(w.name, dom)
+    cpu = None
+    if args.cpu_seconds > 0:
+        import oracle
+        rng = np.random.default_rng(0)
+        # calibrate on growing samples until one takes >= 1 s, then size the
+        # timed sample to about cpu_seconds of oracle work
+        n_try, dt = 256, 0.0
+        while True:
+            t = time.time()
+            oracle.apply_h(M, na, nb, x, z, c, psi_h, out_idx=rng.integers(0, S.dim, n_try))
+            dt = time.time() - t
+            if dt >= 1.0 or n_try >= 4_000_000:
+                break
+            n_try *= 4
+        n_rows = int(max(256, min(20_000_000, n_try * args.cpu_seconds / max(dt, 1e-6))))
+        idx = rng.integers(0, S.dim, n_rows)
+        t = time.time()
+        oracle.apply_h(M, na, nb, x, z, c, psi_h, out_idx=idx)
+        dt = time.time() - t
+        row_bytes = (m["conn"] + 1) * 8
+        if asm is not None:
+            from oracle import jw
+            t_j = time.time()
+            jw.jw_pauli_list(*synth.integrals(w.n_orb, w.seed))
+            asm["oracle_s"] = round(time.time() - t_j, 2)
+        cpu = {"value": round(n_rows * row_bytes / dt / 1e9, 4), "unit": "GB/s",
+               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+               "kind": "oracle",
+               "sample": f"{n_rows} random output rows of H psi ({dt:.1f} s), gather-model bytes"}
+
+    out = {
+        "metric": "H psi GB/s (gather model) + pool-grad evals/s",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {2 * M} qubits, sector ({na},{nb}), dim {m['dim']}, "
+                               f"{m['T']} Pauli terms, pool {m['pool']}",
+                   "parallelism": "1 GPU"},
+        "hpsi_ms": round(hpsi_ms, 3), "hpsi_threads": int(hpsi_threads),
+        "hpsi_fp32_ms": round(hpsi32_ms, 3), "hpsi_fp32_threads": int(threads32),
+        "hpsi_frac_hbm_gather_model": round(value / HBM_PEAK_GBS, 4),
+        "pool_grad_evals_per_s": round(m["pool"] / (sweep_ms * 1e-3), 1) if sweep_ms > 0 else None,
+        "sweep_ms": round(sweep_ms, 3),
+        "support_skip_near_hf": sup,
+        "pauli_assembly": asm,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def extras(hyp, torch, np, synth, S, H, ops, grad, w, M, na, nb):
+    """Support skipping near Hartree-Fock and the device-side assembly."""
     bits = synth.near_hf_bits(M, na, nb, 24, seed=3)
     nidx = np.unique(S.rank(bits))
     rng_s = np.random.default_rng(11)
@@ -280,78 +364,7 @@ def main():
     n_asm = hyp.hyp_assemble_pauli(h_int, g_int)[0].size
     asm = {"terms": int(n_asm), "device_ms": round((time.perf_counter() - t_a) * 1e3, 2)}
 
-    hpsi_kernels = ("k_clear_u32", "k_transpose", "k_ss_compact", "k_ss_apply", "k_mixed")
-    hpsi_ms = sum(prof.get(k, (0.0, 0))[0] for k in hpsi_kernels) / args.steps
-    hpsi_bytes = hpsi_gather_bytes(m)
-    value = hpsi_bytes / (hpsi_ms * 1e-3) / 1e9
-    sweep_kernels = ("k_pool_grad", "k_sum_chunks", "k_tdens", "k_tdens_reduce_ab", "k_tdens_reduce_a",
-                     "k_tdens_final", "k_tdens_rows", "k_tdens_rows_final", "k_eb_rows", "k_gram_grad",
-                     "k_tdens_grad", "k_widen", "rocblas_dgemm_gram_a", "rocblas_dgemm_gram_b",
-                     "k_zero_u32", "k_support", "k_list_nz", "k_rows_compact", "k_gather_rows", "k_gather_cols",
-                     "k_zero_f64")
-    sweep_ms = sum(prof.get(k, (0.0, 0))[0] for k in sweep_kernels) / args.steps
-
-    # dominant kernel of the step and its roofline
-    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
-    dom_ms = prof[dom][0] / prof[dom][1]
-    roof = roofline(dom, dom_ms, m)
-    roof["traffic"] = measured_traffic(w.name, dom)
-    cpu = None
-    if args.cpu_seconds > 0:
-        import oracle
-        rng = np.random.default_rng(0)
-        # calibrate on growing samples until one takes >= 1 s, then size the
-        # timed sample to about cpu_seconds of oracle work
-        n_try, dt = 256, 0.0
-        while True:
-            t = time.time()
-            oracle.apply_h(M, na, nb, x, z, c, psi_h, out_idx=rng.integers(0, S.dim, n_try))
-            dt = time.time() - t
-            if dt >= 1.0 or n_try >= 4_000_000:
-                break
-            n_try *= 4
-        n_rows = int(max(256, min(20_000_000, n_try * args.cpu_seconds / max(dt, 1e-6))))
-        idx = rng.integers(0, S.dim, n_rows)
-        t = time.time()
-        oracle.apply_h(M, na, nb, x, z, c, psi_h, out_idx=idx)
-        dt = time.time() - t
-        row_bytes = (m["conn"] + 1) * 8
-        from oracle import jw
-        t_j = time.time()
-        jw.jw_pauli_list(h_int, g_int)
-        asm["oracle_s"] = round(time.time() - t_j, 2)
-        cpu = {"value": round(n_rows * row_bytes / dt / 1e9, 4), "unit": "GB/s",
-               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
-               "kind": "oracle",
-               "sample": f"{n_rows} random output rows of H psi ({dt:.1f} s), gather-model bytes"}
-
-    out = {
-        "metric": "H psi GB/s (gather model) + pool-grad evals/s",
-        "value": round(value, 2),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(step_ms, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"{w.name}: {2 * M} qubits, sector ({na},{nb}), dim {m['dim']}, "
-                               f"{m['T']} Pauli terms, pool {m['pool']}",
-                   "parallelism": "1 GPU"},
-        "hpsi_ms": round(hpsi_ms, 3), "hpsi_threads": int(hpsi_threads),
-        "hpsi_fp32_ms": round(hpsi32_ms, 3), "hpsi_fp32_threads": int(threads32),
-        "hpsi_frac_hbm_gather_model": round(value / HBM_PEAK_GBS, 4),
-        "pool_grad_evals_per_s": round(m["pool"] / (sweep_ms * 1e-3), 1) if sweep_ms > 0 else None,
-        "sweep_ms": round(sweep_ms, 3),
-        "support_skip_near_hf": sup,
-        "pauli_assembly": asm,
-        "roofline": roof,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    return sup, asm
 
 
 def adapt_early(w, n_iter):
