@@ -127,6 +127,8 @@ def main():
                     help="screened FP32 vs plain FP64 ADAPT iterations on the workload (JSON lines)")
     ap.add_argument("--adapt-early", type=int, default=0, metavar="ITERS",
                     help="plain FP64 ADAPT from Hartree-Fock, support skipping on, then off")
+    ap.add_argument("--skip-only", action="store_true",
+                    help="with --adapt-early: only the run with support skipping (longer trajectories)")
     ap.add_argument("--csr", action="store_true",
                     help="materialised CSR SpMV against the matrix-free product (24- and 28-qubit workloads)")
     ap.add_argument("--batch", action="store_true",
@@ -173,7 +175,7 @@ def main():
         adapt_compare(w, args.adapt_compare, args.shadow)
         return
     if args.adapt_early:
-        adapt_early(w, args.adapt_early)
+        adapt_early(w, args.adapt_early, args.skip_only)
         return
     M, na, nb = w.n_orb, w.n_alpha, w.n_beta
     t0 = time.time()
@@ -367,10 +369,13 @@ def extras(hyp, torch, np, synth, S, H, ops, grad, w, M, na, nb):
     return sup, asm
 
 
-def adapt_early(w, n_iter):
+def adapt_early(w, n_iter, skip_only=False):
     """Plain FP64 ADAPT iterations from Hartree-Fock (full sweep + BFGS),
     with support skipping on and then off: per-iteration wall time, its
-    gradient and optimiser phases, and the selections (which must agree)."""
+    gradient and optimiser phases, the state's fill (nonzero amplitudes over
+    the sector dimension), the cumulative time T_j and the paper's amortised
+    iteration coefficient j / sqrt(T_j), and the selections (which must
+    agree)."""
     import torch
     import synth
     import paper_2604_01176_amd as hyp
@@ -384,21 +389,32 @@ def adapt_early(w, n_iter):
     H.tune(probe, reps=1)
     del probe
     runs = {}
-    for on in (True, False):
+    psi = torch.empty(S.dim, dtype=torch.float64, device="cuda")
+    for on in ((True,) if skip_only else (True, False)):
         hyp.set_support_skip(on)
         A = hyp.Adapt(H, cre, ann, max_iter=n_iter + 1)
         rec = []
+        t_cum = 0.0
         for it in range(n_iter):
             torch.cuda.synchronize()
             t1 = time.time()
             r = A.iterate()
             t2 = time.time()
+            t_cum += t2 - t1
             rec.append(r)
+            A.state(psi)
+            fill = float((psi != 0).sum().item()) / S.dim
             print(json.dumps({"support_skip": on, "iteration": it, "selected": r["selected"], "E": r["energy"],
                               "grad_ms": round(r["grad_ms"], 1), "opt_ms": round(r["opt_ms"], 1),
-                              "n_evals": r["n_evals"], "iter_s": round(t2 - t1, 3)}), flush=True)
+                              "n_evals": r["n_evals"], "iter_s": round(t2 - t1, 3), "fill": fill,
+                              "T_j_s": round(t_cum, 3), "j_over_sqrt_T": round((it + 1) / t_cum ** 0.5, 3)}),
+                  flush=True)
+            if r["selected"] < 0:
+                break
         runs[on] = rec
     hyp.set_support_skip(True)
+    if skip_only:
+        return
     same = [a["selected"] == b["selected"] for a, b in zip(runs[True], runs[False])]
     print(json.dumps({"same_selections": same,
                       "dE_final": runs[True][-1]["energy"] - runs[False][-1]["energy"]}), flush=True)
