@@ -292,7 +292,8 @@ typedef struct {
   int32_t max_iter;   /* maximum ansatz length (buffer capacity), 1..4096 */
   int32_t max_bfgs;   /* BFGS iterations per ADAPT iteration */
   int32_t use_graph;  /* capture each evaluation in a hipGraph */
-  int32_t reserved;
+  int32_t recycle_hessian;  /* 1: BFGS starts from the previous iteration's inverse-Hessian estimate
+                               (identity for the appended parameter); 0: from the identity */
   double tie_tol;     /* relative tie tolerance of the selection, in [0, 1) */
   double gtol;        /* BFGS stop: max_i |dE/dtheta_i| <= gtol, > 0 */
   double gmax_stop;   /* no operator is added when max|g| < gmax_stop */

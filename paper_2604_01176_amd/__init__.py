@@ -307,12 +307,13 @@ class Adapt:
     dtype "f64" or "f32" (FP32 storage, FP64 accumulation).  Defaults follow
     the selection/optimiser readings: tie_tol 1e-9 (f64) / 1e-5 (f32),
     BFGS gtol 1e-9 (f64) / 1e-5 (f32, the gradient's noise floor), early stop
-    when max|g| < 1e-10.
+    when max|g| < 1e-10; BFGS starts from the previous iteration's
+    inverse-Hessian estimate (recycle_hessian).
     """
 
     def __init__(self, ham: Hamiltonian, cre, ann, dtype: str = "f64", max_iter: int = 64,
                  max_bfgs: int = 1000, use_graph: bool = True, tie_tol=None, gtol=None,
-                 gmax_stop: float = 1e-10):
+                 gmax_stop: float = 1e-10, recycle_hessian: bool = True):
         f32 = dtype == "f32"
         self.dtype = dtype
         self.ham = ham
@@ -321,7 +322,7 @@ class Adapt:
         for i, (c_, a_) in enumerate(zip(np.asarray(cre).tolist(), np.asarray(ann).tolist())):
             pool[i].cre, pool[i].ann = int(c_), int(a_)
         o = _lib.AdaptOpts(max_iter=max_iter, max_bfgs=max_bfgs, use_graph=1 if use_graph else 0,
-                           reserved=0, tie_tol=(1e-5 if f32 else 1e-9) if tie_tol is None else tie_tol,
+                           recycle_hessian=1 if recycle_hessian else 0, tie_tol=(1e-5 if f32 else 1e-9) if tie_tol is None else tie_tol,
                            gtol=(1e-5 if f32 else 1e-9) if gtol is None else gtol,
                            gmax_stop=gmax_stop)
         h = ctypes.c_void_p()

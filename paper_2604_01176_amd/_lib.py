@@ -21,7 +21,7 @@ class HypExc(ctypes.Structure):
 
 class AdaptOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("max_bfgs", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("recycle_hessian", ctypes.c_int32),
                 ("tie_tol", ctypes.c_double), ("gtol", ctypes.c_double),
                 ("gmax_stop", ctypes.c_double)]
 

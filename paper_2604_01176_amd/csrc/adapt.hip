@@ -103,6 +103,10 @@ struct Adapt {
   std::vector<double> theta;
   std::vector<double> last_grad;   // pool gradient of the last iteration (NaN = not computed)
   int n_evals = 0;
+  // inverse-Hessian estimate left by the last optimisation (n_rec x n_rec),
+  // the start of the next one when the ansatz has grown by one parameter
+  std::vector<double> h_rec;
+  size_t n_rec = 0;
 };
 
 static hyp_status enqueue_eval(Adapt* A, int j) {
@@ -310,6 +314,12 @@ static hyp_status bfgs(Adapt* A, std::vector<double>& x, double* fout, int* iter
   if (r != HYP_OK) return r;
   std::vector<double> Hi(n * n, 0.0);
   for (size_t i = 0; i < n; ++i) Hi[i * n + i] = 1.0;
+  if (A->o.recycle_hessian && n > 1 && A->n_rec + 1 == n && A->h_rec.size() == A->n_rec * A->n_rec) {
+    // the previous optimisation's estimate for the old parameters, identity
+    // for the appended one (the old parameters keep their order)
+    for (size_t i = 0; i + 1 < n; ++i)
+      for (size_t k = 0; k + 1 < n; ++k) Hi[i * n + k] = A->h_rec[i * (n - 1) + k];
+  }
   int it = 0, stall = 0;
   *conv = 0;
   for (; it < A->o.max_bfgs; ++it) {
@@ -371,9 +381,12 @@ static hyp_status bfgs(Adapt* A, std::vector<double>& x, double* fout, int* iter
   *fout = f;
   *iters = it;
   *ginf = infnorm(g);
-  // converged: the gradient test held, or the line search could not improve
-  // on a point whose gradient is at the precision floor (100 gtol)
-  *conv = (*ginf <= A->o.gtol || (*conv == 0 && *ginf <= 100.0 * A->o.gtol)) ? 1 : 0;
+  A->h_rec = Hi;
+  A->n_rec = n;
+  // converged: the gradient test held, the energy stopped changing with the
+  // gradient within 10 gtol (*conv set in the loop), or the optimisation
+  // ended at a point whose gradient is at the precision floor (100 gtol)
+  *conv = (*ginf <= A->o.gtol || *conv == 1 || *ginf <= 100.0 * A->o.gtol) ? 1 : 0;
   return HYP_OK;
 }
 
@@ -432,7 +445,7 @@ hyp_status hyp_adapt_create(hyp_ham ham, hyp_dtype dtype, const hyp_exc* pool, i
   if (dtype != HYP_F64 && dtype != HYP_F32) return fail(HYP_ERR_ARG, "hyp_adapt_create: bad dtype");
   if (n_pool < 1 || n_pool > (1 << 24)) return fail(HYP_ERR_ARG, "hyp_adapt_create: n_pool out of range");
   if (opts->max_iter < 1 || opts->max_iter > 4096 || opts->max_bfgs < 0 || !(opts->gtol > 0) ||
-      !(opts->tie_tol >= 0) || opts->tie_tol >= 1)
+      !(opts->tie_tol >= 0) || opts->tie_tol >= 1 || (opts->recycle_hessian != 0 && opts->recycle_hessian != 1))
     return fail(HYP_ERR_ARG, "hyp_adapt_create: bad options");
   Sector* S = H->sec;
   for (int64_t k = 0; k < n_pool; ++k) {
@@ -655,6 +668,8 @@ hyp_status hyp_adapt_set_ansatz(hyp_adapt h, const int32_t* ops, const double* t
       return fail(HYP_ERR_ARG, "hyp_adapt_set_ansatz: bad entry");
   A.ops.assign(ops, ops + n);
   A.theta.assign(theta, theta + n);
+  A.h_rec.clear();
+  A.n_rec = 0;
   drop_graph(&A);
   return HYP_OK;
 }
