@@ -481,7 +481,9 @@ def adapt_compare(w, n_iter, shadow=False):
                                                          "n_evals": r64["n_evals"],
                                                          "iter_s": round(t2 - t1, 2)},
                           "screened_fp32": {"selected": info["selected"], "E": info["energy"],
-                                            "judge": info["judge"], "fallback": info["fallback"],
+                                            "judge": info["judge"], "cheaper_full": info["cheaper_full"],
+                                            "fallback": info["fallback"],
+                                            "grad_phase_ms": round(info["grad_phase_ms"], 1),
                                             "n_exact": info["n_exact"], "grad_ms": round(info["grad_ms"], 1),
                                             "opt_ms": round(info["opt_ms"], 1), "n_evals": info["n_evals"],
                                             "iter_s": round(t3 - t2, 2),

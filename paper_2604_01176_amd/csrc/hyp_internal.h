@@ -241,6 +241,9 @@ hyp_status apply_h_internal(hyp_ham h, hyp_dtype dt, const void* psi, void* sigm
 bool prefer_full_sweep(const Sector* S, int64_t n_ops);
 // process-wide support-skipping switch (hyp_set_support_skip)
 bool support_skip();
+// psi's support flags ([db] beta rows, then [da] alpha columns), device
+// scratch of the sweep valid until its next use on this device
+hyp_status support_flags(Sector* S, hyp_dtype dt, const void* psi, const uint32_t** flags, hipStream_t st);
 hyp_status launch_pool_gradients(Sector* S, hyp_dtype dt, const hyp_exc* ops_dev, int64_t n_ops,
                                  const void* psi, const void* sig, double* grad, hipStream_t st);
 hyp_status launch_rotate(Sector* S, hyp_dtype dt, hyp_exc op, double theta,

@@ -122,6 +122,8 @@ __device__ inline double ld(const T* p, int64_t i) {
 template <typename T>
 __global__ void __launch_bounds__(kPairThreads) k_pool_grad(SectorDev S, const hyp_exc* ops,
                                                            const T* psi, const T* sig,
+                                                           const uint32_t* __restrict__ nzb,
+                                                           const uint32_t* __restrict__ nza,
                                                            double* part) {
   __shared__ uint32_t lst[kListMax];
   __shared__ double red[kPairThreads / 64];
@@ -146,6 +148,10 @@ __global__ void __launch_bounds__(kPairThreads) k_pool_grad(SectorDev S, const h
       rIb = rank_of(S.brank, Ib);
       sb = part_sign(c.pb.cm, c.pb.am, Jb) & S.fsign;
     }
+    // support skipping: a pair contributes only if psi[D] or psi[D'] can be
+    // nonzero (its beta row and alpha column both in psi's support)
+    const bool zJ = !nzb || nzb[rJb], zI = !nzb || nzb[rIb];
+    if (!zJ && !zI) continue;
     const int64_t oJ = (int64_t)rJb * S.da, oI = (int64_t)rIb * S.da;
     double rs = 0.0;
     for (int t = threadIdx.x; t < nA; t += blockDim.x) {
@@ -159,6 +165,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pool_grad(SectorDev S, const h
         rIa = (e >> 14) & 0x3fff;
         sa = (e >> 28) & 1;
       }
+      if (nza && !((zJ && nza[rJa]) || (zI && nza[rIa]))) continue;
       const int64_t D = oJ + rJa, Dp = oI + rIa;
       // sigma[D'] psi[D] - sigma[D] psi[D'] (FP32 storage: FP32 products)
       double v;
@@ -364,9 +371,14 @@ static hyp_status launch_pool_grad(Sector* S, const hyp_exc* ops, int64_t n_ops,
   double* part = nullptr;
   hyp_status r = pair_scratch(S, (size_t)n_ops * kPairChunks, &part);
   if (r != HYP_OK) return r;
+  const uint32_t* nz = nullptr;
+  if (support_skip()) {
+    r = support_flags(S, sizeof(T) == 4 ? HYP_F32 : HYP_F64, psi, &nz, st);
+    if (r != HYP_OK) return r;
+  }
   // grid.x is limited to 2^31-1, n_ops <= 40k here
   HYP_LAUNCH("k_pool_grad", k_pool_grad<T>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0, st,
-             S->dev(), ops, (const T*)psi, (const T*)sig, part);
+             S->dev(), ops, (const T*)psi, (const T*)sig, nz, nz ? nz + S->db : nullptr, part);
   HYP_LAUNCH("k_sum_chunks", k_sum_chunks, dim3((unsigned)((n_ops + 255) / 256)), dim3(256), 0, st, part,
              n_ops, 2.0, grad);
   HYP_HIP(hipGetLastError());

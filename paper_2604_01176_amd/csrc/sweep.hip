@@ -887,6 +887,45 @@ static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* 
   return HYP_OK;
 }
 
+// Row and column support flags of psi ([db] beta rows, then [da] alpha
+// columns) in this device's sweep scratch, valid until the next call on the
+// device; also sizes the support lists and their counters.
+hyp_status support_flags(Sector* S, hyp_dtype dt, const void* psi, const uint32_t** flags, hipStream_t st) {
+  int dev = 0;
+  HYP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(HYP_ERR_HIP, "device index out of range");
+  TScratch& ts = g_ts[dev];
+  const int64_t da = S->da, db = S->db;
+  const size_t nneed = (size_t)(da + db);
+  if (nneed > ts.nz_cap) {
+    HYP_HIP(hipDeviceSynchronize());
+    if (ts.nz) HYP_HIP(hipFree(ts.nz));
+    if (ts.lists) HYP_HIP(hipFree(ts.lists));
+    ts.nz = nullptr;
+    ts.lists = nullptr;
+    ts.nz_cap = 0;
+    HYP_HIP(hipMalloc(&ts.nz, nneed * sizeof(uint32_t)));
+    HYP_HIP(hipMalloc(&ts.lists, nneed * sizeof(int)));
+    ts.nz_cap = nneed;
+  }
+  if (!ts.cnt) {
+    HYP_HIP(hipMalloc(&ts.cnt, 2 * sizeof(int)));
+    HYP_HIP(hipHostMalloc((void**)&ts.hcnt, 2 * sizeof(int), hipHostMallocDefault));
+    HYP_HIP(hipEventCreateWithFlags(&ts.cnt_ready, hipEventDisableTiming));
+  }
+  HYP_LAUNCH("k_zero_u32", k_zero_u32, dim3((unsigned)std::min<int64_t>(1024, (da + db + 255) / 256)), dim3(256), 0,
+             st, ts.nz, (int)(da + db));
+  dim3 tg((unsigned)((da + 63) / 64), (unsigned)((db + 63) / 64));
+  if (dt == HYP_F64)
+    HYP_LAUNCH("k_support", k_support<double>, tg, dim3(256), 0, st, (const double*)psi, (int)db, (int)da, ts.nz,
+               ts.nz + db);
+  else
+    HYP_LAUNCH("k_support", k_support<float>, tg, dim3(256), 0, st, (const float*)psi, (int)db, (int)da, ts.nz,
+               ts.nz + db);
+  *flags = ts.nz;
+  return HYP_OK;
+}
+
 hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_ops, const void* psi,
                         const void* sig, double* grad, hipStream_t st, bool bins) {
   int dev = 0;
@@ -918,32 +957,9 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
   // psi's nonzero beta rows and alpha columns
   const bool skip = support_skip() && !bins;
   if (skip) {
-    const size_t nneed = (size_t)(da + db);
-    if (nneed > ts.nz_cap) {
-      HYP_HIP(hipDeviceSynchronize());
-      if (ts.nz) HYP_HIP(hipFree(ts.nz));
-      if (ts.lists) HYP_HIP(hipFree(ts.lists));
-      ts.nz = nullptr;
-      ts.lists = nullptr;
-      ts.nz_cap = 0;
-      HYP_HIP(hipMalloc(&ts.nz, nneed * sizeof(uint32_t)));
-      HYP_HIP(hipMalloc(&ts.lists, nneed * sizeof(int)));
-      ts.nz_cap = nneed;
-    }
-    if (!ts.cnt) {
-      HYP_HIP(hipMalloc(&ts.cnt, 2 * sizeof(int)));
-      HYP_HIP(hipHostMalloc((void**)&ts.hcnt, 2 * sizeof(int), hipHostMallocDefault));
-      HYP_HIP(hipEventCreateWithFlags(&ts.cnt_ready, hipEventDisableTiming));
-    }
-    HYP_LAUNCH("k_zero_u32", k_zero_u32, dim3((unsigned)std::min<int64_t>(1024, (da + db + 255) / 256)), dim3(256),
-               0, st, ts.nz, (int)(da + db));
-    dim3 tg((unsigned)((da + 63) / 64), (unsigned)((db + 63) / 64));
-    if (dt == HYP_F64)
-      HYP_LAUNCH("k_support", k_support<double>, tg, dim3(256), 0, st, (const double*)psi, (int)db, (int)da, ts.nz,
-                 ts.nz + db);
-    else
-      HYP_LAUNCH("k_support", k_support<float>, tg, dim3(256), 0, st, (const float*)psi, (int)db, (int)da, ts.nz,
-                 ts.nz + db);
+    const uint32_t* nz = nullptr;
+    hyp_status rs = support_flags(S, dt, psi, &nz, st);
+    if (rs != HYP_OK) return rs;
     HYP_LAUNCH("k_list_nz", k_list_nz, dim3(1), dim3(1024), 0, st, ts.nz, (int)db, ts.lists, ts.cnt);
     HYP_LAUNCH("k_list_nz", k_list_nz, dim3(1), dim3(1024), 0, st, ts.nz + db, (int)da, ts.lists + db, ts.cnt + 1);
     HYP_HIP(hipMemcpyAsync(ts.hcnt, ts.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));

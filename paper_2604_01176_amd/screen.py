@@ -23,6 +23,8 @@ from __future__ import annotations
 
 import ctypes
 
+import time
+
 import numpy as np
 
 from . import _lib
@@ -203,12 +205,19 @@ class Screen:
     """Screened ADAPT iterations for one problem."""
 
     def __init__(self, adapt: Adapt, sector: Sector, stat, qidx, mlp: MLP, K=512, audit=256,
-                 judge_every=10, seed=42, lr=1e-3, online=True):
+                 judge_every=10, seed=42, lr=1e-3, online=True, cost_policy=True):
+        """cost_policy: besides the judge iterations, take the exact full sweep
+        whenever the last full sweep's gradient phase took no longer than the
+        last screened one (near Hartree-Fock the support-restricted sweep is
+        cheaper than scoring the pool; the screen pays once the state fills)."""
         self.adapt = adapt
         self.fs = FeatureState(sector, stat, qidx)
         self.mlp = mlp
         self.K, self.audit, self.judge_every, self.seed, self.lr = K, audit, judge_every, seed, lr
         self.online = online
+        self.cost_policy = cost_policy
+        self.full_ms = None
+        self.screen_ms = None
         self.n = stat.shape[0]
         self.psi = None
         self.log = []
@@ -219,14 +228,23 @@ class Screen:
         largest |g| and whether the screened pick lies in its tie set."""
         torch = _torch()
         n = self.n
-        full = (it % self.judge_every == 0) or n <= self.K + self.audit
+        judge = (it % self.judge_every == 0) or n <= self.K + self.audit
+        cheaper = (self.cost_policy and not judge and self.full_ms is not None and self.screen_ms is not None
+                   and self.full_ms <= self.screen_ms)
+        full = judge or cheaper
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         self.psi = self.adapt.state(self.psi)
         X = self.fs.features(self.psi)
-        info = {"iteration": it, "judge": full, "fallback": False}
+        info = {"iteration": it, "judge": judge, "cheaper_full": cheaper, "fallback": False}
         g_shadow = None
         if shadow and not full:
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
             self.adapt.gradients(None)
             g_shadow = np.abs(self.adapt.last_gradients())
+            torch.cuda.synchronize()
+            shadow_ms = (time.perf_counter() - ts) * 1e3
         if full:
             rec = self.adapt.gradients(None)
             cand = np.arange(n)
@@ -243,6 +261,15 @@ class Screen:
                 info["fallback"] = True
                 rec = self.adapt.gradients(None)
                 cand = np.arange(n)
+        torch.cuda.synchronize()
+        phase_ms = (time.perf_counter() - t0) * 1e3
+        if g_shadow is not None:
+            phase_ms -= shadow_ms
+        if full:
+            self.full_ms = phase_ms
+        elif not info["fallback"]:
+            self.screen_ms = phase_ms
+        info["grad_phase_ms"] = phase_ms
         g = self.adapt.last_gradients()
         self.fs.update(g)
         if self.online:

@@ -250,7 +250,8 @@ def test_screened_adapt_fp32_vs_full_sweep(hyp, scr, trained, K, audit, online, 
     A32 = hyp.Adapt(H, cre, ann, dtype="f32", max_iter=n_iter + 1)
     stat, qidx = scr.static_features(w.n_orb, cre, ann, cls, h, g)
     net = trained.clone()  # online training must not leak into other tests
-    sc = scr.Screen(A32, S, stat, qidx, net, K=K, audit=audit, judge_every=5, seed=42, online=online)
+    sc = scr.Screen(A32, S, stat, qidx, net, K=K, audit=audit, judge_every=5, seed=42, online=online,
+                    cost_policy=False)
     A64 = hyp.Adapt(H, cre, ann, max_iter=n_iter + 1)
     agree_own, agree_plain, e32, e64 = 0, 0, [], []
     for it in range(n_iter):

@@ -172,34 +172,36 @@ GCASES = [(4, 2, 2), (5, 2, 3), (6, 3, 3), (8, 4, 4), (9, 5, 4), (3, 0, 2), (4, 
 
 @pytest.mark.parametrize("M,na,nb", GCASES)
 def test_sweep_support_skip(hyp, M, na, nb):
-    """Transition-value sweep restricted to psi's support (row pairs, identity
-    slices and both Gram sums) against the oracle, FP64 and FP32, and against
-    the unrestricted sweep."""
+    """Gradients restricted to psi's support, in the transition-value sweep
+    (row pairs, identity slices and both Gram sums) and in the pair kernel
+    (pairs whose two determinants lie outside the support skipped), against
+    the oracle, FP64 and FP32, and against the unrestricted computation."""
     h, g = synth.integrals(M, 300 + M)
     x, z, c = synth.jw_pauli_list(h, g)
     S = hyp.Sector(M, na, nb)
     cre, ann, _ = synth.canonical_pool(M)
     ops = hyp.exc_tensor(cre, ann)
     try:
-        hyp.set_sweep_mode("tdens")
-        for name, psi in _states(M, na, nb, S.da, S.db).items():
-            sig = oracle.apply_h(M, na, nb, x, z, c, psi)
-            ref = oracle.pool_gradients(M, na, nb, cre, ann, psi, sig)
-            got = {}
-            for on in (True, False):
-                hyp.set_support_skip(on)
-                got[on] = (hyp.hyp_pool_gradients(S, ops, _dev(psi), _dev(sig)).cpu().numpy(),
-                           hyp.hyp_pool_gradients(S, ops, _dev(psi, torch.float32),
-                                                  _dev(sig, torch.float32)).cpu().numpy())
-            hyp.set_support_skip(True)
-            if name == "zero":
-                assert all(np.all(v == 0.0) for pair in got.values() for v in pair), name
-                continue
-            scale = max(1.0, np.abs(ref).max())
-            for on, (g64, g32) in got.items():
-                assert np.abs(g64 - ref).max() <= 1e-12 * scale, (name, on)
-                assert np.abs(g32 - ref).max() <= 1e-5 * scale, (name, on)
-            assert np.abs(got[True][0] - got[False][0]).max() <= 1e-13 * scale, name
+        for mode in ("tdens", "pairs"):
+            hyp.set_sweep_mode(mode)
+            for name, psi in _states(M, na, nb, S.da, S.db).items():
+                sig = oracle.apply_h(M, na, nb, x, z, c, psi)
+                ref = oracle.pool_gradients(M, na, nb, cre, ann, psi, sig)
+                got = {}
+                for on in (True, False):
+                    hyp.set_support_skip(on)
+                    got[on] = (hyp.hyp_pool_gradients(S, ops, _dev(psi), _dev(sig)).cpu().numpy(),
+                               hyp.hyp_pool_gradients(S, ops, _dev(psi, torch.float32),
+                                                      _dev(sig, torch.float32)).cpu().numpy())
+                hyp.set_support_skip(True)
+                if name == "zero":
+                    assert all(np.all(v == 0.0) for pair in got.values() for v in pair), (mode, name)
+                    continue
+                scale = max(1.0, np.abs(ref).max())
+                for on, (g64, g32) in got.items():
+                    assert np.abs(g64 - ref).max() <= 1e-12 * scale, (mode, name, on)
+                    assert np.abs(g32 - ref).max() <= 1e-5 * scale, (mode, name, on)
+                assert np.abs(got[True][0] - got[False][0]).max() <= 1e-13 * scale, (mode, name)
     finally:
         hyp.set_support_skip(True)
         hyp.set_sweep_mode("auto")
