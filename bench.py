@@ -131,6 +131,8 @@ def main():
                     help="with --adapt-early: only the run with support skipping (longer trajectories)")
     ap.add_argument("--csr", action="store_true",
                     help="materialised CSR SpMV against the matrix-free product (24- and 28-qubit workloads)")
+    ap.add_argument("--graph", action="store_true",
+                    help="inner-optimiser evaluation (state prep + H psi + E + adjoint gradient): captured graph vs eager")
     ap.add_argument("--batch", action="store_true",
                     help="full pool-gradient sweeps of the eight uneven batch instances: one persistent batched "
                          "launch (autotuned tile) against per-instance sweeps (JSON line)")
@@ -166,6 +168,9 @@ def main():
         return
     if args.csr:
         csr_bench()
+        return
+    if args.graph:
+        graph_bench()
         return
     w = synth.WORKLOADS[args.workload]
     if args.fp32_study:
@@ -501,6 +506,41 @@ def adapt_compare(w, n_iter, shadow=False):
                       "dE": A32.energy_fp64() - A64.energy_fp64(), "final_E_screened_polished_fp64": rp["energy"],
                       "dE_polished": rp["energy"] - A64.energy_fp64(), "polish_s": round(time.time() - t4, 2),
                       "polish_evals": rp["n_evals"]}), flush=True)
+
+
+def graph_bench(reps=40):
+    """One inner-optimiser evaluation E(theta), dE/dtheta (state preparation
+    by j rotations, H psi, energy, adjoint gradient: 3j + O(1) launches)
+    replayed from a captured hipGraph against the same launches issued
+    eagerly; host wall time per evaluation over `reps` evaluations with
+    fresh parameters (each evaluation waits for its energy and gradient)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2604_01176_amd as hyp
+
+    for name, js in (("h4_8q", (8, 32)), ("h8_16q", (8, 32)), ("h12_24q", (8, 32))):
+        w = synth.WORKLOADS[name]
+        x, z, c, _, _ = synth.hamiltonian(w)
+        cre, ann, _ = synth.canonical_pool(w.n_orb)
+        S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+        H = hyp.Hamiltonian(S, x, z, c)
+        rng = np.random.default_rng(5)
+        for j in js:
+            ops = rng.choice(len(cre), size=j, replace=False).astype(np.int32)
+            out = {"workload": name, "dim": S.dim, "parameters": j}
+            for use_graph in (True, False):
+                A = hyp.Adapt(H, cre, ann, max_iter=j + 1, use_graph=use_graph)
+                A.set_ansatz(ops, rng.uniform(-0.3, 0.3, j))
+                A.eval(rng.uniform(-0.3, 0.3, j))  # capture / warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    A.eval(rng.uniform(-0.3, 0.3, j))
+                out["graph_ms" if use_graph else "eager_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+                A.close()
+            out["speedup"] = round(out["eager_ms"] / out["graph_ms"], 2)
+            print(json.dumps(out), flush=True)
 
 
 def csr_bench(reps=5):
