@@ -272,6 +272,15 @@ def main():
     dom_ms = prof[dom][0] / prof[dom][1]
     roof = roofline(dom, dom_ms, m)
     roof["traffic"] = measured_traffic(w.name, dom)
+    # H psi's measured HBM bytes (committed counter table) over its time: the
+    # DRAM-counter fraction of the HBM peak (null when a kernel's table entry
+    # is missing or stale)
+    hb = [measured_traffic(w.name, k) for k in ("k_mixed", "k_ss_apply", "k_transpose")]
+    hpsi_hbm = None
+    if all(v is not None for v in hb):
+        bytes_per_hpsi = hb[0] + 2 * hb[1] + hb[2]
+        hpsi_hbm = {"bytes": round(bytes_per_hpsi), "gbs": round(bytes_per_hpsi / (hpsi_ms * 1e-3) / 1e9, 1),
+                    "frac": round(bytes_per_hpsi / (hpsi_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     cpu = None
     if args.cpu_seconds > 0:
         import oracle
@@ -321,6 +330,7 @@ def main():
         "hpsi_ms": round(hpsi_ms, 3), "hpsi_threads": int(hpsi_threads),
         "hpsi_fp32_ms": round(hpsi32_ms, 3), "hpsi_fp32_threads": int(threads32),
         "hpsi_frac_hbm_gather_model": round(value / HBM_PEAK_GBS, 4),
+        "hpsi_hbm_measured": hpsi_hbm,
         "pool_grad_evals_per_s": round(m["pool"] / (sweep_ms * 1e-3), 1) if sweep_ms > 0 else None,
         "sweep_ms": round(sweep_ms, 3),
         "support_skip_near_hf": sup,
