@@ -160,6 +160,10 @@ hyp_status hyp_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* si
  * over at most half of its range (beta rows for G_a, alpha columns for G_b)
  * runs on gathered rows or columns.  The call then waits on the host for the
  * support scan of psi (two counts), not for the kernels queued after it.
+ * (hyp_pool_gradients already copies the generator list to the host to
+ * validate it, so it is synchronous and not graph-capturable either way.)
+ * The pair kernel (mode 1 and candidate subsets) skips pairs whose two
+ * determinants both lie outside psi's row or column support.
  * Results equal the dense evaluation up to summation order.  Near the
  * Hartree-Fock state (early ADAPT iterations) both cost a small fraction of
  * the dense ones; for a dense psi the extra work is a support scan, list
@@ -236,6 +240,14 @@ hyp_status hyp_set_pool_kind(int kind);
  * psi_D' <- s sin psi_D + cos psi_D'; other amplitudes unchanged. */
 hyp_status hyp_apply_excitation(hyp_sector s, hyp_dtype dtype, hyp_exc op, double theta,
                                 void* psi_dev, void* stream);
+
+/* psi <- exp(theta[n-1] A_{n-1}) ... exp(theta[0] A_0) psi: the state
+ * preparation of an ansatz, rotations enqueued in order on `stream`.  ops and
+ * theta are host arrays of n elements; every generator and angle is
+ * validated (as for hyp_apply_excitation) before the first rotation is
+ * enqueued, so an error leaves psi untouched. */
+hyp_status hyp_apply_excitations(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops, const double* theta,
+                                 int64_t n, void* psi_dev, void* stream);
 
 /* Batched pool gradients for up to 16 instances (possibly of different
  * sectors, one dtype).  Jobs whose list covers at least a quarter of their

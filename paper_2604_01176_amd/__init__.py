@@ -264,6 +264,18 @@ def hyp_apply_excitation(sector: Sector, cre: int, ann: int, theta: float, psi):
     return psi
 
 
+def hyp_apply_excitations(sector: Sector, cre, ann, theta, psi):
+    """psi <- exp(theta[n-1] A_{n-1}) ... exp(theta[0] A_0) psi in place."""
+    n = len(theta)
+    ops = (_lib.HypExc * max(1, n))()
+    for i, (c_, a_) in enumerate(zip(np.asarray(cre).tolist(), np.asarray(ann).tolist())):
+        ops[i].cre, ops[i].ann = int(c_), int(a_)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    check(_lib.load().hyp_apply_excitations(sector.handle, _dtype_code(psi), ops, th.ctypes.data if n else None,
+                                            n, _dev_ptr(psi, sector.dim, "psi"), _stream()))
+    return psi
+
+
 def set_sweep_mode(mode: str = "auto"):
     """hyp_set_sweep_mode: "auto", "pairs" (per-generator kernel), "tdens"
     (row-batched transition values) or "tdens_bins" (per-stage LDS bins)."""

@@ -78,6 +78,7 @@ SIGNATURES = {
     "hyp_set_sweep_mode": (_ci, [_ci]),
     "hyp_set_support_skip": (_ci, [_ci]),
     "hyp_set_pool_kind": (_ci, [_ci]),
+    "hyp_apply_excitations": (_ci, [_vp, _ci, _vp, _vp, _i64, _vp, _vp]),
     "hyp_csr_build": (_ci, [_vp, _vp, ctypes.POINTER(_vp)]),
     "hyp_csr_apply": (_ci, [_vp, _ci, _vp, _vp, _vp]),
     "hyp_csr_export": (_ci, [_vp, _vp, _vp, _vp]),

@@ -524,4 +524,23 @@ hyp_status hyp_apply_excitation(hyp_sector sh, hyp_dtype dtype, hyp_exc op, doub
   return launch_rotate(S, dtype, op, theta, nullptr, psi, (hipStream_t)stream);
 }
 
+hyp_status hyp_apply_excitations(hyp_sector sh, hyp_dtype dtype, const hyp_exc* ops, const double* theta,
+                                 int64_t n, void* psi, void* stream) {
+  Sector* S = sector_of(sh);
+  if (!S || !psi || n < 0 || (n > 0 && (!ops || !theta)))
+    return fail(HYP_ERR_ARG, "hyp_apply_excitations: NULL argument or negative count");
+  if (dtype != HYP_F64 && dtype != HYP_F32) return fail(HYP_ERR_ARG, "hyp_apply_excitations: bad dtype");
+  // everything is validated before the first rotation is enqueued
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(theta[i])) return fail(HYP_ERR_ARG, "hyp_apply_excitations: non-finite theta");
+    hyp_status r = validate_exc(S, ops[i]);
+    if (r != HYP_OK) return r;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    hyp_status r = launch_rotate(S, dtype, ops[i], theta[i], nullptr, psi, (hipStream_t)stream);
+    if (r != HYP_OK) return r;
+  }
+  return HYP_OK;
+}
+
 }  // extern "C"

@@ -248,3 +248,29 @@ def test_sweep_support_skip_32q_near_hartree_fock(hyp):
     ref = oracle.pool_gradients(M, na, nb, cre[k], ann[k], psi_h, sig)
     assert np.abs(outs[True][k] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
     assert times[True] < times[False]
+
+
+def test_apply_excitations_sequence(hyp):
+    M, na, nb = 6, 3, 3
+    S = hyp.Sector(M, na, nb)
+    cre, ann, _ = synth.canonical_pool(M)
+    rng = np.random.default_rng(4)
+    k = rng.choice(cre.size, 10, replace=False)
+    th = rng.uniform(-1, 1, 10)
+    psi = synth.random_state(S.dim, 6)
+    ref = psi.copy()
+    for i in range(10):
+        ref = oracle.rotate(M, na, nb, cre[k[i]], ann[k[i]], th[i], ref)
+    d = _dev(psi)
+    hyp.hyp_apply_excitations(S, cre[k], ann[k], th, d)
+    assert np.abs(d.cpu().numpy() - ref).max() <= 1e-13
+    # an invalid generator anywhere in the list: nothing is applied
+    bad_c, bad_a = cre[k].copy(), ann[k].copy()
+    bad_c[5] = bad_a[5]
+    d2 = _dev(psi)
+    with pytest.raises(hyp.HypError):
+        hyp.hyp_apply_excitations(S, bad_c, bad_a, th, d2)
+    assert np.array_equal(d2.cpu().numpy(), psi)
+    # the empty sequence
+    hyp.hyp_apply_excitations(S, [], [], [], d2)
+    assert np.array_equal(d2.cpu().numpy(), psi)
