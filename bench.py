@@ -63,12 +63,25 @@ def kernel_flops(name, m):
     return 2.0 * m["nnz"], "alu"
 
 
+# LDS: 128 bytes per clock per CU, 256 CUs at 2.4 GHz
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
+
+
 def roofline(name, ms, m):
     flops, bound = kernel_flops(name, m)
     achieved = flops / (ms * 1e-3) / 1e12
-    return {"bound": bound, "kernel": name, "achieved": round(achieved, 3), "peak": FP64_VECTOR_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_TFLOPS, 4), "traffic": None,
-            "ms_per_launch": round(ms, 3)}
+    out = {"bound": bound, "kernel": name, "achieved": round(achieved, 3), "peak": FP64_VECTOR_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_TFLOPS, 4), "traffic": None,
+           "ms_per_launch": round(ms, 3)}
+    # the LDS-staged product kernels: algorithmic LDS read bytes per launch
+    # (two 8-byte reads per mixed-pass product: coefficient and amplitude;
+    # one per transition-value product) against the chip's LDS bandwidth
+    per_product = {"k_mixed": 16.0, "k_tdens_rows": 8.0}.get(name)
+    if per_product is not None:
+        lds = flops / 2.0 * per_product / (ms * 1e-3) / 1e12
+        out["lds"] = {"achieved": round(lds, 2), "peak": round(LDS_PEAK_TBS, 1), "unit": "TB/s",
+                      "frac": round(lds / LDS_PEAK_TBS, 4)}
+    return out
 
 
 # source file of each kernel whose counters are committed
