@@ -288,8 +288,15 @@ hyp_status hyp_build_hamiltonian_integrals(hyp_sector s, int n_orb, const double
   hyp_status r = assemble_pauli(n_orb, h_dev, g_dev, e_core, x.p, z.p, c.p, cap, &n, st);
   if (r != HYP_OK) return r;
   // the grouped table is folded and uploaded by the common build
-  std::vector<uint32_t> hx(n), hz(n);
-  std::vector<double> hc(n);
+  std::vector<uint32_t> hx, hz;
+  std::vector<double> hc;
+  try {
+    hx.resize(n);
+    hz.resize(n);
+    hc.resize(n);
+  } catch (...) {
+    return fail(HYP_ERR_NOMEM, "hyp_build_hamiltonian_integrals: host allocation");
+  }
   if (n > 0) {
     HYP_HIP(hipMemcpyAsync(hx.data(), x.p, n * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HYP_HIP(hipMemcpyAsync(hz.data(), z.p, n * sizeof(uint32_t), hipMemcpyDeviceToHost, st));

@@ -20,6 +20,7 @@
 #include "hyp_internal.h"
 
 #include <algorithm>
+#include <new>
 
 namespace hyp {
 
@@ -216,7 +217,8 @@ hyp_status hyp_csr_build(hyp_ham hh, void* stream, hyp_csr* out) {
     return fail(HYP_ERR_NOMEM, "hyp_csr_build: the CSR needs " + std::to_string(bytes) + " bytes, " +
                                    std::to_string(free_b) + " free on the device");
   hipStream_t st = (hipStream_t)stream;
-  hyp_csr m = new hyp_csr_s;
+  hyp_csr m = new (std::nothrow) hyp_csr_s;
+  if (!m) return fail(HYP_ERR_NOMEM, "hyp_csr_build: host allocation");
   m->dim = S->dim;
   m->nnz = nnz;
   hipError_t e = hipMalloc(&m->rp, (S->dim + 1) * sizeof(int64_t));
