@@ -146,6 +146,8 @@ def main():
                     help="materialised CSR SpMV against the matrix-free product (24- and 28-qubit workloads)")
     ap.add_argument("--graph", action="store_true",
                     help="inner-optimiser evaluation (state prep + H psi + E + adjoint gradient): captured graph vs eager")
+    ap.add_argument("--cpu-study", action="store_true",
+                    help="the CPU oracle timed on this host at 1 thread and all threads (H psi, sweep, ADAPT)")
     ap.add_argument("--batch", action="store_true",
                     help="full pool-gradient sweeps of the eight uneven batch instances: one persistent batched "
                          "launch (autotuned tile) against per-instance sweeps (JSON line)")
@@ -160,6 +162,10 @@ def main():
               "(the beta-row-partitioned design is described in the design notes, not implemented).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_study:  # host only: no GPU needed
+        cpu_study()
+        return
 
     import numpy as np
     import torch
@@ -185,6 +191,7 @@ def main():
     if args.graph:
         graph_bench()
         return
+
     w = synth.WORKLOADS[args.workload]
     if args.fp32_study:
         fp32_study(w, args.fp32_study)
@@ -529,6 +536,64 @@ def adapt_compare(w, n_iter, shadow=False):
                       "dE": A32.energy_fp64() - A64.energy_fp64(), "final_E_screened_polished_fp64": rp["energy"],
                       "dE_polished": rp["energy"] - A64.energy_fp64(), "polish_s": round(time.time() - t4, 2),
                       "polish_evals": rp["n_evals"]}), flush=True)
+
+
+def cpu_study(budget_s=20.0):
+    """The CPU oracle (plain C + OpenMP, FP64, term by term / pair by pair)
+    timed on this host at 1 thread and at all threads: H psi (every output
+    row up to 24 qubits, a random row sample above, scaled), the pool sweep
+    (every generator at 8 and 16 qubits, a random sample of generators above,
+    scaled by the sample's share), and one ADAPT iteration (gradients +
+    scipy BFGS) at 8 and 16 qubits.  Rates in the benchmark's units."""
+    import numpy as np
+    import synth
+    import oracle
+    from oracle.adapt import SectorProblem, run_adapt
+
+    all_threads = oracle.max_threads()
+    for name in ("h4_8q", "h8_16q", "h12_24q", "h14_28q", "h16_32q"):
+        w = synth.WORKLOADS[name]
+        M, na, nb = w.n_orb, w.n_alpha, w.n_beta
+        x, z, c, _, _ = synth.hamiltonian(w)
+        cre, ann, _ = synth.canonical_pool(M)
+        m = model(M, na, nb, len(c), len(cre))
+        dim = m["dim"]
+        psi = synth.random_state(dim, 7)
+        rng = np.random.default_rng(1)
+        for th in (1, all_threads):
+            oracle.set_threads(th)
+            out = {"workload": name, "threads": th}
+            # H psi: all rows if cheap, else a sample sized to about budget_s / 4
+            rows = None if dim <= 5000 else rng.integers(0, dim, 2048)
+            t0 = time.time()
+            oracle.apply_h(M, na, nb, x, z, c, psi, out_idx=rows)
+            dt = time.time() - t0
+            frac = 1.0 if rows is None else rows.size / dim
+            out["hpsi_s"] = round(dt / frac, 3)
+            out["hpsi_gbs_gather_model"] = round(hpsi_gather_bytes(m) * frac / dt / 1e9, 4)
+            # sweep: all generators if dim is small, else a sample
+            if dim <= 5000:
+                k = np.arange(len(cre))
+            else:
+                nk = 128 if dim <= 1_000_000 else (16 if dim <= 20_000_000 else 4)
+                k = rng.choice(len(cre), size=min(len(cre), nk), replace=False)
+            if True:
+                # the sweep's cost does not depend on the values: psi stands in
+                # for sigma above the small sizes
+                sig = oracle.apply_h(M, na, nb, x, z, c, psi) if dim <= 5000 else psi
+                t0 = time.time()
+                oracle.pool_gradients(M, na, nb, cre[k], ann[k], psi, sig)
+                dt = time.time() - t0
+                out["sweep_s"] = round(dt * len(cre) / k.size, 2)
+                out["sweep_evals_per_s"] = round(k.size / dt, 2)
+                out["sweep_sampled_generators"] = int(k.size)
+            if dim <= 5000:
+                prob = SectorProblem(M, na, nb, x, z, c, cre, ann)
+                t0 = time.time()
+                run_adapt(prob, 1)
+                out["adapt_first_iteration_s"] = round(time.time() - t0, 3)
+            print(json.dumps(out), flush=True)
+    oracle.set_threads(all_threads)
 
 
 def graph_bench(reps=40):

@@ -74,6 +74,10 @@ def lib():
         L.orc_rotate.argtypes = [ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, f64p]
         L.orc_set_qubit_excitations.restype = None
         L.orc_set_qubit_excitations.argtypes = [ci]
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [ci]
+        L.orc_max_threads.restype = ci
+        L.orc_max_threads.argtypes = []
         L.orc_pair_count.restype = i64
         L.orc_pair_count.argtypes = [ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32]
         L.orc_occupations.argtypes = [ci, ci, ci, f64p, f64p]
@@ -157,6 +161,15 @@ def energy(M, na, nb, x, z, c, psi):
     """E = <psi|H|psi> / <psi|psi>."""
     s = apply_h(M, na, nb, x, z, c, psi)
     return dot(psi, s) / dot(psi, psi)
+
+
+def set_threads(n: int):
+    """Thread count of the oracle's parallel loops (for timing)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 class qubit_excitations:

@@ -27,6 +27,11 @@
 
 static int64_t binom_tab[65][65];
 
+#include <omp.h>
+/* thread count of the parallel loops below (timing at 1 thread and at all) */
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
+
 __attribute__((constructor)) static void binom_init(void) {
     /* Pascal's triangle */
     for (int m = 0; m <= 64; ++m) {
