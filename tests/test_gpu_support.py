@@ -69,7 +69,8 @@ def _states(M, na, nb, da, db):
     return out
 
 
-CASES = [(4, 2, 2), (5, 3, 2), (6, 3, 3), (7, 2, 5), (8, 4, 4), (9, 5, 4), (3, 0, 2), (4, 4, 1), (10, 4, 5)]
+CASES = [(4, 2, 2), (5, 3, 2), (6, 3, 3), (7, 2, 5), (8, 4, 4), (9, 5, 4), (3, 0, 2), (4, 4, 1), (10, 4, 5),
+         (5, 2, 0), (4, 1, 4)]
 
 
 @pytest.mark.parametrize("M,na,nb", CASES)
@@ -167,7 +168,7 @@ def test_support_skip_32q_near_hartree_fock(hyp):
 # ------------------------------------------------------------- gradient sweep
 
 GCASES = [(4, 2, 2), (5, 2, 3), (6, 3, 3), (8, 4, 4), (9, 5, 4), (3, 0, 2), (4, 4, 1), (7, 3, 2), (10, 4, 5),
-          (2, 1, 1)]
+          (2, 1, 1), (5, 2, 0)]
 
 
 @pytest.mark.parametrize("M,na,nb", GCASES)
