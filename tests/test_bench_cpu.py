@@ -1,0 +1,31 @@
+"""Host-side checks of the benchmark's contract (no GPU): one GPU only, and
+the algorithmic byte / flop models it reports against."""
+import math
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+
+
+def test_models_at_32_qubits():
+    sys.path.insert(0, ROOT)
+    import bench
+    m = bench.model(16, 8, 8, 94849, 39960)
+    assert m["dim"] == math.comb(16, 8) ** 2
+    # gather model: (nnz + dim) 8 + 16 T bytes, 7.678 TB at 32 qubits
+    assert abs(bench.hpsi_gather_bytes(m) / 1e12 - 7.678) < 0.01
+    # the mixed pass: 2 flops per product, s_a s_b + s_a + s_b + 1 products per output
+    flops, bound = bench.kernel_flops("k_mixed", m)
+    assert bound == "alu" and abs(flops - 2 * m["dim"] * (64 * 64 + 64 + 64 + 1)) < 1
+    r = bench.roofline("k_mixed", 218.0, m)
+    assert abs(r["frac"] - r["achieved"] / 78.6) < 1e-3
+    assert abs(r["lds"]["achieved"] - flops / 2 * 16 / 0.218 / 1e12) < 0.05
+    assert abs(bench.LDS_PEAK_TBS - 78.6432) < 1e-3
