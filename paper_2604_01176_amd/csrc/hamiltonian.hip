@@ -467,17 +467,29 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   uint32_t ex[64];
 #pragma unroll
   for (int x = 0; x < 64; ++x) ex[x] = rbase + (uint32_t)a.da * (uint32_t)sizeof(T);
-  int ns = 0;
   {
+    // every string of the sector has N_a (M - N_a) singles in the same
+    // (occupied, empty) order, so the slot counter x and the position ie in
+    // the empty list are the same on every lane: each entry goes straight to
+    // a fixed register, and the walk to the next occupied orbital is a
+    // uniform branch
     const RankTables* R = a.arank;
-    uint32_t occ = s;
-    while (occ) {
-      const int i = __ffs(occ) - 1;
-      occ &= occ - 1;
-      uint32_t emp = ~s & amask;
-      while (emp) {
+    const int nemp = M - a.na;
+    const int nex = a.na * nemp;
+    uint32_t occ = s, emp = 0u;
+    int i = 0, ie = nemp;
+#pragma unroll
+    for (int x = 0; x < 64; ++x) {
+      if (x < nex) {
+        if (ie == nemp) {
+          i = __ffs(occ) - 1;
+          occ &= occ - 1;
+          emp = ~s & amask;
+          ie = 0;
+        }
         const int e = __ffs(emp) - 1;
         emp &= emp - 1;
+        ++ie;
         const int p = min(i, e), q = max(i, e);
         const int pid = pair_id(p, q);
         const uint32_t t2 = s ^ (1u << i) ^ (1u << e);
@@ -488,12 +500,8 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
         // LDS byte offsets: the source amplitude (bits 0..16) and the
         // coefficient s_fab[(pair*2 + O)*2 + sab] (bits 17..28); bit 29 is
         // the sign of the singles' dressing
-        const uint32_t ent = (rbase + r2 * (uint32_t)sizeof(T)) |
-                             (((((uint32_t)pid * 2u + O) * 2u + sab) * (uint32_t)sizeof(T)) << 17) | (ssg << 29);
-#pragma unroll
-        for (int x = 0; x < 64; ++x)
-          if (x == ns) ex[x] = ent;
-        ++ns;
+        ex[x] = (rbase + r2 * (uint32_t)sizeof(T)) |
+                (((((uint32_t)pid * 2u + O) * 2u + sab) * (uint32_t)sizeof(T)) << 17) | (ssg << 29);
       }
     }
   }
