@@ -222,6 +222,17 @@ hyp_status hyp_pool_gradients(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_
  * Process-wide setting. */
 hyp_status hyp_set_sweep_mode(int mode);
 
+/* Row staging of mode 2's kernel (a tuning and testing control, no effect on
+ * results): 0 (default) stages, for FP64 state vectors whose rows are whole
+ * 16-byte blocks and 512-column chunks, only the blocks of each source row
+ * that the chunk's columns and their single excitations reach, into two
+ * alternating LDS buffers so that the next row's copy overlaps this row's
+ * products (per-device tables of about C(M,N_a) * 2.1 bytes, built on the
+ * first sweep of a string space; falls back to whole rows where a chunk needs
+ * more than 4094 blocks); 1 always stages whole rows.  Both give the same
+ * gradients bit for bit.  Process-wide; HYP_ERR_ARG unless mode is 0 or 1. */
+hyp_status hyp_set_row_staging(int mode);
+
 /* Kind of the pool generators (the paper's ADAPT-VQE description names the
  * qubit-excitation-based, QEB, pool as an example): 0 fermionic excitations
  * (default), 1 qubit excitations.  Both take the same (cre, ann) masks; a

@@ -287,6 +287,13 @@ def set_pool_kind(kind: str = "fermionic"):
     check(_lib.load().hyp_set_pool_kind({"fermionic": 0, "qubit": 1}[kind]))
 
 
+def set_row_staging(mode: str = "compact"):
+    """hyp_set_row_staging: "compact" (default; FP64 sweep stages only the
+    blocks of each source row its chunk reaches, double-buffered) or "rows"
+    (whole rows).  Same results bit for bit."""
+    check(_lib.load().hyp_set_row_staging({"compact": 0, "rows": 1}[mode]))
+
+
 def set_support_skip(on: bool = True):
     """hyp_set_support_skip: restrict H psi to psi's row and column support."""
     check(_lib.load().hyp_set_support_skip(1 if on else 0))

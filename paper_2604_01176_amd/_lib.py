@@ -76,6 +76,7 @@ SIGNATURES = {
     "hyp_pool_gradients": (_ci, [_vp, _ci, _vp, _i64, _vp, _vp, _vp, _vp]),
     "hyp_apply_excitation": (_ci, [_vp, _ci, HypExc, _d, _vp, _vp]),
     "hyp_set_sweep_mode": (_ci, [_ci]),
+    "hyp_set_row_staging": (_ci, [_ci]),
     "hyp_set_support_skip": (_ci, [_ci]),
     "hyp_set_pool_kind": (_ci, [_ci]),
     "hyp_apply_excitations": (_ci, [_vp, _ci, _vp, _vp, _i64, _vp, _vp]),

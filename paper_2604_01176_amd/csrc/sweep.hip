@@ -26,6 +26,7 @@
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 namespace hyp {
@@ -342,6 +343,263 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
   }
   // flush: per-wave LDS bins (the row buffer is free now), then one slot of
   // the partial buffer per (slot, chunk)
+  __syncthreads();
+  double* s_bins = (double*)smem;  // [nt / 64][kBins]
+  const int nw = nt >> 6;
+  for (int i = tid; i < nw * kBins; i += nt) s_bins[i] = 0.0;
+  __syncthreads();
+  if (live) {
+    uint32_t bins[16];
+#pragma unroll
+    for (int x = 0; x < 16; ++x) bins[x] = 0u;
+    uint64_t signs = 0;
+    alpha_bins(s, amask, bins, &signs);
+    if (!a.fsign) signs = 0;
+#pragma unroll
+    for (int x = 0; x < 64; ++x) {
+      if (x < ns) {
+        const uint32_t bin = (bins[x >> 2] >> ((x & 3) * 8)) & 0xffu;
+        atomicAdd(&s_bins[(tid >> 6) * kBins + bin], ((signs >> x) & 1ull) ? -acc[x] : acc[x]);
+      }
+    }
+  }
+  double d = acc_id;
+  for (int o = 32; o > 0; o >>= 1) d += __shfl_down(d, o, 64);
+  if ((tid & 63) == 0) s_red[tid >> 6] = d;
+  __syncthreads();
+  double* out = a.part + ((int64_t)slot * a.nchunk + chunk) * kStageW;
+  for (int x = tid; x < kBins; x += nt) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += s_bins[w * kBins + x];
+    out[x] = t;
+  }
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += s_red[w];
+    out[kBins] = t;
+  }
+}
+
+// ---------------------------------------------------------------- compact staging
+// A workgroup of the row-batched kernel reads, from each staged source row,
+// only the amplitudes its own columns' alpha singles reach, plus its own
+// columns.  Over a chunk of consecutive colex ranks these cluster: for
+// 512-column chunks of the 16-orbital, 8-electron string space they are 43%
+// of the row on average (52% at most), in the same proportion of 16-byte
+// blocks.  k_tdens_rows_c stages just those blocks (FP64 rows), which leaves
+// room for two buffers: the copy of the next row pair runs while this one's
+// products are formed.  Per-chunk tables, built once per string space:
+//   bpos[c][b]  position of 16-byte block b in chunk c's staged list
+//   blist[c][i] the staged blocks in ascending order, nblk_c[c] of them.
+constexpr int kCMaxBlk = 4094;         // staged blocks per buffer: both buffers and zero slots below 2^17 B
+constexpr uint32_t kCBuf1 = 65520u;    // byte offset of the second buffer (fits a ds_read offset)
+constexpr int kCPerThread = 8;         // staged blocks per thread at 512 threads
+
+__global__ void k_cs_mark(int da, int nt, int M, const uint32_t* __restrict__ astr, const RankTables* __restrict__ R,
+                          int nblk, uint8_t* __restrict__ mark) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= da) return;
+  uint8_t* m = mark + (int64_t)(col / nt) * nblk;
+  const uint32_t s = astr[col], amask = (1u << M) - 1u;
+  m[col >> 1] = 1;
+  uint32_t occ = s;
+  while (occ) {
+    const int i = __ffs(occ) - 1;
+    occ &= occ - 1;
+    uint32_t emp = ~s & amask;
+    while (emp) {
+      const int e = __ffs(emp) - 1;
+      emp &= emp - 1;
+      const uint32_t t2 = s ^ (1u << i) ^ (1u << e);
+      m[(R->lo[t2 & 255u] + R->hi[(t2 >> 8) & 255u]) >> 1] = 1;
+    }
+  }
+}
+
+// One workgroup per chunk: positions of the marked blocks, in block order.
+__global__ void __launch_bounds__(256) k_cs_scan(const uint8_t* __restrict__ mark, int nblk,
+                                                 uint16_t* __restrict__ bpos, uint16_t* __restrict__ blist,
+                                                 int* __restrict__ nblk_c) {
+  __shared__ int s_cnt[256];
+  const int c = blockIdx.x, t = threadIdx.x;
+  const uint8_t* m = mark + (int64_t)c * nblk;
+  const int per = (nblk + 255) / 256;
+  const int b0 = min(nblk, t * per), b1 = min(nblk, b0 + per);
+  int n = 0;
+  for (int b = b0; b < b1; ++b) n += m[b] ? 1 : 0;
+  s_cnt[t] = n;
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int i = 0; i < 256; ++i) {
+      const int v = s_cnt[i];
+      s_cnt[i] = run;
+      run += v;
+    }
+    nblk_c[c] = run;
+  }
+  __syncthreads();
+  int pos = s_cnt[t];
+  for (int b = b0; b < b1; ++b) {
+    if (m[b]) {
+      if (pos < kCMaxBlk) blist[(int64_t)c * kCMaxBlk + pos] = (uint16_t)b;
+      bpos[(int64_t)c * nblk + b] = (uint16_t)min(pos, 65535);
+      ++pos;
+    } else {
+      bpos[(int64_t)c * nblk + b] = 0xffffu;
+    }
+  }
+}
+
+// 16 bytes per lane from global memory straight into LDS at lds_wave + 16 *
+// lane.  Written as one asm statement so that the compiler does not order
+// later LDS reads of the other buffer behind this copy: the caller waits for
+// it (s_waitcnt vmcnt(0)) and synchronises before reading what it wrote.
+__device__ inline void dma16(uint32_t lds_wave, const void* src) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(lds_wave), "v"(src)
+               : "memory");
+}
+
+// Stage chunk blocks blk[k] (k-th group of nt blocks) of one FP64 row.
+__device__ inline void stage_blocks(uint32_t buf, const double* row, const int (&blk)[kCPerThread], int nb, int tid,
+                                    int nt) {
+  const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < kCPerThread; ++k) {
+    const int base = k * nt + w * 64;  // wave-uniform
+    if (base < nb) {
+      const uint32_t dst = (uint32_t)__builtin_amdgcn_readfirstlane(buf + (uint32_t)base * 16u);
+      if (base + lane < nb) dma16(dst, row + 2 * (int64_t)blk[k]);
+    }
+  }
+}
+
+// k_tdens_rows for FP64 with compact, double-buffered staging; same products
+// in the same order, so the same partials bit for bit.
+__global__ void __launch_bounds__(512) k_tdens_rows_c(TRArgs a, const uint16_t* __restrict__ bpos,
+                                                      const uint16_t* __restrict__ blist,
+                                                      const int* __restrict__ nblk_c, int nblk,
+                                                      uint32_t pairs_off) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double s_red[8];
+  const int M = a.M;
+  const uint32_t amask = (1u << M) - 1u;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int b = blockIdx.x, xcd = b & 7, jj = b >> 3;
+  const int slot = (jj / a.nchunk) * 8 + xcd;
+  const int chunk = jj % a.nchunk;
+  if (slot >= a.n_eb + a.n_id) return;
+  const int col = chunk * nt + tid;
+  const bool live = col < a.da;
+  const uint32_t s = live ? a.astr[col] : a.astr[0];
+  const int nb = nblk_c[chunk];
+  const uint16_t* bp = bpos + (int64_t)chunk * nblk;
+  const uint32_t rbase = lds_addr(smem);
+  // alpha sources as ranks (pad = da), then as byte addresses in buffer 0;
+  // unused slots read the zero slot after the staged blocks
+  uint32_t ex[64];
+  int ns = 0;
+  alpha_sources<double>(s, amask, a.arank, (uint32_t)a.da * 8u, ex, &ns);
+  const uint32_t zslot = rbase + (uint32_t)nb * 16u;
+#pragma unroll
+  for (int x = 0; x < 64; ++x) {
+    const uint32_t r = ex[x] >> 3;
+    const bool real = live && r < (uint32_t)a.da;
+    const uint32_t pos = bp[(real ? r : 0u) >> 1];  // unconditional: the 64 reads go out together
+    ex[x] = real ? rbase + pos * 16u + (r & 1u) * 8u : zslot;
+  }
+  const uint32_t own = live ? rbase + (uint32_t)bp[col >> 1] * 16u + ((uint32_t)col & 1u) * 8u : zslot;
+  int blk[kCPerThread];
+#pragma unroll
+  for (int k = 0; k < kCPerThread; ++k) {
+    const int i = k * nt + tid;
+    blk[k] = i < nb ? (int)blist[(int64_t)chunk * kCMaxBlk + i] : 0;
+  }
+  double acc[64];
+#pragma unroll
+  for (int x = 0; x < 64; ++x) acc[x] = 0.0;
+  double acc_id = 0.0;
+  const bool ident = slot >= a.n_eb;
+  const int row0 = ident ? (slot - a.n_eb) * a.Kid : 0;
+  int nrows;
+  if (ident)
+    nrows = a.idrows ? max(0, min(a.Kid, *a.n_idrows - row0)) : min(a.Kid, a.db - row0);
+  else
+    nrows = a.rcount ? a.rcount[slot] : a.K;
+  const double* psi = (const double*)a.psi;
+  const double* sig = (const double*)a.sig;
+  if (tid == 0) {
+    *(__attribute__((address_space(3))) double*)(uintptr_t)zslot = 0.0;
+    *(__attribute__((address_space(3))) double*)(uintptr_t)(zslot + kCBuf1) = 0.0;
+  }
+  // the slot's row pairs, copied once into LDS after the two buffers: a
+  // pair is then one broadcast LDS read rather than a global load whose
+  // latency would sit in front of every copy
+  {
+    const int2* rl = a.rows + (int64_t)(ident ? 0 : slot) * a.K;
+    int2* s_pairs = (int2*)(smem + pairs_off);
+    for (int k = tid; k < nrows; k += nt) {
+      int2 v;
+      if (!ident) {
+        v = rl[k];
+      } else {
+        const int r = a.idrows ? a.idrows[row0 + k] : row0 + k;
+        v = make_int2(r, r);
+      }
+      s_pairs[k] = v;
+    }
+  }
+  __syncthreads();
+  const uint32_t s_pairs_addr = rbase + pairs_off;
+  auto pair_at = [&](int k) -> int2 {
+    const uint64_t u = lds_load<uint64_t>(s_pairs_addr + (uint32_t)k * 8u);
+    return make_int2((int)(uint32_t)u, (int)(uint32_t)(u >> 32));
+  };
+  // pairs k (being formed) and k + 1 (being copied); sv of pair k
+  int2 p0 = nrows > 0 ? pair_at(0) : make_int2(0, 0);
+  int2 p1 = nrows > 1 ? pair_at(1) : p0;
+  double sv0 = (live && nrows > 0) ? sig[(int64_t)(p0.y & 0x7fffffff) * a.da + col] : 0.0;
+  if (nrows > 0) stage_blocks(rbase, psi + (int64_t)p0.x * a.da, blk, nb, tid, nt);
+  auto step = [&](auto boffc, int k) {
+    constexpr uint32_t kOff = decltype(boffc)::value;
+    constexpr uint32_t kNext = kOff ? 0u : kCBuf1;
+    const int2 p2 = (k + 2 < nrows) ? pair_at(k + 2) : p1;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // sv0 arrived with that wait; passing it through an asm statement keeps
+    // the compiler from waiting on its load after the copy below is issued
+    // (the hardware counter would then also wait for the copy)
+    asm volatile("" : "+v"(sv0));
+    __syncthreads();  // pair k staged by every wave; pair k - 1's reads of the other buffer done
+    double sv1 = 0.0;
+    if (k + 1 < nrows) {
+      sv1 = live ? sig[(int64_t)(p1.y & 0x7fffffff) * a.da + col] : 0.0;
+      stage_blocks(rbase + kNext, psi + (int64_t)p1.x * a.da, blk, nb, tid, nt);
+    }
+    if (live) {
+      const double w = (p0.y < 0 ? -1.0 : 1.0) * sv0;
+#pragma unroll
+      for (int g8 = 0; g8 < 8; ++g8) {
+        if (g8 * 8 < a.nsx) {
+          double v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = lds_load<double>(ex[g8 * 8 + j] + kOff);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) acc[g8 * 8 + j] += w * v[j];
+        }
+      }
+      if (!ident) acc_id += w * lds_load<double>(own + kOff);
+    }
+    p0 = p1;
+    p1 = p2;
+    sv0 = sv1;
+  };
+  int k = 0;
+  for (; k + 1 < nrows; k += 2) {
+    step(std::integral_constant<uint32_t, 0u>(), k);
+    step(std::integral_constant<uint32_t, kCBuf1>(), k + 1);
+  }
+  if (k < nrows) step(std::integral_constant<uint32_t, 0u>(), k);
+  // flush, as in k_tdens_rows
   __syncthreads();
   double* s_bins = (double*)smem;  // [nt / 64][kBins]
   const int nw = nt >> 6;
@@ -773,9 +1031,55 @@ struct TScratch {
   int2* crows = nullptr;
   int* rcount = nullptr;
   size_t crows_cap = 0;
+  // compact staging tables of k_tdens_rows_c for one (orbitals, alpha
+  // electrons, chunk width); c_ok: every chunk fits the two buffers
+  uint16_t* c_bpos = nullptr;
+  uint16_t* c_blist = nullptr;
+  int* c_nb = nullptr;
+  int c_M = -1, c_na = -1, c_nt = -1, c_max = 0;
+  bool c_ok = false;
 };
 TScratch g_ts[64];
 }  // namespace
+int g_row_staging = 0;  // 0 compact where it applies, 1 whole rows
+
+// Builds (once per string space and chunk width) the compact staging tables.
+static hyp_status compact_tables(Sector* S, TScratch& ts, int nt, int nchunk, hipStream_t st) {
+  if (ts.c_M == S->M && ts.c_na == S->na && ts.c_nt == nt) return HYP_OK;
+  const int da = (int)S->da, nblk = (da + 1) / 2;
+  HYP_HIP(hipDeviceSynchronize());
+  if (ts.c_bpos) HYP_HIP(hipFree(ts.c_bpos));
+  if (ts.c_blist) HYP_HIP(hipFree(ts.c_blist));
+  if (ts.c_nb) HYP_HIP(hipFree(ts.c_nb));
+  ts.c_bpos = nullptr;
+  ts.c_blist = nullptr;
+  ts.c_nb = nullptr;
+  ts.c_M = ts.c_na = ts.c_nt = -1;
+  ts.c_ok = false;
+  uint8_t* mark = nullptr;
+  HYP_HIP(hipMalloc(&ts.c_bpos, (size_t)nchunk * nblk * sizeof(uint16_t)));
+  HYP_HIP(hipMalloc(&ts.c_blist, (size_t)nchunk * kCMaxBlk * sizeof(uint16_t)));
+  HYP_HIP(hipMalloc(&ts.c_nb, (size_t)nchunk * sizeof(int)));
+  const int mwords = (int)(((size_t)nchunk * nblk + 3) / 4);
+  HYP_HIP(hipMalloc(&mark, (size_t)mwords * 4));
+  HYP_LAUNCH("k_zero_u32", k_zero_u32, dim3((unsigned)std::min(1024, (mwords + 255) / 256)), dim3(256), 0, st,
+             (uint32_t*)mark, mwords);
+  HYP_LAUNCH("k_cs_mark", k_cs_mark, dim3((unsigned)((da + 255) / 256)), dim3(256), 0, st, da, nt, S->M, S->d_astr,
+             S->d_arank, nblk, mark);
+  HYP_LAUNCH("k_cs_scan", k_cs_scan, dim3((unsigned)nchunk), dim3(256), 0, st, mark, nblk, ts.c_bpos, ts.c_blist,
+             ts.c_nb);
+  std::vector<int> h((size_t)nchunk);
+  HYP_HIP(hipMemcpyAsync(h.data(), ts.c_nb, (size_t)nchunk * sizeof(int), hipMemcpyDeviceToHost, st));
+  HYP_HIP(hipStreamSynchronize(st));
+  HYP_HIP(hipFree(mark));
+  const int mx = h.empty() ? 0 : *std::max_element(h.begin(), h.end());
+  ts.c_max = mx;
+  ts.c_ok = mx <= kCMaxBlk && (mx + nt - 1) / nt <= kCPerThread;
+  ts.c_M = S->M;
+  ts.c_na = S->na;
+  ts.c_nt = nt;
+  return HYP_OK;
+}
 
 size_t tdens_bytes(const Sector* S) {
   const int nt = std::max(64, std::min(768, (int)((S->da + 63) / 64 * 64)));
@@ -871,6 +1175,24 @@ static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* 
   const size_t shm = std::max(row_bytes, (size_t)(nt / 64) * kBins * sizeof(double));
   const int64_t nslot = a.n_eb + a.n_id;
   const int64_t nblk = (int64_t)8 * ((nslot + 7) / 8) * a.nchunk;
+  // compact staging: FP64 rows whose 16-byte blocks start at the row start
+  if (dt == HYP_F64 && g_row_staging == 0 && nt == 512 && a.da % 2 == 0 && ((uintptr_t)psi & 15u) == 0) {
+    hyp_status r = compact_tables(S, ts, nt, a.nchunk, st);
+    if (r != HYP_OK) return r;
+    // LDS: buffer 0 | buffer 1 at kCBuf1 (each with its zero slot) | row pairs
+    const size_t pairs_off = (size_t)kCBuf1 + ((size_t)ts.c_max + 1) * 16;
+    const size_t cshm = std::max(pairs_off + (size_t)std::max(a.K, a.Kid) * sizeof(int2),
+                                 (size_t)(nt / 64) * kBins * sizeof(double));
+    if (ts.c_ok && cshm <= 160 * 1024 - 256) {
+      HYP_HIP(hipFuncSetAttribute((const void*)k_tdens_rows_c, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)cshm));
+      HYP_LAUNCH("k_tdens_rows", k_tdens_rows_c, dim3((unsigned)nblk), dim3(nt), cshm, st, a, ts.c_bpos, ts.c_blist,
+                 ts.c_nb, (a.da + 1) / 2, (uint32_t)pairs_off);
+      HYP_LAUNCH("k_tdens_rows_final", k_tdens_rows_final, dim3((kBins * kStageW + kBins + 255) / 256), dim3(256),
+                 0, st, ts.rpart, a.n_eb, a.n_id, a.nchunk, Ta, Tb, Tab);
+      return HYP_OK;
+    }
+  }
   if (dt == HYP_F64) {
     if (shm > 48 * 1024)
       HYP_HIP(hipFuncSetAttribute((const void*)k_tdens_rows<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1147,3 +1469,9 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
 }
 
 }  // namespace hyp
+
+extern "C" hyp_status hyp_set_row_staging(int mode) {
+  if (mode != 0 && mode != 1) return hyp::fail(HYP_ERR_ARG, "hyp_set_row_staging: mode must be 0 or 1");
+  hyp::g_row_staging = mode;
+  return HYP_OK;
+}
