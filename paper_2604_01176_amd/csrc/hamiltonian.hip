@@ -23,6 +23,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <type_traits>
 
 namespace hyp {
 
@@ -605,6 +606,274 @@ __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   }
 }
 
+// k_mixed for FP64 with compact, double-buffered staging: 768-column chunks
+// (at 16 orbitals and 8 electrons at most 4083 blocks, 52% of a row) stage only the 16-byte blocks of a source row their columns reach (the
+// chunk's list from the compact tables), into buffers alternating between
+// LDS byte offsets 0 and kCBuf1 of the dynamic area; the coefficient and
+// dressing tables of a stage alternate with them, so that the next source
+// row's copy and table fill overlap this row's products.  Per output the
+// products, and the order they are summed in, are those of k_mixed: sigma is
+// the same bit for bit.
+struct MixedLdsC {
+  double fab[2][kMaxPairs * 4];   // per buffer: [(pid*2+O)*2 + sign]
+  double srow[kMaxPairs * 4];     // [(pid*2+O)*2 + sign]
+  double dmix[kMaxOrb];
+  double bdress[2][kMaxOrb + 1];  // per buffer; [kMaxOrb] = 0 for padded reads
+  int2 stage[64];
+  int nstage;
+  int own;
+};
+constexpr uint32_t kFab1 = kMaxPairs * 4 * 8;  // byte offset of fab[1] from fab[0]
+constexpr uint32_t kBd1 = (kMaxOrb + 1) * 8;   // byte offset of bdress[1] from bdress[0]
+
+__global__ void __launch_bounds__(768) k_mixed_c(MixedArgs a, const uint16_t* __restrict__ bpos,
+                                                 const uint16_t* __restrict__ blist, const int* __restrict__ nblk_c,
+                                                 int nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ MixedLdsC L;
+  const int M = a.M;
+  const uint32_t amask = (1u << M) - 1u;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const HamDev& H = a.H;
+  const int b = blockIdx.x, xcd = b & 7, jj = b >> 3;
+  const int brow = (jj / a.nchunk) * 8 + xcd;
+  const int chunk = jj % a.nchunk;
+  if (brow >= a.db) return;
+  const uint32_t bs = a.bstr[brow];
+  const int col = chunk * nt + tid;
+  const bool live = col < a.da;
+  const uint32_t s = live ? a.astr[col] : a.astr[0];
+
+  // stage table, as in k_mixed
+  const int nbemp = M - a.nb;
+  const int nbs = a.nb * nbemp;
+  if (tid < 64) {
+    const int jb = tid;
+    bool keep = false;
+    int2 ent = make_int2(0, 0);
+    if (jb < nbs) {
+      const int io = jb / nbemp, ie = jb % nbemp;
+      uint32_t occ = bs, emp = ~bs & amask;
+      for (int j = 0; j < io; ++j) occ &= occ - 1;
+      for (int j = 0; j < ie; ++j) emp &= emp - 1;
+      const int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
+      const int p = min(i, e), q = max(i, e);
+      const int pb = pair_id(p, q);
+      const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
+      const uint32_t jsb = H.sJ[kMaxPairs + pb] >> M;
+      const uint32_t sgn_s = __popc(jsb & bs) & 1u;
+      const uint32_t sgn_ab = __popc((H.abJb[pb] >> M) & bs) & 1u;
+      const int r2 = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
+      ent = make_int2(r2, pb | ((i == q) ? 1 << 16 : 0) | (int)(sgn_s << 17) | (int)(sgn_ab << 18));
+      keep = !a.row_nz || a.row_nz[r2] != 0u;
+    }
+    const uint64_t m = __ballot(keep);
+    const uint64_t below = (jb == 0) ? 0ull : (~0ull >> (64 - jb));
+    if (keep) L.stage[__popcll(m & below)] = ent;
+    if (jb == 0) {
+      L.nstage = __popcll(m);
+      L.own = (!a.row_nz || a.row_nz[brow] != 0u) ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  const int nst = L.nstage;
+  const bool own = L.own != 0;
+  if (nst == 0 && !own) {
+    if (live) {
+      const double v = a.pb[(int64_t)brow * a.da + col] + a.pa_t[(int64_t)col * a.db + brow];
+      ((double*)a.sigma)[(int64_t)brow * a.da + col] = v;
+    }
+    return;
+  }
+  for (int k = tid; k < M; k += nt) {
+    double v = 0.0;
+    uint32_t o = bs;
+    while (o) {
+      const int l = __ffs(o) - 1;
+      o &= o - 1;
+      v += H.dC[k * 32 + (l + M)];
+    }
+    L.dmix[k] = v;
+  }
+  for (int i = tid; i < kMaxPairs * 2; i += nt) {
+    const double* B = H.sB + (size_t)i * 32;
+    double v = 0.0;
+    uint32_t o = bs;
+    while (o) {
+      const int l = __ffs(o) - 1;
+      o &= o - 1;
+      v += B[l + M];
+    }
+    L.srow[2 * i] = v;
+    L.srow[2 * i + 1] = -v;
+  }
+  // compact positions: block b of a row sits at byte 16 * bp[b] of a buffer
+  const uint32_t rbase = lds_addr(smem);
+  const int nbk = nblk_c[chunk];
+  const uint16_t* bp = bpos + (int64_t)chunk * nblk;
+  const uint32_t zslot = rbase + (uint32_t)nbk * 16u;
+  const uint32_t fbase = lds_addr(&L.fab[0][0]);
+  uint32_t ex[64];
+#pragma unroll
+  for (int x = 0; x < 64; ++x) ex[x] = zslot;
+  {
+    const RankTables* R = a.arank;
+    const int nemp = M - a.na;
+    const int nex = a.na * nemp;
+    uint32_t occ = s, emp = 0u;
+    int i = 0, ie = nemp;
+#pragma unroll
+    for (int x = 0; x < 64; ++x) {
+      if (x < nex) {
+        if (ie == nemp) {
+          i = __ffs(occ) - 1;
+          occ &= occ - 1;
+          emp = ~s & amask;
+          ie = 0;
+        }
+        const int e = __ffs(emp) - 1;
+        emp &= emp - 1;
+        ++ie;
+        const int p = min(i, e), q = max(i, e);
+        const int pid = pair_id(p, q);
+        const uint32_t t2 = s ^ (1u << i) ^ (1u << e);
+        const uint32_t r2 = (uint32_t)(R->lo[t2 & 255u] + R->hi[(t2 >> 8) & 255u]);
+        const uint32_t sab = __popc(H.abJa[pid] & s) & 1u;
+        const uint32_t ssg = __popc(H.sJ[pid] & s) & 1u;
+        const uint32_t O = (i == q) ? 1u : 0u;
+        const uint32_t amp = live ? rbase + (uint32_t)bp[r2 >> 1] * 16u + (r2 & 1u) * 8u : zslot;
+        ex[x] = amp | ((((uint32_t)pid * 2u + O) * 2u + sab) * 8u << 17) | (ssg << 29);
+      }
+    }
+  }
+  const uint32_t ocol = live ? rbase + (uint32_t)bp[col >> 1] * 16u + ((uint32_t)col & 1u) * 8u : zslot;
+  int blk[kCPerThread];
+#pragma unroll
+  for (int k = 0; k < kCPerThread; ++k) {
+    const int i = k * nt + tid;
+    blk[k] = i < nbk ? (int)blist[(int64_t)chunk * kCMaxBlk + i] : 0;
+  }
+  uint32_t occ_off[16];
+  {
+    const uint32_t dbase = lds_addr(&L.bdress[0][0]);
+    const uint32_t zero = lds_addr(&L.bdress[0][kMaxOrb]);
+    uint32_t o = s;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      occ_off[j] = o ? dbase + (uint32_t)(__ffs(o) - 1) * 8u : zero;
+      o &= o - 1;
+    }
+  }
+  const int occ_groups = (__popc(s) + 7) >> 3;
+  if (tid == 0) {
+    *(__attribute__((address_space(3))) double*)(uintptr_t)zslot = 0.0;
+    *(__attribute__((address_space(3))) double*)(uintptr_t)(zslot + kCBuf1) = 0.0;
+    L.bdress[0][kMaxOrb] = 0.0;
+    L.bdress[1][kMaxOrb] = 0.0;
+  }
+  const double* psi = (const double*)a.psi;
+  const int ownoff = own ? 1 : 0;
+  const int nitems = ownoff + nst;  // item 0 the own row when kept, then the stages
+  auto src_of = [&](int it) -> int { return (own && it == 0) ? brow : L.stage[it - ownoff].x; };
+  // coefficient and dressing values of stage item `it`, thread tid's entries
+  auto load_coef = [&](int it, double& f_ld, double& d_ld) {
+    const int info = L.stage[it - ownoff].y;
+    const int pb = info & 0xffff, Ob = (info >> 16) & 1;
+    f_ld = 0.0;
+    d_ld = 0.0;
+    if (tid < kMaxPairs * 2) f_ld = H.abF[((size_t)(tid >> 1) * kMaxPairs + pb) * 4 + (tid & 1) * 2 + Ob];
+    if (tid < M) d_ld = H.sB[(size_t)((kMaxPairs + pb) * 2 + Ob) * 32 + tid];
+  };
+  auto write_coef = [&](int P, int it, double f_ld, double d_ld) {
+    const int info = L.stage[it - ownoff].y;
+    if (tid < kMaxPairs * 2) {
+      const double f = ((info >> 18) & 1) ? -f_ld : f_ld;
+      L.fab[P][2 * tid] = f;
+      L.fab[P][2 * tid + 1] = -f;
+    }
+    if (tid < M) L.bdress[P][tid] = ((info >> 17) & 1) ? -d_ld : d_ld;
+  };
+  double acc = 0.0;
+  // prologue: item 0's row into buffer 0 (and its tables, for a stage)
+  stage_blocks(rbase, psi + (int64_t)src_of(0) * a.da, blk, nbk, tid, nt);
+  if (!own) {
+    double f_ld, d_ld;
+    load_coef(0, f_ld, d_ld);
+    write_coef(0, 0, f_ld, d_ld);
+  }
+  auto step = [&](auto pc, auto ownc, int it) {
+    constexpr int P = decltype(pc)::value;
+    constexpr bool kOwn = decltype(ownc)::value;
+    constexpr uint32_t kBuf = P ? kCBuf1 : 0u;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();  // item it staged and its tables written; reads of the other buffer done
+    const bool nxt = it + 1 < nitems;
+    double f_ld = 0.0, d_ld = 0.0;
+    if (nxt) {
+      load_coef(it + 1, f_ld, d_ld);
+      stage_blocks(rbase + (P ? 0u : kCBuf1), psi + (int64_t)src_of(it + 1) * a.da, blk, nbk, tid, nt);
+    }
+    if (kOwn) {
+      // alpha-beta diagonal and the alpha singles' beta dressing (buffer 0)
+      double v = 0.0;
+      uint32_t o = s;
+      while (o) {
+        const int i = __ffs(o) - 1;
+        o &= o - 1;
+        v += L.dmix[i];
+      }
+      acc += v * lds_load<double>(ocol);
+#pragma unroll
+      for (int x = 0; x < 64; ++x) {
+        const uint32_t e = ex[x];
+        const int fi = (int)(((((e >> 17) & 0xfffu) / 8u) & ~1u) | ((e >> 29) & 1u));
+        acc += L.srow[fi] * lds_load<double>(e & 0x1ffffu);
+      }
+      asm volatile("" : "+v"(acc));
+    } else {
+#pragma unroll
+      for (int x = 0; x < 64; ++x) asm volatile("" : "+v"(ex[x]));
+      double dr = 0.0;
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+        if (g < occ_groups) {
+          double v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = lds_load<double>(occ_off[g * 8 + j] + (P ? kBd1 : 0u));
+#pragma unroll
+          for (int j = 0; j < 8; ++j) dr += v[j];
+        }
+      double sum = dr * lds_load<double>(ocol + kBuf);
+#pragma unroll
+      for (int x = 0; x < 64; ++x) {
+        const uint32_t e2 = ex[x];
+        sum += lds_load<double>(fbase + ((e2 >> 17) & 0xfffu) + (P ? kFab1 : 0u)) *
+               lds_load<double>((e2 & 0x1ffffu) + kBuf);
+      }
+      acc += sum;
+      asm volatile("" : "+v"(acc));
+    }
+    if (nxt) write_coef(P ? 0 : 1, it + 1, f_ld, d_ld);
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using BF = std::integral_constant<bool, false>;
+  using BT = std::integral_constant<bool, true>;
+  int it = 0;
+  if (own) step(I0(), BT(), it++);
+  if ((it & 1) && it < nitems) step(I1(), BF(), it++);
+  for (; it + 1 < nitems; it += 2) {
+    step(I0(), BF(), it);
+    step(I1(), BF(), it + 1);
+  }
+  if (it < nitems) step(I0(), BF(), it);
+
+  if (live) {
+    const double v = acc + a.pb[(int64_t)brow * a.da + col] + a.pa_t[(int64_t)col * a.db + brow];
+    ((double*)a.sigma)[(int64_t)brow * a.da + col] = v;
+  }
+}
+
 // ---------------------------------------------------------------- generic
 
 struct GenericArgs {
@@ -776,6 +1045,18 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   ma.row_nz = nz_b;
   const int nt = Hm->threads[sizeof(T) == 4 ? 1 : 0];
   ma.nchunk = (da + nt - 1) / nt;
+  if (sizeof(T) == 8 && nt == kCMixedThreads && row_staging_compact() && W->c_ok && (da % 2) == 0 &&
+      ((uintptr_t)psi & 15u) == 0) {
+    // compact, double-buffered staging (buffer 0 | buffer 1 at kCBuf1, each
+    // with its zero slot)
+    const size_t cshm = (size_t)kCBuf1 + ((size_t)W->c_max + 1) * 16;
+    HYP_HIP(hipFuncSetAttribute((const void*)k_mixed_c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cshm));
+    const int64_t nblk = (int64_t)8 * ((db + 7) / 8) * ma.nchunk;
+    HYP_LAUNCH("k_mixed", k_mixed_c, dim3((unsigned)nblk), dim3(nt), cshm, st, ma, W->c_bpos, W->c_blist, W->c_nb,
+               (da + 1) / 2);
+    HYP_HIP(hipGetLastError());
+    return HYP_OK;
+  }
   // the row plus one zero slot (index da) that padded excitation entries read
   const size_t shm = ((size_t)(da + 1) * sizeof(T) + 15) & ~(size_t)15;
   if (shm > 48 * 1024)
@@ -1123,6 +1404,19 @@ hyp_status hyp_build_hamiltonian(hyp_sector sh, const uint32_t* x_mask, const ui
       hyp_ham_destroy(hh);
       return rb;
     }
+    // compact staging tables of the FP64 mixed pass (768-column chunks);
+    // where they fit, 768 threads is the default FP64 width
+    if (S->da % 2 == 0 && S->da > kCMixedThreads - 64) {
+      int mx = 0;
+      rb = build_compact_tables(S, kCMixedThreads, &hh->w.c_bpos, &hh->w.c_blist, &hh->w.c_nb, &mx, st);
+      if (rb != HYP_OK) {
+        hyp_ham_destroy(hh);
+        return rb;
+      }
+      hh->w.c_max = mx;
+      hh->w.c_ok = mx <= kCMaxBlk && (mx + kCMixedThreads - 1) / kCMixedThreads <= kCPerThread;
+      if (hh->w.c_ok) H.threads[0] = kCMixedThreads;
+    }
   }
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return cleanup_fail(e, "hyp_build_hamiltonian: upload sync");
@@ -1153,6 +1447,9 @@ hyp_status hyp_ham_destroy(hyp_ham hh) {
   (void)hipFree(hh->w.cb_rank);
   (void)hipFree(hh->w.cb_coef);
   (void)hipFree(hh->w.cb_n);
+  (void)hipFree(hh->w.c_bpos);
+  (void)hipFree(hh->w.c_blist);
+  (void)hipFree(hh->w.c_nb);
   delete hh;
   return HYP_OK;
 }

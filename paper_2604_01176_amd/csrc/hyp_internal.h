@@ -206,6 +206,39 @@ __device__ inline T lds_load(uint32_t a) {
   return *(const __attribute__((address_space(3))) T*)(uintptr_t)a;
 }
 
+// Compact staging of FP64 rows (the transition-value sweep, 512-column
+// chunks, and the mixed pass, 768-column chunks): a chunk stages only the
+// 16-byte blocks of a source row that its columns and their alpha single
+// excitations reach, into one of two LDS buffers, the second at a fixed offset that fits the
+// immediate offset of a ds_read.
+constexpr int kCMaxBlk = 4094;         // staged blocks per buffer: both buffers and zero slots below 2^17 B
+constexpr uint32_t kCBuf1 = 65520u;    // byte offset of the second buffer
+constexpr int kCPerThread = 8;         // staged blocks per thread at 512 threads
+constexpr int kCThreads = 512;         // chunk width of the sweep's compact tables
+constexpr int kCMixedThreads = 768;    // chunk width of the mixed pass's compact tables
+// 16 bytes per lane from global memory straight into LDS at lds_wave + 16 *
+// lane.  Written as one asm statement so that the compiler does not order
+// later LDS reads of the other buffer behind this copy: the caller waits for
+// it (s_waitcnt vmcnt(0)) and synchronises before reading what it wrote.
+__device__ inline void dma16(uint32_t lds_wave, const void* src) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(lds_wave), "v"(src)
+               : "memory");
+}
+
+// Stage chunk blocks blk[k] (k-th group of nt blocks) of one FP64 row.
+__device__ inline void stage_blocks(uint32_t buf, const double* row, const int (&blk)[kCPerThread], int nb, int tid,
+                                    int nt) {
+  const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < kCPerThread; ++k) {
+    const int base = k * nt + w * 64;  // wave-uniform
+    if (base < nb) {
+      const uint32_t dst = (uint32_t)__builtin_amdgcn_readfirstlane(buf + (uint32_t)base * 16u);
+      if (base + lane < nb) dma16(dst, row + 2 * (int64_t)blk[k]);
+    }
+  }
+}
+
 // shared entry points between translation units
 Sector* sector_of(hyp_sector h);
 Ham* ham_of(hyp_ham h);
@@ -231,8 +264,23 @@ struct HamWork {
   int* cb_rank = nullptr;
   double* cb_coef = nullptr;
   int* cb_n = nullptr;
+  // compact staging tables of the mixed pass (768-column chunks); c_ok when
+  // every chunk fits a buffer
+  uint16_t* c_bpos = nullptr;
+  uint16_t* c_blist = nullptr;
+  int* c_nb = nullptr;
+  int c_max = 0;
+  bool c_ok = false;
 };
 HamWork* work_of(hyp_ham h);
+// Compact staging tables of a string space for nt-column chunks, into new
+// allocations (caller frees): per chunk the position of every 16-byte block
+// of a row in its staged list (0xffff: not staged), the list, and its
+// length; *max_nb = the longest list.  Synchronous on st.
+hyp_status build_compact_tables(const Sector* S, int nt, uint16_t** bpos, uint16_t** blist, int** nb, int* max_nb,
+                                hipStream_t st);
+// process-wide row staging switch (hyp_set_row_staging): true = compact
+bool row_staging_compact();
 hyp_status ensure_binom();
 hyp_status validate_exc(const Sector* S, hyp_exc op);
 hyp_status pair_scratch(Sector* S, size_t n_doubles, double** out);

@@ -391,10 +391,6 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
 // products are formed.  Per-chunk tables, built once per string space:
 //   bpos[c][b]  position of 16-byte block b in chunk c's staged list
 //   blist[c][i] the staged blocks in ascending order, nblk_c[c] of them.
-constexpr int kCMaxBlk = 4094;         // staged blocks per buffer: both buffers and zero slots below 2^17 B
-constexpr uint32_t kCBuf1 = 65520u;    // byte offset of the second buffer (fits a ds_read offset)
-constexpr int kCPerThread = 8;         // staged blocks per thread at 512 threads
-
 __global__ void k_cs_mark(int da, int nt, int M, const uint32_t* __restrict__ astr, const RankTables* __restrict__ R,
                           int nblk, uint8_t* __restrict__ mark) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
@@ -447,29 +443,6 @@ __global__ void __launch_bounds__(256) k_cs_scan(const uint8_t* __restrict__ mar
       ++pos;
     } else {
       bpos[(int64_t)c * nblk + b] = 0xffffu;
-    }
-  }
-}
-
-// 16 bytes per lane from global memory straight into LDS at lds_wave + 16 *
-// lane.  Written as one asm statement so that the compiler does not order
-// later LDS reads of the other buffer behind this copy: the caller waits for
-// it (s_waitcnt vmcnt(0)) and synchronises before reading what it wrote.
-__device__ inline void dma16(uint32_t lds_wave, const void* src) {
-  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(lds_wave), "v"(src)
-               : "memory");
-}
-
-// Stage chunk blocks blk[k] (k-th group of nt blocks) of one FP64 row.
-__device__ inline void stage_blocks(uint32_t buf, const double* row, const int (&blk)[kCPerThread], int nb, int tid,
-                                    int nt) {
-  const int lane = tid & 63, w = tid >> 6;
-#pragma unroll
-  for (int k = 0; k < kCPerThread; ++k) {
-    const int base = k * nt + w * 64;  // wave-uniform
-    if (base < nb) {
-      const uint32_t dst = (uint32_t)__builtin_amdgcn_readfirstlane(buf + (uint32_t)base * 16u);
-      if (base + lane < nb) dma16(dst, row + 2 * (int64_t)blk[k]);
     }
   }
 }
@@ -1043,10 +1016,49 @@ TScratch g_ts[64];
 }  // namespace
 int g_row_staging = 0;  // 0 compact where it applies, 1 whole rows
 
-// Builds (once per string space and chunk width) the compact staging tables.
-static hyp_status compact_tables(Sector* S, TScratch& ts, int nt, int nchunk, hipStream_t st) {
+bool row_staging_compact() { return g_row_staging == 0; }
+
+hyp_status build_compact_tables(const Sector* S, int nt, uint16_t** bpos, uint16_t** blist, int** nb, int* max_nb,
+                                hipStream_t st) {
+  const int da = (int)S->da, nblk = (da + 1) / 2, nchunk = (da + nt - 1) / nt;
+  *bpos = nullptr;
+  *blist = nullptr;
+  *nb = nullptr;
+  *max_nb = 0;
+  uint8_t* mark = nullptr;
+  const int mwords = (int)(((size_t)nchunk * nblk + 3) / 4);
+  hipError_t e = hipMalloc(bpos, (size_t)nchunk * nblk * sizeof(uint16_t));
+  if (e == hipSuccess) e = hipMalloc(blist, (size_t)nchunk * kCMaxBlk * sizeof(uint16_t));
+  if (e == hipSuccess) e = hipMalloc(nb, (size_t)nchunk * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&mark, (size_t)mwords * 4);
+  std::vector<int> h((size_t)nchunk);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min(1024, (mwords + 255) / 256)), dim3(256), 0, st,
+                       (uint32_t*)mark, mwords);
+    hipLaunchKernelGGL(k_cs_mark, dim3((unsigned)((da + 255) / 256)), dim3(256), 0, st, da, nt, S->M, S->d_astr,
+                       S->d_arank, nblk, mark);
+    hipLaunchKernelGGL(k_cs_scan, dim3((unsigned)nchunk), dim3(256), 0, st, mark, nblk, *bpos, *blist, *nb);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), *nb, (size_t)nchunk * sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (mark) (void)hipFree(mark);
+  if (e != hipSuccess) {
+    (void)hipFree(*bpos);
+    (void)hipFree(*blist);
+    (void)hipFree(*nb);
+    *bpos = nullptr;
+    *blist = nullptr;
+    *nb = nullptr;
+    return hip_fail(e, "build_compact_tables");
+  }
+  *max_nb = h.empty() ? 0 : *std::max_element(h.begin(), h.end());
+  return HYP_OK;
+}
+
+// The sweep's compact staging tables (once per string space and chunk width).
+static hyp_status compact_tables(Sector* S, TScratch& ts, int nt, hipStream_t st) {
   if (ts.c_M == S->M && ts.c_na == S->na && ts.c_nt == nt) return HYP_OK;
-  const int da = (int)S->da, nblk = (da + 1) / 2;
   HYP_HIP(hipDeviceSynchronize());
   if (ts.c_bpos) HYP_HIP(hipFree(ts.c_bpos));
   if (ts.c_blist) HYP_HIP(hipFree(ts.c_blist));
@@ -1056,23 +1068,9 @@ static hyp_status compact_tables(Sector* S, TScratch& ts, int nt, int nchunk, hi
   ts.c_nb = nullptr;
   ts.c_M = ts.c_na = ts.c_nt = -1;
   ts.c_ok = false;
-  uint8_t* mark = nullptr;
-  HYP_HIP(hipMalloc(&ts.c_bpos, (size_t)nchunk * nblk * sizeof(uint16_t)));
-  HYP_HIP(hipMalloc(&ts.c_blist, (size_t)nchunk * kCMaxBlk * sizeof(uint16_t)));
-  HYP_HIP(hipMalloc(&ts.c_nb, (size_t)nchunk * sizeof(int)));
-  const int mwords = (int)(((size_t)nchunk * nblk + 3) / 4);
-  HYP_HIP(hipMalloc(&mark, (size_t)mwords * 4));
-  HYP_LAUNCH("k_zero_u32", k_zero_u32, dim3((unsigned)std::min(1024, (mwords + 255) / 256)), dim3(256), 0, st,
-             (uint32_t*)mark, mwords);
-  HYP_LAUNCH("k_cs_mark", k_cs_mark, dim3((unsigned)((da + 255) / 256)), dim3(256), 0, st, da, nt, S->M, S->d_astr,
-             S->d_arank, nblk, mark);
-  HYP_LAUNCH("k_cs_scan", k_cs_scan, dim3((unsigned)nchunk), dim3(256), 0, st, mark, nblk, ts.c_bpos, ts.c_blist,
-             ts.c_nb);
-  std::vector<int> h((size_t)nchunk);
-  HYP_HIP(hipMemcpyAsync(h.data(), ts.c_nb, (size_t)nchunk * sizeof(int), hipMemcpyDeviceToHost, st));
-  HYP_HIP(hipStreamSynchronize(st));
-  HYP_HIP(hipFree(mark));
-  const int mx = h.empty() ? 0 : *std::max_element(h.begin(), h.end());
+  int mx = 0;
+  hyp_status r = build_compact_tables(S, nt, &ts.c_bpos, &ts.c_blist, &ts.c_nb, &mx, st);
+  if (r != HYP_OK) return r;
   ts.c_max = mx;
   ts.c_ok = mx <= kCMaxBlk && (mx + nt - 1) / nt <= kCPerThread;
   ts.c_M = S->M;
@@ -1177,7 +1175,7 @@ static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* 
   const int64_t nblk = (int64_t)8 * ((nslot + 7) / 8) * a.nchunk;
   // compact staging: FP64 rows whose 16-byte blocks start at the row start
   if (dt == HYP_F64 && g_row_staging == 0 && nt == 512 && a.da % 2 == 0 && ((uintptr_t)psi & 15u) == 0) {
-    hyp_status r = compact_tables(S, ts, nt, a.nchunk, st);
+    hyp_status r = compact_tables(S, ts, nt, st);
     if (r != HYP_OK) return r;
     // LDS: buffer 0 | buffer 1 at kCBuf1 (each with its zero slot) | row pairs
     const size_t pairs_off = (size_t)kCBuf1 + ((size_t)ts.c_max + 1) * 16;

@@ -1,8 +1,9 @@
 """GPU parity of the compact, double-buffered row staging of the FP64
-transition-value sweep: the gradients equal those of whole-row staging bit
-for bit (the products and their order are the same), the oracle on samples
-of generators, the fallbacks (odd alpha dimension, chunks below 512 columns,
-FP32), support skipping, and the 32-qubit sweep both ways."""
+transition-value sweep and mixed pass: gradients and sigma equal those of
+whole-row staging bit for bit (the products and their order are the same),
+the oracle on samples of generators and rows, the fallbacks (odd alpha
+dimension, chunks below 512 columns, FP32), support skipping, and the
+32-qubit sweep and product both ways."""
 import time
 
 import numpy as np
@@ -134,4 +135,83 @@ def test_compact_staging_32q(hyp):
           flush=True)
     assert np.array_equal(out["compact"], out["rows"])
     del psi, sig
+    torch.cuda.empty_cache()
+
+
+def _apply(hyp, H, psi, staging):
+    try:
+        hyp.set_row_staging(staging)
+        out = H.apply(psi)
+        torch.cuda.synchronize()
+        return out
+    finally:
+        hyp.set_row_staging("compact")
+
+
+@pytest.mark.parametrize("M,na,nb", CASES)
+def test_compact_mixed_pass_bit_exact_and_oracle(hyp, M, na, nb):
+    """H psi with the compact, double-buffered mixed pass (FP64, 512-column
+    chunks) equals the whole-row mixed pass bit for bit, and the oracle on
+    sampled rows."""
+    h, g = synth.integrals(M, 400 + M)
+    x, z, c = synth.jw_pauli_list(h, g)
+    S = hyp.Sector(M, na, nb)
+    H = hyp.Hamiltonian(S, x, z, c)
+    p = synth.random_state(S.dim, 41 + M)
+    psi = _dev(p)
+    s_c = _apply(hyp, H, psi, "compact")
+    s_r = _apply(hyp, H, psi, "rows")
+    assert torch.equal(s_c, s_r)
+    rng = np.random.default_rng(M * 7 + nb)
+    idx = np.unique(np.concatenate([[0, S.dim - 1], rng.integers(0, S.dim, 150)]))
+    ref = oracle.apply_h(M, na, nb, x, z, c, p, out_idx=idx)
+    assert np.abs(s_c.cpu().numpy()[idx] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_compact_mixed_pass_with_support_skipping(hyp):
+    M, na, nb = 12, 6, 6
+    h, g = synth.integrals(M, 13)
+    x, z, c = synth.jw_pauli_list(h, g)
+    S = hyp.Sector(M, na, nb)
+    H = hyp.Hamiltonian(S, x, z, c)
+    idx = np.unique(oracle.rank(M, na, nb, synth.near_hf_bits(M, na, nb, 24, seed=9)))
+    val = np.random.default_rng(4).standard_normal(idx.size)
+    val /= np.linalg.norm(val)
+    psi = torch.zeros(S.dim, dtype=torch.float64, device="cuda")
+    psi[torch.from_numpy(idx).cuda()] = torch.from_numpy(val).cuda()
+    try:
+        hyp.set_support_skip(True)
+        s_c = _apply(hyp, H, psi, "compact")
+        s_r = _apply(hyp, H, psi, "rows")
+        hyp.set_support_skip(False)
+        s_d = _apply(hyp, H, psi, "compact")
+    finally:
+        hyp.set_support_skip(True)
+    assert torch.equal(s_c, s_r)
+    ref = oracle.apply_h_sparse(M, na, nb, x, z, c, idx, val)
+    a = s_c.cpu().numpy()
+    assert np.linalg.norm(a - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.linalg.norm(s_d.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_compact_mixed_pass_32q(hyp):
+    """32-qubit H psi both ways, bit for bit, timed."""
+    w = synth.WORKLOADS["h16_32q"]
+    x, z, c, _, _ = synth.hamiltonian(w)
+    S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    psi = _dev(synth.random_state(S.dim, 8))
+    out, times = {}, {}
+    for staging in ("compact", "rows"):
+        out[staging] = _apply(hyp, H, psi, staging)
+        t0 = time.perf_counter()
+        hyp.set_row_staging(staging)
+        H.apply(psi, out[staging])
+        torch.cuda.synchronize()
+        hyp.set_row_staging("compact")
+        times[staging] = (time.perf_counter() - t0) * 1e3
+    print(f"[staging] 32q H psi (768 threads): compact {times['compact']:.1f} ms, whole rows {times['rows']:.1f} ms",
+          flush=True)
+    assert torch.equal(out["compact"], out["rows"])
+    del psi, out
     torch.cuda.empty_cache()
