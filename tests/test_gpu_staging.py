@@ -215,3 +215,35 @@ def test_compact_mixed_pass_32q(hyp):
     assert torch.equal(out["compact"], out["rows"])
     del psi, out
     torch.cuda.empty_cache()
+
+
+def test_compact_mixed_pass_in_captured_graph_24q(hyp):
+    """The ADAPT evaluation graph captured with the compact mixed pass (24
+    qubits: 924-column alpha space, two 768-column chunks), replayed with
+    eager work in between, against eager evaluations with whole-row staging."""
+    w = synth.WORKLOADS["h12_24q"]
+    x, z, c, _, _ = synth.hamiltonian(w)
+    cre, ann, _ = synth.canonical_pool(w.n_orb)
+    S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    Ag = hyp.Adapt(H, cre, ann, max_iter=8, use_graph=True)
+    Ae = hyp.Adapt(H, cre, ann, max_iter=8, use_graph=False)
+    ops = [int(v) for v in np.random.default_rng(1).integers(0, len(cre), 6)]
+    th = np.linspace(-0.25, 0.35, 6)
+    Ag.set_ansatz(ops, th)
+    Ae.set_ansatz(ops, th)
+    outs = []
+    for rep in range(3):
+        th2 = th * (1 + 0.2 * rep)
+        e_g, g_g = Ag.eval(th2)
+        try:
+            hyp.set_row_staging("rows")
+            e_e, g_e = Ae.eval(th2)
+        finally:
+            hyp.set_row_staging("compact")
+        outs.append((e_g, g_g, e_e, g_e))
+        torch.cuda.synchronize()
+    for e_g, g_g, e_e, g_e in outs:
+        assert abs(e_g - e_e) < 1e-13
+        assert np.abs(g_g - g_e).max() < 1e-12
+    assert len({round(o[0], 12) for o in outs}) == 3  # the replays saw the new parameters
