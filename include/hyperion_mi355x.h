@@ -131,7 +131,9 @@ int hyp_ham_is_structured(hyp_ham h);
  * thread per alpha column): times the candidates {128,...,1024} on this
  * Hamiltonian with reps applications each (HIP events on `stream`), keeps
  * the fastest for later hyp_apply_h calls on h in that storage type (FP64
- * and FP32 keep separate widths) and returns it.  Overwrites sigma_dev.  A
+ * and FP32 keep separate widths) and returns it.  In FP64 the 768-thread
+ * candidate is the compact, double-buffered mixed pass wherever its staging
+ * tables exist (see hyp_set_row_staging).  Overwrites sigma_dev.  A
  * generic (non-structured) Hamiltonian returns 0 threads. */
 hyp_status hyp_tune_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* sigma_dev,
                             int reps, void* stream, int* best_threads, double* best_ms);
@@ -222,15 +224,19 @@ hyp_status hyp_pool_gradients(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_
  * Process-wide setting. */
 hyp_status hyp_set_sweep_mode(int mode);
 
-/* Row staging of mode 2's kernel (a tuning and testing control, no effect on
- * results): 0 (default) stages, for FP64 state vectors whose rows are whole
- * 16-byte blocks and 512-column chunks, only the blocks of each source row
- * that the chunk's columns and their single excitations reach, into two
+/* Row staging of mode 2's kernel and of the FP64 mixed pass of hyp_apply_h
+ * (a tuning and testing control, no effect on results): 0 (default) stages,
+ * for FP64 state vectors whose rows are whole 16-byte blocks, only the blocks
+ * of each source row that a column chunk (512 columns in the sweep, 768 in
+ * the mixed pass) and its columns' single excitations reach, into two
  * alternating LDS buffers so that the next row's copy overlaps this row's
- * products (per-device tables of about C(M,N_a) * 2.1 bytes, built on the
- * first sweep of a string space; falls back to whole rows where a chunk needs
- * more than 4094 blocks); 1 always stages whole rows.  Both give the same
- * gradients bit for bit.  Process-wide; HYP_ERR_ARG unless mode is 0 or 1. */
+ * products.  Tables of about C(M,N_a) * 2.1 bytes: the sweep's per device,
+ * for up to eight string spaces, built on the first sweep of one; the mixed
+ * pass's with the Hamiltonian (hyp_build_hamiltonian), where the mixed pass
+ * then defaults to 768 threads.  Falls back to whole rows where a chunk needs
+ * more than 4094 blocks.  1 always stages whole rows (hyp_apply_h: calls and
+ * graph captures made after the switch).  Both give the same gradients and
+ * sigma bit for bit.  Process-wide; HYP_ERR_ARG unless mode is 0 or 1. */
 hyp_status hyp_set_row_staging(int mode);
 
 /* Kind of the pool generators (the paper's ADAPT-VQE description names the

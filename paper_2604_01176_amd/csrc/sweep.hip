@@ -1004,13 +1004,18 @@ struct TScratch {
   int2* crows = nullptr;
   int* rcount = nullptr;
   size_t crows_cap = 0;
-  // compact staging tables of k_tdens_rows_c for one (orbitals, alpha
-  // electrons, chunk width); c_ok: every chunk fits the two buffers
-  uint16_t* c_bpos = nullptr;
-  uint16_t* c_blist = nullptr;
-  int* c_nb = nullptr;
-  int c_M = -1, c_na = -1, c_nt = -1, c_max = 0;
-  bool c_ok = false;
+  // compact staging tables of k_tdens_rows_c, one entry per (orbitals,
+  // alpha electrons, chunk width) seen on the device (batched sweeps mix
+  // string spaces), oldest replaced first; ok: every chunk fits the buffers
+  struct CTab {
+    uint16_t* bpos = nullptr;
+    uint16_t* blist = nullptr;
+    int* nb = nullptr;
+    int M = -1, na = -1, nt = -1, max = 0;
+    bool ok = false;
+  };
+  CTab ctab[8];
+  int ctab_next = 0;
 };
 TScratch g_ts[64];
 }  // namespace
@@ -1056,26 +1061,32 @@ hyp_status build_compact_tables(const Sector* S, int nt, uint16_t** bpos, uint16
   return HYP_OK;
 }
 
-// The sweep's compact staging tables (once per string space and chunk width).
-static hyp_status compact_tables(Sector* S, TScratch& ts, int nt, hipStream_t st) {
-  if (ts.c_M == S->M && ts.c_na == S->na && ts.c_nt == nt) return HYP_OK;
-  HYP_HIP(hipDeviceSynchronize());
-  if (ts.c_bpos) HYP_HIP(hipFree(ts.c_bpos));
-  if (ts.c_blist) HYP_HIP(hipFree(ts.c_blist));
-  if (ts.c_nb) HYP_HIP(hipFree(ts.c_nb));
-  ts.c_bpos = nullptr;
-  ts.c_blist = nullptr;
-  ts.c_nb = nullptr;
-  ts.c_M = ts.c_na = ts.c_nt = -1;
-  ts.c_ok = false;
+// The sweep's compact staging tables of a string space and chunk width
+// (built on first use).
+static hyp_status compact_tables(Sector* S, TScratch& ts, int nt, hipStream_t st, const TScratch::CTab** out) {
+  for (const TScratch::CTab& t : ts.ctab)
+    if (t.M == S->M && t.na == S->na && t.nt == nt) {
+      *out = &t;
+      return HYP_OK;
+    }
+  TScratch::CTab& t = ts.ctab[ts.ctab_next];
+  if (t.bpos || t.blist || t.nb) {
+    HYP_HIP(hipDeviceSynchronize());  // queued launches may still read the replaced entry
+    if (t.bpos) HYP_HIP(hipFree(t.bpos));
+    if (t.blist) HYP_HIP(hipFree(t.blist));
+    if (t.nb) HYP_HIP(hipFree(t.nb));
+  }
+  t = TScratch::CTab();
   int mx = 0;
-  hyp_status r = build_compact_tables(S, nt, &ts.c_bpos, &ts.c_blist, &ts.c_nb, &mx, st);
+  hyp_status r = build_compact_tables(S, nt, &t.bpos, &t.blist, &t.nb, &mx, st);
   if (r != HYP_OK) return r;
-  ts.c_max = mx;
-  ts.c_ok = mx <= kCMaxBlk && (mx + nt - 1) / nt <= kCPerThread;
-  ts.c_M = S->M;
-  ts.c_na = S->na;
-  ts.c_nt = nt;
+  t.max = mx;
+  t.ok = mx <= kCMaxBlk && (mx + nt - 1) / nt <= kCPerThread;
+  t.M = S->M;
+  t.na = S->na;
+  t.nt = nt;
+  ts.ctab_next = (ts.ctab_next + 1) % 8;
+  *out = &t;
   return HYP_OK;
 }
 
@@ -1175,17 +1186,18 @@ static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* 
   const int64_t nblk = (int64_t)8 * ((nslot + 7) / 8) * a.nchunk;
   // compact staging: FP64 rows whose 16-byte blocks start at the row start
   if (dt == HYP_F64 && g_row_staging == 0 && nt == 512 && a.da % 2 == 0 && ((uintptr_t)psi & 15u) == 0) {
-    hyp_status r = compact_tables(S, ts, nt, st);
+    const TScratch::CTab* ct = nullptr;
+    hyp_status r = compact_tables(S, ts, nt, st, &ct);
     if (r != HYP_OK) return r;
     // LDS: buffer 0 | buffer 1 at kCBuf1 (each with its zero slot) | row pairs
-    const size_t pairs_off = (size_t)kCBuf1 + ((size_t)ts.c_max + 1) * 16;
+    const size_t pairs_off = (size_t)kCBuf1 + ((size_t)ct->max + 1) * 16;
     const size_t cshm = std::max(pairs_off + (size_t)std::max(a.K, a.Kid) * sizeof(int2),
                                  (size_t)(nt / 64) * kBins * sizeof(double));
-    if (ts.c_ok && cshm <= 160 * 1024 - 256) {
+    if (ct->ok && cshm <= 160 * 1024 - 256) {
       HYP_HIP(hipFuncSetAttribute((const void*)k_tdens_rows_c, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)cshm));
-      HYP_LAUNCH("k_tdens_rows", k_tdens_rows_c, dim3((unsigned)nblk), dim3(nt), cshm, st, a, ts.c_bpos, ts.c_blist,
-                 ts.c_nb, (a.da + 1) / 2, (uint32_t)pairs_off);
+      HYP_LAUNCH("k_tdens_rows", k_tdens_rows_c, dim3((unsigned)nblk), dim3(nt), cshm, st, a, ct->bpos, ct->blist,
+                 ct->nb, (a.da + 1) / 2, (uint32_t)pairs_off);
       HYP_LAUNCH("k_tdens_rows_final", k_tdens_rows_final, dim3((kBins * kStageW + kBins + 255) / 256), dim3(256),
                  0, st, ts.rpart, a.n_eb, a.n_id, a.nchunk, Ta, Tb, Tab);
       return HYP_OK;
