@@ -41,8 +41,10 @@ def _grads(hyp, S, ops, psi, sig, staging):
 
 # (11,5), (12,6), (12,5), (13,6), (14,7): even alpha dimension above 448,
 # compact staging; (13,5), (14,4): odd alpha dimension, whole rows; (10,5):
-# 256-column chunks, whole rows
-CASES = [(11, 5, 5), (11, 5, 3), (12, 6, 6), (12, 5, 4), (13, 6, 2), (13, 5, 1), (14, 7, 1), (10, 5, 5), (14, 4, 2)]
+# 256-column chunks, whole rows; N_beta = 0 and N_beta = M: no beta singles
+# (no stages, one identity slice)
+CASES = [(11, 5, 5), (11, 5, 3), (12, 6, 6), (12, 5, 4), (13, 6, 2), (13, 5, 1), (14, 7, 1), (10, 5, 5), (14, 4, 2),
+         (12, 6, 0), (12, 5, 12)]
 
 
 @pytest.mark.parametrize("M,na,nb", CASES)
