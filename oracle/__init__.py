@@ -70,6 +70,7 @@ def lib():
         L.orc_apply_tau.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                     ctypes.POINTER(ctypes.c_uint32)]
         L.orc_pool_gradients.argtypes = [ci, ci, ci, i64, u32p, u32p, f64p, f64p, f64p]
+        L.orc_pool_gradients_sparse.argtypes = [ci, ci, ci, i64, u32p, u32p, i64, i64p, f64p, f64p, f64p]
         L.orc_apply_generator.argtypes = [ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, f64p, f64p]
         L.orc_rotate.argtypes = [ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, f64p]
         L.orc_set_qubit_excitations.restype = None
@@ -196,6 +197,18 @@ def pool_gradients(M, na, nb, cre, ann, psi, sigma):
     cre, ann, psi, sigma = _u32(cre), _u32(ann), _f64(psi), _f64(sigma)
     out = np.empty(cre.size)
     lib().orc_pool_gradients(M, na, nb, cre.size, _p(cre), _p(ann), _p(psi), _p(sigma), _p(out))
+    return out
+
+
+def pool_gradients_sparse(M, na, nb, cre, ann, nz, psi, sigma):
+    """The same g_k for a psi whose nonzeros are the sector indices nz (each
+    once): the pair sum taken over pairs with a listed end only, exact since
+    every other pair contributes 0 (psi and sigma dense, all dim entries)."""
+    cre, ann, psi, sigma = _u32(cre), _u32(ann), _f64(psi), _f64(sigma)
+    nz = np.ascontiguousarray(nz, dtype=np.int64)
+    out = np.empty(cre.size)
+    lib().orc_pool_gradients_sparse(M, na, nb, cre.size, _p(cre), _p(ann), nz.size, _p(nz), _p(psi), _p(sigma),
+                                    _p(out))
     return out
 
 

@@ -256,6 +256,38 @@ void orc_pool_gradients(int M, int na, int nb, int64_t nops, const uint32_t *cre
     }
 }
 
+/*
+ * The same pool gradients when psi is given with the list of its nonzero
+ * sector indices nz[0..n_nz) (psi and sigma still dense).  Every pair
+ * (D, D' = tau D) of g_k = 2 sum s (sigma[D'] psi[D] - sigma[D] psi[D'])
+ * whose D and D' both lie outside the list contributes exactly 0, so the sum
+ * is split into its two halves and each is taken over the listed states only:
+ *   2 sum_{b listed, tau b != 0}       s(b)  sigma[tau b]      psi[b]
+ * - 2 sum_{b listed, tau^dag b != 0}   s'(b) sigma[tau^dag b] psi[b],
+ * where tau^dag = a+_{a1} a+_{a2} a_{c2} a_{c1} is applied literally (the
+ * excitation with creation and annihilation masks swapped) and its sign
+ * s' = <tau^dag b| tau^dag |b> equals <b| tau |tau^dag b> (real matrix
+ * elements).  A listed index must be a nonzero of psi, each listed once.
+ */
+void orc_pool_gradients_sparse(int M, int na, int nb, int64_t nops, const uint32_t *cre,
+                               const uint32_t *ann, int64_t n_nz, const int64_t *nz,
+                               const double *psi, const double *sigma, double *grad) {
+    sector_t S; sector_init(&S, M, na, nb);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nops; ++k) {
+        double g = 0.0;
+        for (int64_t i = 0; i < n_nz; ++i) {
+            int64_t d = nz[i];
+            uint32_t b = sector_unrank(&S, d), bp;
+            int s = orc_apply_tau(cre[k], ann[k], b, &bp);
+            if (s) g += 2.0 * s * sigma[sector_rank(&S, bp)] * psi[d];
+            s = orc_apply_tau(ann[k], cre[k], b, &bp);
+            if (s) g -= 2.0 * s * sigma[sector_rank(&S, bp)] * psi[d];
+        }
+        grad[k] = g;
+    }
+}
+
 /* out = A psi  (A = tau - tau^dagger), out must not alias psi */
 void orc_apply_generator(int M, int na, int nb, uint32_t cre, uint32_t ann,
                          const double *psi, double *out) {

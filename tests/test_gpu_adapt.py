@@ -1,8 +1,21 @@
 """GPU ADAPT-VQE driver against the oracle ADAPT loop (scipy BFGS) on the same
 seeded workloads.  Parity is on selections and converged energies, not on
-optimiser paths: the oracle is teacher-forced to the GPU's pick whenever that
-pick lies inside the oracle's own tie set (several selections are correct
-when |g| ties exactly)."""
+optimiser paths.
+
+Selections are checked twice.
+  * Strictly: at every iteration the oracle evaluates the pool gradients on
+    the GPU run's own state (its ansatz and parameters rebuilt with the
+    oracle's rotations); the GPU's pick must lie in that gradient vector's tie
+    set, |g_k| >= max|g| (1 - 1e-9), the selection rule with its FP64
+    tolerance, plus 1e-12 absolute for the rounding of the two evaluations.
+  * The oracle's own trajectory: scipy's BFGS and the GPU's BFGS both stop at
+    max |dE/dtheta| <= 1e-9 but at slightly different parameters, so the two
+    runs' pool gradients differ by a measured delta = max_k |g_gpu-state -
+    g_oracle-state|.  When the oracle's own argmax differs from the GPU's pick
+    the oracle is teacher-forced to it, which is accepted only when the pick
+    is within 2 delta (absolute) of the oracle's maximum; forced selections
+    are counted and printed.
+"""
 import numpy as np
 import pytest
 
@@ -14,11 +27,20 @@ import synth
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
+TIE_TOL = 1e-9
+
 
 @pytest.fixture(scope="module")
 def hyp():
     import paper_2604_01176_amd as hyp
     return hyp
+
+
+def _grads(prob, psi):
+    sig = prob.hpsi(psi)
+    if isinstance(prob, DenseSectorProblem):
+        return prob.gradients(psi, sig)
+    return oracle.pool_gradients(prob.M, prob.na, prob.nb, prob.cre, prob.ann, psi, sig)
 
 
 def _run_pair(hyp, w, n_iter, dtype="f64", use_graph=True):
@@ -27,8 +49,9 @@ def _run_pair(hyp, w, n_iter, dtype="f64", use_graph=True):
     S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
     H = hyp.Hamiltonian(S, x, z, c)
     A = hyp.Adapt(H, cre, ann, dtype=dtype, max_iter=n_iter + 1, use_graph=use_graph)
-    recs = []
+    recs, before = [], []
     for it in range(n_iter):
+        before.append(A.ansatz())  # the state the GPU selects on
         r = A.iterate()
         recs.append(r)
         if r["selected"] < 0:
@@ -39,17 +62,24 @@ def _run_pair(hyp, w, n_iter, dtype="f64", use_graph=True):
     checks = []
 
     def force(it, gvec, own):
-        # the GPU pick must be the oracle's argmax up to a near-tie: both
-        # optimisers stop at max|dE/dtheta| <= 1e-9, so gradients of the two
-        # runs differ by ~1e-9; below |g| ~ 1e-7 the selection is noise
         k = sel[it]
+        ops_b, th_b = before[it]
+        g_gpu_state = _grads(prob, prob.state([int(o) for o in ops_b], np.asarray(th_b)))
+        gm_gpu = float(np.abs(g_gpu_state).max())
+        # strict: the pick is in the tie set of the exact gradients on the GPU's state
+        assert abs(g_gpu_state[k]) >= gm_gpu * (1 - TIE_TOL) - 1e-12, (it, k, abs(g_gpu_state[k]), gm_gpu)
+        delta = float(np.abs(g_gpu_state - gvec).max())
         gm = float(np.abs(gvec).max())
-        checks.append((it, k, own, float(abs(gvec[k])), gm))
-        assert abs(gvec[k]) >= gm * (1 - 1e-6) - 1e-7, (it, k, own, abs(gvec[k]), gm)
+        checks.append((it, k, own, float(abs(gvec[k])), gm, delta))
+        if k != own:
+            assert abs(gvec[k]) >= gm * (1 - TIE_TOL) - 2 * delta, (it, k, own, abs(gvec[k]), gm, delta)
         return k
 
     log = run_adapt(prob, len(sel), force=force)
     log.checks = checks
+    print(f"forced selections: {log.forced} of {len(log.selected)}; "
+          f"max gradient difference between the two runs' states: "
+          f"{max((ch[5] for ch in checks), default=0.0):.2e}", flush=True)
     return A, recs, sel, log, (x, z, c, h, g)
 
 
@@ -58,8 +88,9 @@ def test_adapt_8q_fp64_parity_and_fci():
     w = synth.WORKLOADS["h4_8q"]
     A, recs, sel, log, (x, z, c, h, g) = _run_pair(hyp, w, w.iterations)
     n = len(log.selected)  # the oracle may stop earlier (max|g| < 1e-10 at noise level)
-    assert n >= 1 and log.selected == sel[:n]  # every pick passed the near-tie check in force()
-    print("selection checks (it, gpu, oracle, |g_gpu_pick|, max|g|):", log.checks)
+    assert n >= 1 and log.selected == sel[:n]  # every pick passed the checks in force()
+    print("selection checks (it, gpu, oracle, |g_gpu_pick|, max|g|, delta):", log.checks)
+    assert log.forced == sum(1 for ch in log.checks if ch[1] != ch[2])
     e_gpu = np.array([r["energy"] for r in recs if r["selected"] >= 0])
     e_orc = np.array(log.energies)
     assert np.abs(e_gpu[:n] - e_orc).max() < 1e-9
@@ -105,7 +136,10 @@ def test_adapt_16q_fp64_parity():
     e_gpu = np.array([r["energy"] for r in recs if r["selected"] >= 0])
     n = len(log.selected)
     assert n == len(sel) and log.selected == sel
-    print("selection checks (it, gpu, oracle, |g_gpu_pick|, max|g|):", log.checks)
+    print("selection checks (it, gpu, oracle, |g_gpu_pick|, max|g|, delta):", log.checks)
+    # both optimisers converge to the same parameters up to their tolerance
+    assert max(ch[5] for ch in log.checks) < 1e-5
+    assert log.forced == sum(1 for ch in log.checks if ch[1] != ch[2])
     assert np.abs(e_gpu - np.array(log.energies)).max() < 1e-9
     assert np.all(np.diff(e_gpu) <= 1e-10)
 
