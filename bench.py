@@ -36,7 +36,7 @@ def model(M, na, nb, T, pool):
     nnz = dim * conn
     pairs = (nnz - dim) // 2
     return dict(dim=dim, da=da, db=db, conn=conn, nnz=nnz, pairs=pairs, sa=sa, sb=sb,
-                dda=dda, ddb=ddb, T=T, pool=pool)
+                dda=dda, ddb=ddb, T=T, pool=pool, M=M, na=na, nb=nb)
 
 
 def hpsi_gather_bytes(m, S=8):
@@ -54,10 +54,14 @@ def kernel_flops(name, m):
         return 2.0 * dim * (1 + (sa + m["dda"] + sb + m["ddb"]) / 2), "alu"
     if name in ("k_tdens", "k_tdens_rows"):
         return 2.0 * dim * (sa + sb * (sa + 1)), "alu"
-    if name == "rocblas_dgemm_gram_a":
-        return 2.0 * m["da"] * m["da"] * m["db"], "mfma"
-    if name == "rocblas_dgemm_gram_b":
-        return 2.0 * m["db"] * m["db"] * m["da"], "mfma"
+    if name in ("k_core_gram_a", "k_core_gram_b"):
+        # 2 flops per (core, slot i, slot j, column): the S x S block of every
+        # (N-2)-electron core over the other spin's strings
+        M = m["M"]
+        N = m["na"] if name.endswith("_a") else m["nb"]
+        K = m["db"] if name.endswith("_a") else m["da"]
+        S = math.comb(M - N + 2, 2)
+        return 2.0 * math.comb(M, N - 2) * S * S * K, "alu"
     if name == "k_pool_grad":
         return 4.0 * m["pairs"], "alu"
     return 2.0 * m["nnz"], "alu"
@@ -282,9 +286,8 @@ def main():
     value = hpsi_bytes / (hpsi_ms * 1e-3) / 1e9
     sweep_kernels = ("k_pool_grad", "k_sum_chunks", "k_tdens", "k_tdens_reduce_ab", "k_tdens_reduce_a",
                      "k_tdens_final", "k_tdens_rows", "k_tdens_rows_final", "k_eb_rows", "k_gram_grad",
-                     "k_tdens_grad", "k_widen", "rocblas_dgemm_gram_a", "rocblas_dgemm_gram_b",
-                     "k_zero_u32", "k_support", "k_list_nz", "k_rows_compact", "k_gather_rows", "k_gather_cols",
-                     "k_zero_f64")
+                     "k_tdens_grad", "k_core_gram_a", "k_core_gram_b", "k_gram_transpose", "k_gram_widen",
+                     "k_zero_u32", "k_support", "k_list_nz", "k_rows_compact")
     sweep_ms = sum(prof.get(k, (0.0, 0))[0] for k in sweep_kernels) / args.steps
 
     # dominant kernel of the step and its roofline

@@ -158,12 +158,12 @@ hyp_status hyp_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* si
  * synchronisation), so the product can be captured in a HIP graph either
  * way.  The generic kernel always evaluates densely.
  * hyp_pool_gradients (modes 0 and 2): the row pairs and identity slices of
- * the transition values keep only source rows in psi's support; a Gram sum
- * over at most half of its range (beta rows for G_a, alpha columns for G_b)
- * runs on gathered rows or columns.  The call then waits on the host for the
- * support scan of psi (two counts), not for the kernels queued after it.
- * (hyp_pool_gradients already copies the generator list to the host to
- * validate it, so it is synchronous and not graph-capturable either way.)
+ * the transition values keep only source rows in psi's support; the
+ * same-spin Gram blocks of a core whose slots hold no nonzero psi row are
+ * zero without a product, and a Gram whose contraction range (beta rows for
+ * the alpha blocks, alpha columns for the beta blocks) is at most half in the
+ * support sums over the gathered support only.  These decisions are taken on
+ * the device too: the sweep never waits on the host and can be captured.
  * The pair kernel (mode 1 and candidate subsets) skips pairs whose two
  * determinants both lie outside psi's row or column support.
  * Results equal the dense evaluation up to summation order.  Near the
@@ -203,11 +203,26 @@ hyp_status hyp_expectation(hyp_sector s, hyp_dtype dtype, const void* a_dev, con
 
 /* grad_dev[k] = 2 <sigma| A_k psi> for the n_ops generators in ops_dev
  * (device array of hyp_exc), with sigma = H psi given: the ADAPT-VQE pool
- * gradient dE/dtheta at theta = 0 of appending exp(theta A_k).  FP64 output,
- * FP64 accumulation.  Every excitation is validated (host copy) first. */
+ * gradient dE/dtheta at theta = 0 of appending exp(theta A_k) ("Numerical
+ * performance": the gradient over the pool selects each new operator).  FP64
+ * output, FP64 accumulation.  Asynchronous and graph-capturable: nothing
+ * waits on the host (scratch grows, and per-string-space tables are built,
+ * on the first call for a sector size; capture after one eager call).
+ * Host-side arguments are validated before anything is enqueued
+ * (HYP_ERR_ARG: NULL pointer, bad dtype, n_ops outside [0, 2^24]).  The
+ * excitations live in device memory and are validated there by the kernels
+ * that read them with the rules of hyp_apply_excitation: an invalid one gets
+ * grad_dev[k] = NaN, is never used as an index, and is recorded for
+ * hyp_pool_check; the other gradients are unaffected. */
 hyp_status hyp_pool_gradients(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_dev,
                               int64_t n_ops, const void* psi_dev, const void* sigma_dev,
                               double* grad_dev, void* stream);
+
+/* Waits for `stream`, then reports the first invalid excitation that
+ * hyp_pool_gradients met on this device since the last report: HYP_ERR_ARG
+ * or HYP_ERR_SECTOR (the largest status met), its list position in
+ * hyp_last_error(), and clears the record; HYP_OK when there was none. */
+hyp_status hyp_pool_check(void* stream);
 
 /* Strategy of hyp_pool_gradients: 0 automatic (default), 1 the per-generator
  * pair kernel, 2 transition values, 3 transition values with per-stage bins.

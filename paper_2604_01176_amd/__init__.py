@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import HYP_F32, HYP_F64, HypError, HypExc, check
 
 __all__ = ["Sector", "Hamiltonian", "Adapt", "hyp_apply_h", "hyp_expectation",
-           "hyp_pool_gradients", "hyp_apply_excitation", "HypError", "HYP_F64", "HYP_F32",
+           "hyp_pool_gradients", "hyp_pool_check", "hyp_apply_excitation", "HypError", "HYP_F64", "HYP_F32",
            "exc_tensor", "profile_enable", "profile_reset", "profile_read"]
 
 _lib.load()
@@ -245,6 +245,8 @@ def exc_tensor(cre, ann, device="cuda"):
 
 
 def hyp_pool_gradients(sector: Sector, ops, psi, sigma, out=None):
+    """Enqueue g_k = 2 <sigma|A_k psi> on the current stream (no host wait).
+    Invalid excitations get NaN and are reported by hyp_pool_check()."""
     torch = _torch()
     if ops.dtype != torch.int32 or ops.dim() != 2 or ops.shape[1] != 2:
         raise TypeError("ops must be an int32 [n, 2] tensor of (cre, ann) masks")
@@ -256,6 +258,12 @@ def hyp_pool_gradients(sector: Sector, ops, psi, sigma, out=None):
                                          _dev_ptr(sigma, sector.dim, "sigma"),
                                          _dev_ptr(out, n, "grad"), _stream()))
     return out
+
+
+def hyp_pool_check():
+    """Wait for the current stream; raise HypError for the first invalid
+    excitation hyp_pool_gradients met on this device since the last check."""
+    check(_lib.load().hyp_pool_check(_stream()))
 
 
 def hyp_apply_excitation(sector: Sector, cre: int, ann: int, theta: float, psi):

@@ -220,9 +220,15 @@ constexpr int kCMixedThreads = 768;    // chunk width of the mixed pass's compac
 // lane.  Written as one asm statement so that the compiler does not order
 // later LDS reads of the other buffer behind this copy: the caller waits for
 // it (s_waitcnt vmcnt(0)) and synchronises before reading what it wrote.
+// m0 (the LDS base the copy reads at issue) is saved and restored inside the
+// statement, so code the compiler places around it keeps its own m0.
 __device__ inline void dma16(uint32_t lds_wave, const void* src) {
-  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(lds_wave), "v"(src)
-               : "memory");
+  uint32_t save;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %2, off\n\ts_mov_b32 m0, %0"
+      : "=&s"(save)
+      : "s"(lds_wave), "v"(src)
+      : "memory");
 }
 
 // Stage chunk blocks blk[k] (k-th group of nt blocks) of one FP64 row.
@@ -283,6 +289,28 @@ hyp_status build_compact_tables(const Sector* S, int nt, uint16_t** bpos, uint16
 bool row_staging_compact();
 hyp_status ensure_binom();
 hyp_status validate_exc(const Sector* S, hyp_exc op);
+// The same rules on the device, for lists that live in device memory:
+// HYP_OK, HYP_ERR_ARG (a mask bit >= 2M, |cre| != |ann|, |cre| not in {1, 2},
+// cre and ann overlap) or HYP_ERR_SECTOR (N_alpha / N_beta changed).
+__host__ __device__ inline int exc_status(hyp_exc op, int M) {
+  const uint32_t all = (2 * M == 32) ? 0xffffffffu : ((1u << (2 * M)) - 1u);
+  const uint32_t m = (1u << M) - 1u;
+  if ((op.cre | op.ann) & ~all) return HYP_ERR_ARG;
+  const int nc = __builtin_popcount(op.cre), na = __builtin_popcount(op.ann);
+  if (nc != na || nc < 1 || nc > 2) return HYP_ERR_ARG;
+  if (op.cre & op.ann) return HYP_ERR_ARG;
+  if (__builtin_popcount(op.cre & m) != __builtin_popcount(op.ann & m)) return HYP_ERR_SECTOR;
+  return HYP_OK;
+}
+// Record of the invalid excitations a gradient kernel met: rec[0] the
+// largest status, rec[1] the smallest list position (read and cleared by
+// hyp_pool_check).
+__device__ inline void note_bad_exc(int* rec, int status, int64_t k) {
+  atomicMax(&rec[0], status);
+  atomicMin(&rec[1], (int)min(k, (int64_t)0x7fffffff));
+}
+// This device's record (device memory), or NULL on a HIP failure.
+int* bad_exc_record();
 hyp_status pair_scratch(Sector* S, size_t n_doubles, double** out);
 hyp_status apply_h_internal(hyp_ham h, hyp_dtype dt, const void* psi, void* sigma, hipStream_t st);
 // true when hyp_pool_gradients takes the transition-value sweep for this list
@@ -303,5 +331,32 @@ int max_rot_chunks();
 size_t tdens_bytes(const Sector* S);
 hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_ops, const void* psi,
                         const void* sig, double* grad, hipStream_t st, bool bins);
+
+// Core Gram blocks of a string space (M orbitals, N electrons; core_gram.hip):
+// the (N-2)-electron cores in colex order, S = C(F, 2) slots each (F = M - N + 2),
+// Gc[core][i][j] = sum_k sigma(slot i, k) psi(slot j, k).  ncore = 0 when the
+// space has no same-spin double.
+struct CoreSpace {
+  int F = 0, S = 0, ntile = 0;
+  int64_t ncore = 0;
+};
+CoreSpace core_space(int M, int N);
+size_t core_gram_doubles(int M, int N);
+struct CoreGramCall {
+  const char* name;           // profiler name of the launch
+  int M, N;                   // the string space whose pairs the blocks cover
+  const RankTables* rank_host;
+  bool f64;                   // storage type of psi and sigma
+  const void* psi;
+  const void* sig;
+  int64_t rs, cs;             // storage element (string r, column k) at [r * rs + k * cs]
+  int nrow, K;                // strings of the space, columns (the other spin's strings)
+  const int* klist;           // support skipping (else null): psi's nonzero columns,
+  const int* kcount;          //   their number (device),
+  const uint32_t* rflag;      //   psi's nonzero rows (flags per string)
+  double* work;               // 2 * nrow * (K rounded up to even) doubles
+  double* G;                  // core_gram_doubles(M, N) doubles
+};
+hyp_status launch_core_gram(const CoreGramCall& g, hipStream_t st);
 
 }  // namespace hyp

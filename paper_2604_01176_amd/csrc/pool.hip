@@ -124,10 +124,18 @@ __global__ void __launch_bounds__(kPairThreads) k_pool_grad(SectorDev S, const h
                                                            const T* psi, const T* sig,
                                                            const uint32_t* __restrict__ nzb,
                                                            const uint32_t* __restrict__ nza,
-                                                           double* part) {
+                                                           double* part, int* bad_rec) {
   __shared__ uint32_t lst[kListMax];
   __shared__ double red[kPairThreads / 64];
   const int k = blockIdx.x, chunk = blockIdx.y;
+  const int bad = exc_status(ops[k], S.M);
+  if (bad != HYP_OK) {  // an invalid excitation: its gradient is NaN, nothing is indexed
+    if (threadIdx.x == 0) {
+      part[(int64_t)k * kPairChunks + chunk] = __builtin_nan("");
+      if (chunk == 0) note_bad_exc(bad_rec, bad, k);
+    }
+    return;
+  }
   const PairCtx c = make_ctx(ops[k], S);
   build_alpha_list(c, S, lst);
   __syncthreads();
@@ -362,6 +370,22 @@ hyp_status validate_exc(const Sector* S, hyp_exc op) {
   return HYP_OK;
 }
 
+// [0] the largest status met, [1] the smallest list position with it
+// (positions of one call; cleared by hyp_pool_check)
+__device__ int g_bad_exc[2] = {0, 0x7fffffff};
+
+int* bad_exc_record() {
+  static int* rec[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (!rec[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_bad_exc)) != hipSuccess) return nullptr;
+    rec[dev] = (int*)p;
+  }
+  return rec[dev];
+}
+
 // grow-only per-sector scratch for chunk partials
 hyp_status pair_scratch(Sector* S, size_t n_doubles, double** out);
 
@@ -376,9 +400,11 @@ static hyp_status launch_pool_grad(Sector* S, const hyp_exc* ops, int64_t n_ops,
     r = support_flags(S, sizeof(T) == 4 ? HYP_F32 : HYP_F64, psi, &nz, st);
     if (r != HYP_OK) return r;
   }
-  // grid.x is limited to 2^31-1, n_ops <= 40k here
+  int* rec = bad_exc_record();
+  if (!rec) return fail(HYP_ERR_HIP, "excitation check record not found");
+  // grid.x is limited to 2^31-1, n_ops <= 2^24 here
   HYP_LAUNCH("k_pool_grad", k_pool_grad<T>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0, st,
-             S->dev(), ops, (const T*)psi, (const T*)sig, nz, nz ? nz + S->db : nullptr, part);
+             S->dev(), ops, (const T*)psi, (const T*)sig, nz, nz ? nz + S->db : nullptr, part, rec);
   HYP_LAUNCH("k_sum_chunks", k_sum_chunks, dim3((unsigned)((n_ops + 255) / 256)), dim3(256), 0, st, part,
              n_ops, 2.0, grad);
   HYP_HIP(hipGetLastError());
@@ -502,15 +528,25 @@ hyp_status hyp_pool_gradients(hyp_sector sh, hyp_dtype dtype, const hyp_exc* ops
   if (dtype != HYP_F64 && dtype != HYP_F32) return fail(HYP_ERR_ARG, "hyp_pool_gradients: bad dtype");
   if (n_ops < 0 || n_ops > (int64_t)1 << 24) return fail(HYP_ERR_ARG, "hyp_pool_gradients: n_ops out of range");
   if (n_ops == 0) return HYP_OK;
+  // the list is in device memory: every kernel that reads an excitation
+  // checks it there (an invalid one gets a NaN gradient and is recorded for
+  // hyp_pool_check), so nothing here waits for the device
+  return launch_pool_gradients(S, dtype, ops, n_ops, psi, sigma, grad, (hipStream_t)stream);
+}
+
+hyp_status hyp_pool_check(void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  std::vector<hyp_exc> h((size_t)n_ops);
-  HYP_HIP(hipMemcpyAsync(h.data(), ops, (size_t)n_ops * sizeof(hyp_exc), hipMemcpyDeviceToHost, st));
+  int* rec = bad_exc_record();
+  if (!rec) return fail(HYP_ERR_HIP, "hyp_pool_check: record not found");
+  int h[2] = {0, 0x7fffffff};
+  HYP_HIP(hipMemcpyAsync(h, rec, sizeof(h), hipMemcpyDeviceToHost, st));
   HYP_HIP(hipStreamSynchronize(st));
-  for (int64_t k = 0; k < n_ops; ++k) {
-    hyp_status r = validate_exc(S, h[(size_t)k]);
-    if (r != HYP_OK) return r;
-  }
-  return launch_pool_gradients(S, dtype, ops, n_ops, psi, sigma, grad, st);
+  if (h[0] == HYP_OK) return HYP_OK;
+  const int clear[2] = {0, 0x7fffffff};
+  HYP_HIP(hipMemcpy(rec, clear, sizeof(clear), hipMemcpyHostToDevice));
+  const std::string what = h[0] == HYP_ERR_SECTOR ? "changes N_alpha / N_beta"
+                                                  : "is not a valid excitation (mask bits, counts or overlap)";
+  return fail((hyp_status)h[0], "hyp_pool_gradients: excitation " + std::to_string(h[1]) + " " + what);
 }
 
 hyp_status hyp_apply_excitation(hyp_sector sh, hyp_dtype dtype, hyp_exc op, double theta,

@@ -1,9 +1,10 @@
 // Full pool-gradient sweep through transition values.
 //
-// Same-spin doubles use the Gram matrices of the two states instead:
+// Same-spin doubles use Gram entries of the two states instead:
 //   G_a[I][J] = sum_beta sigma[beta][I] psi[beta][J]   (alpha strings I, J)
 //   G_b[I][J] = sum_alpha sigma[I][alpha] psi[J][alpha] (beta strings)
-// (two plain FP64 GEMMs on the matrix cores, rocBLAS), then
+// computed only for string pairs one same-spin double apart, grouped by their
+// shared core (core_gram.hip), then
 // T(tau) = sum over the generator's string pairs of s G[I][J].
 //
 // For an excitation tau (ordered: creates i, annihilates e, per spin)
@@ -19,11 +20,8 @@
 // adds s sigma[I] psi[J] to the LDS bin of its ordered alpha excitation.
 // Each workgroup writes its bins for every stage to a partial buffer (no
 // atomics outside LDS); a second pass sums the partials of each transition
-// value in a fixed order, and a third forms the gradients.  Same-spin doubles
-// keep the per-generator pair kernel.
+// value in a fixed order, and a third forms the gradients.
 #include "hyp_internal.h"
-
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <type_traits>
@@ -763,11 +761,17 @@ __device__ inline int ord_bin(uint32_t cre, uint32_t ann) {  // one-spin single:
 // grad[k] for singles and alpha-beta doubles from the transition values;
 // same-spin doubles were written by k_gram_grad.
 __global__ void k_tdens_grad(const hyp_exc* ops, int64_t n, int M, const double* Ta, const double* Tb,
-                             const double* Tab, double* grad) {
+                             const double* Tab, double* grad, int* bad_rec) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const uint32_t m = (1u << M) - 1u;
   const hyp_exc op = ops[k];
+  const int bad = exc_status(op, M);
+  if (bad != HYP_OK) {  // an invalid excitation: NaN, nothing indexed
+    grad[k] = __builtin_nan("");
+    note_bad_exc(bad_rec, bad, k);
+    return;
+  }
   const uint32_t ca = op.cre & m, aa = op.ann & m, cb = (op.cre >> M) & m, ab = (op.ann >> M) & m;
   const int na_ = __popc(ca), nb_ = __popc(cb);
   double g;
@@ -826,16 +830,36 @@ __device__ inline int gram_sign(uint32_t cm, uint32_t am, uint32_t s) {
   return odd & 1;
 }
 
+// Colex rank of a core (a k-subset) and the slot of a 2-orbital mask among
+// the pairs of the orbitals outside it (comp): w (w - 1) / 2 + u for the
+// mask's orbitals at positions u < w of comp, as the core Gram blocks are
+// laid out.
+__device__ inline int core_rank(uint32_t K) {
+  int r = 0, j = 0;
+  while (K) {
+    const int o = __ffs(K) - 1;
+    K &= K - 1;
+    r += c_binom_s[o][++j];
+  }
+  return r;
+}
+__device__ inline int core_slot(uint32_t comp, uint32_t m2) {
+  const int p = __ffs(m2) - 1, q = 31 - __clz(m2);
+  const int u = __popc(comp & ((1u << p) - 1u)), w = __popc(comp & ((1u << q) - 1u));
+  return w * (w - 1) / 2 + u;
+}
+
 // One workgroup per generator: same-spin doubles get
-// g = 2 sum_{J} s (G[tau J][J] - G[J][tau J]) over the generator's strings J
-// (G column-major: G(I, J) at G[I + J * D]); other generators are skipped.
-__global__ void k_gram_grad(const hyp_exc* ops, int M, int na, int nb, const double* Ga, int64_t da,
-                            const double* Gb, int64_t db, const RankTables* arank, const RankTables* brank,
-                            int fsign, double* grad) {
+// g = 2 sum_J s (Gc[tau J][J] - Gc[J][tau J]) over the generator's strings J,
+// read from the block of the core K = J - {a1, a2} (Gc[K][i][j] = sum over
+// the other spin of sigma(slot i) psi(slot j)); other generators are skipped.
+__global__ void k_gram_grad(const hyp_exc* ops, int M, int na, int nb, const double* Ga, int Sa, const double* Gb,
+                            int Sb, int fsign, double* grad) {
   __shared__ double red[4];
   const int64_t k = blockIdx.x;
   const uint32_t m = (1u << M) - 1u;
   const hyp_exc op = ops[k];
+  if (exc_status(op, M) != HYP_OK) return;  // k_tdens_grad writes NaN
   const int ca = __popc(op.cre & m), cb = __popc((op.cre >> M) & m);
   const bool alpha = ca == 2 && cb == 0, beta = ca == 0 && cb == 2;
   if (!alpha && !beta) return;
@@ -843,17 +867,17 @@ __global__ void k_gram_grad(const hyp_exc* ops, int M, int na, int nb, const dou
   const uint32_t am = alpha ? (op.ann & m) : ((op.ann >> M) & m);
   const int N = alpha ? na : nb;
   const double* G = alpha ? Ga : Gb;
-  const int64_t D = alpha ? da : db;
-  const RankTables* R = alpha ? arank : brank;
+  const int64_t S = alpha ? Sa : Sb;
   const int nfree = M - 4, nsel = N - 2;
   const int cnt = (nsel < 0 || nsel > nfree) ? 0 : c_binom_s[nfree][nsel];
   double acc = 0.0;
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
     const uint32_t J = gram_string(cm, am, M, N, i);
-    const uint32_t I = J ^ cm ^ am;
-    const int64_t rj = R->lo[J & 255u] + R->hi[(J >> 8) & 255u];
-    const int64_t ri = R->lo[I & 255u] + R->hi[(I >> 8) & 255u];
-    const double v = G[ri + rj * D] - G[rj + ri * D];
+    const uint32_t core = J & ~am;
+    const uint32_t comp = m & ~core;
+    const double* Gk = G + (int64_t)core_rank(core) * S * S;
+    const int64_t sI = core_slot(comp, cm), sJ = core_slot(comp, am);
+    const double v = Gk[sI * S + sJ] - Gk[sJ * S + sI];
     acc += (gram_sign(cm, am, J) & fsign) ? -v : v;
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
@@ -945,38 +969,6 @@ __global__ void __launch_bounds__(256) k_rows_compact(const int2* __restrict__ r
   if (lane == 0) rcount[eb] = n;
 }
 
-// dst[i][c] = src[list[i]][c] (whole rows, widened to FP64)
-template <typename T>
-__global__ void k_gather_rows(const T* __restrict__ src, const int* __restrict__ list, int n, int cols,
-                              double* __restrict__ dst) {
-  const int64_t tot = (int64_t)n * cols;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / cols, c = i - r * cols;
-    dst[i] = (double)src[(int64_t)list[r] * cols + c];
-  }
-}
-
-// dst[r][j] = src[r][list[j]] (selected columns of every row, widened)
-template <typename T>
-__global__ void k_gather_cols(const T* __restrict__ src, const int* __restrict__ list, int n, int rows, int cols,
-                              double* __restrict__ dst) {
-  const int64_t tot = (int64_t)rows * n;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / n, j = i - r * n;
-    dst[i] = (double)src[r * cols + list[j]];
-  }
-}
-
-__global__ void k_zero_f64(double* p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0;
-}
-
-__global__ void k_widen(const float* a, int64_t n, double* b) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    b[i] = (double)a[i];
-}
-
 namespace {
 struct TScratch {
   double* part = nullptr;
@@ -984,23 +976,21 @@ struct TScratch {
   double* T = nullptr;   // Ta | Tb | Tab
   double* red = nullptr; // second-level partials
   bool binom = false;
-  rocblas_handle blas = nullptr;
-  double* gram = nullptr;  // G_a | G_b | widened psi | widened sigma
+  double* gram = nullptr;  // core Gram blocks (alpha | beta) | dense FP64 operand rows
   size_t gram_cap = 0;
   int2* rows = nullptr;    // beta excitation row pairs of the row-batched kernel
   int rows_M = -1, rows_nb = -1, rows_fsign = -1;
   size_t rows_cap = 0;
   double* rpart = nullptr; // partials of the row-batched kernel
   size_t rpart_cap = 0;
-  hipEvent_t cnt_ready = nullptr;
   // support skipping: flags and ordered lists of psi's nonzero beta rows
-  // and alpha columns, their two lengths (device and pinned host), and the
-  // kept row pairs of each beta excitation
+  // and alpha columns, their two lengths (device memory: every decision
+  // that depends on them is taken on the device), and the kept row pairs of
+  // each beta excitation
   uint32_t* nz = nullptr;
   int* lists = nullptr;
   size_t nz_cap = 0;
   int* cnt = nullptr;
-  int* hcnt = nullptr;
   int2* crows = nullptr;
   int* rcount = nullptr;
   size_t crows_cap = 0;
@@ -1242,8 +1232,6 @@ hyp_status support_flags(Sector* S, hyp_dtype dt, const void* psi, const uint32_
   }
   if (!ts.cnt) {
     HYP_HIP(hipMalloc(&ts.cnt, 2 * sizeof(int)));
-    HYP_HIP(hipHostMalloc((void**)&ts.hcnt, 2 * sizeof(int), hipHostMallocDefault));
-    HYP_HIP(hipEventCreateWithFlags(&ts.cnt_ready, hipEventDisableTiming));
   }
   HYP_LAUNCH("k_zero_u32", k_zero_u32, dim3((unsigned)std::min<int64_t>(1024, (da + db + 255) / 256)), dim3(256), 0,
              st, ts.nz, (int)(da + db));
@@ -1294,8 +1282,6 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
     if (rs != HYP_OK) return rs;
     HYP_LAUNCH("k_list_nz", k_list_nz, dim3(1), dim3(1024), 0, st, ts.nz, (int)db, ts.lists, ts.cnt);
     HYP_LAUNCH("k_list_nz", k_list_nz, dim3(1), dim3(1024), 0, st, ts.nz + db, (int)da, ts.lists + db, ts.cnt + 1);
-    HYP_HIP(hipMemcpyAsync(ts.hcnt, ts.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HYP_HIP(hipEventRecord(ts.cnt_ready, st));
   }
   if (!bins) {
     hyp_status r = tdens_rows(S, dt, ts, psi, sig, Ta, Tb, Tab, skip, st);
@@ -1344,8 +1330,11 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
   HYP_LAUNCH("k_tdens_final", k_tdens_final, dim3((kBins * kStageW + kBins + 255) / 256), dim3(256), 0, st,
              red_ab, red_a, Ta, Tb, Tab);
   }
-  // same-spin doubles: Gram matrices on the matrix cores, then the gather
-  const size_t gneed = (size_t)(da * da + db * db) + ((dt == HYP_F32 || skip) ? 2 * (size_t)S->dim : 0);
+  // same-spin doubles: per-core Gram blocks of both string spaces (only the
+  // string pairs one same-spin double apart), then the gather
+  const size_t na_g = core_gram_doubles(S->M, S->na), nb_g = core_gram_doubles(S->M, S->nb);
+  const size_t wneed = 2 * (size_t)std::max(da * ((db + 1) & ~(int64_t)1), db * ((da + 1) & ~(int64_t)1));
+  const size_t gneed = na_g + nb_g + ((na_g + nb_g) > 0 ? wneed : 0);
   if (gneed > ts.gram_cap) {
     HYP_HIP(hipDeviceSynchronize());
     if (ts.gram) HYP_HIP(hipFree(ts.gram));
@@ -1354,126 +1343,30 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
     HYP_HIP(hipMalloc(&ts.gram, gneed * sizeof(double)));
     ts.gram_cap = gneed;
   }
-  if (!ts.blas && rocblas_create_handle(&ts.blas) != rocblas_status_success)
-    return fail(HYP_ERR_HIP, "rocblas_create_handle failed");
   double* Ga = ts.gram;
-  double* Gb = Ga + da * da;
-  double* work = Gb + db * db;  // 2 dim doubles: widened or gathered operands
-  // support sizes (the host waits for the support scan only, not for the
-  // transition-value kernel queued after it); a Gram sum over at most half
-  // of its range takes gathered operands
-  int64_t nR = db, nC = da;
-  if (skip) {
-    HYP_HIP(hipEventSynchronize(ts.cnt_ready));
-    nR = ts.hcnt[0];
-    nC = ts.hcnt[1];
+  double* Gb = Ga + na_g;
+  double* work = Gb + nb_g;
+  if (na_g > 0) {
+    // alpha strings as rows, beta rows as columns: element (alpha I, beta k)
+    // of the [beta][alpha] state at I + k * D_a
+    CoreGramCall g{"k_core_gram_a", S->M, S->na, &S->h_arank, dt == HYP_F64, psi, sig, 1, da, (int)da, (int)db,
+                   skip ? ts.lists : nullptr, skip ? ts.cnt : nullptr, skip ? ts.nz + db : nullptr, work, Ga};
+    hyp_status r = launch_core_gram(g, st);
+    if (r != HYP_OK) return r;
   }
-  const bool gat_a = skip && 2 * nR <= db, gat_b = skip && 2 * nC <= da;
-  bool widened = false;
-  auto dense_ops = [&](const double** X, const double** Y) -> hyp_status {
-    if (dt == HYP_F64) {
-      *X = (const double*)psi;
-      *Y = (const double*)sig;
-      return HYP_OK;
-    }
-    if (!widened) {
-      HYP_LAUNCH("k_widen", k_widen, dim3(4096), dim3(256), 0, st, (const float*)psi, S->dim, work);
-      HYP_LAUNCH("k_widen", k_widen, dim3(4096), dim3(256), 0, st, (const float*)sig, S->dim, work + S->dim);
-      widened = true;
-    }
-    *X = work;
-    *Y = work + S->dim;
-    return HYP_OK;
-  };
-  if (rocblas_set_stream(ts.blas, st) != rocblas_status_success)
-    return fail(HYP_ERR_HIP, "rocblas_set_stream failed");
-  const double one = 1.0, zero = 0.0;
-  // column-major view: sigma, psi are D_a x D_b with leading dimension D_a
-  // G_a = Y X^T (D_a x D_a, sum over beta rows), G_b = Y^T X (D_b x D_b, sum
-  // over alpha columns)
-  rocblas_status bs = rocblas_status_success;
-  {
-    const double *X, *Y;
-    int64_t K = db;
-    if (gat_a) {
-      // the support's beta rows of psi and sigma, gathered (and widened)
-      widened = false;
-      double* xr = work;
-      double* yr = work + nR * da;
-      const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (nR * da + 255) / 256));
-      if (nR > 0) {
-        if (dt == HYP_F64) {
-          HYP_LAUNCH("k_gather_rows", k_gather_rows<double>, dim3(g), dim3(256), 0, st, (const double*)psi,
-                     ts.lists, (int)nR, (int)da, xr);
-          HYP_LAUNCH("k_gather_rows", k_gather_rows<double>, dim3(g), dim3(256), 0, st, (const double*)sig,
-                     ts.lists, (int)nR, (int)da, yr);
-        } else {
-          HYP_LAUNCH("k_gather_rows", k_gather_rows<float>, dim3(g), dim3(256), 0, st, (const float*)psi, ts.lists,
-                     (int)nR, (int)da, xr);
-          HYP_LAUNCH("k_gather_rows", k_gather_rows<float>, dim3(g), dim3(256), 0, st, (const float*)sig, ts.lists,
-                     (int)nR, (int)da, yr);
-        }
-      }
-      X = xr;
-      Y = yr;
-      K = nR;
-    } else {
-      hyp_status r = dense_ops(&X, &Y);
-      if (r != HYP_OK) return r;
-    }
-    ProfScope ps_("rocblas_dgemm_gram_a", st);
-    if (K == 0)
-      HYP_LAUNCH("k_zero_f64", k_zero_f64, dim3(4096), dim3(256), 0, st, Ga, da * da);
-    else
-      bs = rocblas_dgemm(ts.blas, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)da,
-                         (rocblas_int)da, (rocblas_int)K, &one, Y, (rocblas_int)da, X, (rocblas_int)da, &zero, Ga,
-                         (rocblas_int)da);
+  if (nb_g > 0) {
+    CoreGramCall g{"k_core_gram_b", S->M, S->nb, &S->h_brank, dt == HYP_F64, psi, sig, da, 1, (int)db, (int)da,
+                   skip ? ts.lists + db : nullptr, skip ? ts.cnt + 1 : nullptr, skip ? ts.nz : nullptr, work, Gb};
+    hyp_status r = launch_core_gram(g, st);
+    if (r != HYP_OK) return r;
   }
-  if (bs != rocblas_status_success) return fail(HYP_ERR_HIP, "rocblas_dgemm (alpha Gram) failed");
-  {
-    const double *X, *Y;
-    int64_t K = da, ld = da;
-    if (gat_b) {
-      // the support's alpha columns of every row, gathered (and widened):
-      // column-major nC x D_b
-      widened = false;
-      double* xc = work;
-      double* yc = work + nC * db;
-      const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (nC * db + 255) / 256));
-      if (nC > 0) {
-        if (dt == HYP_F64) {
-          HYP_LAUNCH("k_gather_cols", k_gather_cols<double>, dim3(g), dim3(256), 0, st, (const double*)psi,
-                     ts.lists + db, (int)nC, (int)db, (int)da, xc);
-          HYP_LAUNCH("k_gather_cols", k_gather_cols<double>, dim3(g), dim3(256), 0, st, (const double*)sig,
-                     ts.lists + db, (int)nC, (int)db, (int)da, yc);
-        } else {
-          HYP_LAUNCH("k_gather_cols", k_gather_cols<float>, dim3(g), dim3(256), 0, st, (const float*)psi,
-                     ts.lists + db, (int)nC, (int)db, (int)da, xc);
-          HYP_LAUNCH("k_gather_cols", k_gather_cols<float>, dim3(g), dim3(256), 0, st, (const float*)sig,
-                     ts.lists + db, (int)nC, (int)db, (int)da, yc);
-        }
-      }
-      X = xc;
-      Y = yc;
-      K = nC;
-      ld = std::max<int64_t>(1, nC);
-    } else {
-      hyp_status r = dense_ops(&X, &Y);
-      if (r != HYP_OK) return r;
-    }
-    ProfScope ps_("rocblas_dgemm_gram_b", st);
-    if (K == 0)
-      HYP_LAUNCH("k_zero_f64", k_zero_f64, dim3(4096), dim3(256), 0, st, Gb, db * db);
-    else
-      bs = rocblas_dgemm(ts.blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)db,
-                         (rocblas_int)db, (rocblas_int)K, &one, Y, (rocblas_int)ld, X, (rocblas_int)ld, &zero, Gb,
-                         (rocblas_int)db);
-  }
-  if (bs != rocblas_status_success) return fail(HYP_ERR_HIP, "rocblas_dgemm (beta Gram) failed");
-  HYP_LAUNCH("k_gram_grad", k_gram_grad, dim3((unsigned)n_ops), dim3(256), 0, st, ops, S->M, S->na, S->nb, Ga, da,
-             Gb, db, S->d_arank, S->d_brank, pool_kind() == 0 ? 1 : 0, grad);
+  const CoreSpace csa = core_space(S->M, S->na), csb = core_space(S->M, S->nb);
+  HYP_LAUNCH("k_gram_grad", k_gram_grad, dim3((unsigned)n_ops), dim3(256), 0, st, ops, S->M, S->na, S->nb, Ga,
+             csa.S, Gb, csb.S, pool_kind() == 0 ? 1 : 0, grad);
+  int* rec = bad_exc_record();
+  if (!rec) return fail(HYP_ERR_HIP, "excitation check record not found");
   HYP_LAUNCH("k_tdens_grad", k_tdens_grad, dim3((unsigned)((n_ops + 255) / 256)), dim3(256), 0, st, ops, n_ops,
-             S->M, Ta, Tb, Tab, grad);
+             S->M, Ta, Tb, Tab, grad, rec);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
 }

@@ -12,6 +12,15 @@ times.
   edges of the column chunks.
 * The full pool-gradient sweep in all three strategies against each other
   and, on a sample of generators, against the oracle.
+* With support skipping off (every kernel evaluates the whole sector, the
+  dense path the benchmark times): sigma over all 165,636,900 entries (FP64
+  and FP32) and all 39,960 gradients of the default sweep (compact staging,
+  per-core Gram blocks over the full contraction range) on the sparse input,
+  against the oracle's pair sum restricted to the input's nonzeros (exact:
+  every other pair contributes 0).
+* Dense operands: the sweep of a dense random psi with an independent dense
+  random sigma (the gradient is defined for any pair of vectors), 64
+  generators of every class against the oracle's full pair sum.
 """
 import numpy as np
 import pytest
@@ -53,6 +62,13 @@ def _full(S, idx, val):
     v = np.zeros(S.dim)
     v[idx] = val
     return v
+
+
+@pytest.fixture
+def skip_off(hyp):
+    hyp.set_support_skip(False)
+    yield
+    hyp.set_support_skip(True)
 
 
 def test_hpsi_32q_sparse_input_every_entry(hyp, prob):
@@ -138,3 +154,53 @@ def test_rotation_32q_every_entry(hyp, prob, cls_pick):
     ref = oracle.rotate(W.n_orb, W.n_alpha, W.n_beta, int(cre[k]), int(ann[k]), 0.37, _full(S, prob["idx"], prob["val"]))
     assert np.abs(got - ref).max() <= 1e-13
     assert np.count_nonzero(ref) > np.size(prob["idx"])  # the rotation moved weight
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_hpsi_32q_skip_off_every_entry(hyp, prob, skip_off, dtype):
+    S, H = prob["S"], prob["H"]
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    psi = _sparse_dev(S, prob["idx"], prob["val"], tdt)
+    print(f"[full-size] H psi {dtype}, support skipping off", flush=True)
+    sig = H.apply(psi).cpu().numpy().astype(np.float64)
+    ref = prob["sig_ref"]
+    tol = 1e-12 if dtype == "f64" else 2e-6
+    assert np.linalg.norm(sig - ref) <= tol * np.linalg.norm(ref)
+    if dtype == "f64":
+        assert np.abs(sig - ref).max() <= 1e-12 * np.abs(ref).max()
+        assert np.count_nonzero(sig[ref == 0.0]) == 0
+
+
+def test_sweep_32q_skip_off_every_gradient(hyp, prob, skip_off):
+    S = prob["S"]
+    cre, ann, _ = synth.canonical_pool(W.n_orb)
+    ops = hyp.exc_tensor(cre, ann)
+    psi = _sparse_dev(S, prob["idx"], prob["val"])
+    sig = torch.from_numpy(prob["sig_ref"]).cuda()  # the oracle's sigma as the input
+    print("[full-size] sweep, support skipping off", flush=True)
+    g = hyp.hyp_pool_gradients(S, ops, psi, sig).cpu().numpy()
+    ref = oracle.pool_gradients_sparse(W.n_orb, W.n_alpha, W.n_beta, cre, ann, prob["idx"],
+                                       _full(S, prob["idx"], prob["val"]), prob["sig_ref"])
+    assert np.count_nonzero(ref) > 1000
+    assert np.abs(g - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_sweep_32q_dense_operands_oracle_sample(hyp, prob):
+    S = prob["S"]
+    cre, ann, cls = synth.canonical_pool(W.n_orb)
+    ops = hyp.exc_tensor(cre, ann)
+    psi_h = synth.random_state(S.dim, 7)
+    sig_h = synth.random_state(S.dim, 8)
+    print("[full-size] sweep on dense random psi and sigma", flush=True)
+    g = hyp.hyp_pool_gradients(S, ops, torch.from_numpy(psi_h).cuda(), torch.from_numpy(sig_h).cuda())
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(5)
+    pick = list(np.argsort(-np.abs(g), kind="stable")[:4])
+    for k in range(5):
+        members = np.nonzero(cls == k)[0]
+        pick += [int(members[0]), int(members[-1])] + rng.choice(members, 14, replace=False).tolist()
+    pick = np.array(sorted(set(int(p) for p in pick)))
+    assert pick.size >= 64
+    print(f"[full-size] oracle on {pick.size} generators", flush=True)
+    ref = oracle.pool_gradients(W.n_orb, W.n_alpha, W.n_beta, cre[pick], ann[pick], psi_h, sig_h)
+    assert np.abs(g[pick] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
