@@ -218,6 +218,24 @@ hyp_status hyp_pool_gradients(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_
                               int64_t n_ops, const void* psi_dev, const void* sigma_dev,
                               double* grad_dev, void* stream);
 
+/* hyp_pool_gradients for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the per-generator pair kernel (the strategy of candidate
+ * subsets, hyp_set_sweep_mode 1) with its per-chunk partials in a static
+ * per-GPU array of the library (32,768 generators x 16 chunks of doubles,
+ * 4 MiB, held by every GPU the library runs on until the process ends).
+ * No call allocates or frees device memory.  The first call on a device
+ * takes the array's address there and uploads the binomial table (a
+ * synchronous copy; later calls are asynchronous).  No support skipping:
+ * every pair is evaluated.  Same arguments, output and device-side
+ * excitation checks as hyp_pool_gradients; HYP_ERR_ARG also when n_ops
+ * exceeds 32,768 (nothing enqueued).  Every call on one GPU shares the
+ * array: calls that overlap on one GPU (several streams, or several host
+ * threads) race; calls ordered on one stream do not. */
+hyp_status hyp_pool_gradients_noalloc(hyp_sector s, hyp_dtype dtype, const hyp_exc* ops_dev,
+                                      int64_t n_ops, const void* psi_dev, const void* sigma_dev,
+                                      double* grad_dev, void* stream);
+
 /* Waits for `stream`, then reports the first invalid excitation that
  * hyp_pool_gradients met on this device since the last report: HYP_ERR_ARG
  * or HYP_ERR_SECTOR (the largest status met), its list position in

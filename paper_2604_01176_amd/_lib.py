@@ -75,6 +75,7 @@ SIGNATURES = {
     "hyp_expectation": (_ci, [_vp, _ci, _vp, _vp, _vp, _vp]),
     "hyp_pool_gradients": (_ci, [_vp, _ci, _vp, _i64, _vp, _vp, _vp, _vp]),
     "hyp_pool_check": (_ci, [_vp]),
+    "hyp_pool_gradients_noalloc": (_ci, [_vp, _ci, _vp, _i64, _vp, _vp, _vp, _vp]),
     "hyp_apply_excitation": (_ci, [_vp, _ci, HypExc, _d, _vp, _vp]),
     "hyp_set_sweep_mode": (_ci, [_ci]),
     "hyp_set_row_staging": (_ci, [_ci]),

@@ -534,6 +534,51 @@ hyp_status hyp_pool_gradients(hyp_sector sh, hyp_dtype dtype, const hyp_exc* ops
   return launch_pool_gradients(S, dtype, ops, n_ops, psi, sigma, grad, (hipStream_t)stream);
 }
 
+// Scratch of hyp_pool_gradients_noalloc: the pair kernel's per-chunk
+// partials, one array per GPU for the life of the process, shared by every
+// call on that GPU (overlapping calls race).  Host code uses only the device
+// address taken with hipGetSymbolAddress, never the array's name.
+constexpr int64_t kNoAllocOps = 32768;
+static __device__ __align__(256) double scratch[kNoAllocOps * kPairChunks];
+static double* g_scratch_ptr[64] = {};
+
+hyp_status hyp_pool_gradients_noalloc(hyp_sector sh, hyp_dtype dtype, const hyp_exc* ops, int64_t n_ops,
+                                      const void* psi, const void* sigma, double* grad, void* stream) {
+  Sector* S = sector_of(sh);
+  if (!S || !ops || !psi || !sigma || !grad) return fail(HYP_ERR_ARG, "hyp_pool_gradients_noalloc: NULL argument");
+  if (dtype != HYP_F64 && dtype != HYP_F32) return fail(HYP_ERR_ARG, "hyp_pool_gradients_noalloc: bad dtype");
+  if (n_ops < 0 || n_ops > kNoAllocOps)
+    return fail(HYP_ERR_ARG, "hyp_pool_gradients_noalloc: n_ops must be in [0, " + std::to_string(kNoAllocOps) +
+                                 "] (the size of its static scratch)");
+  int dev = 0;
+  HYP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(HYP_ERR_HIP, "device index out of range");
+  if (!g_scratch_ptr[dev]) {
+    // set-up, once per device with that device current: the array's
+    // address on this GPU, and the binomial table of the pair kernel
+    void* p = nullptr;
+    HYP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    hyp_status r = ensure_binom();
+    if (r != HYP_OK) return r;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  if (n_ops == 0) return HYP_OK;
+  int* rec = bad_exc_record();
+  if (!rec) return fail(HYP_ERR_HIP, "excitation check record not found");
+  hipStream_t st = (hipStream_t)stream;
+  double* part = g_scratch_ptr[dev];  // every (generator, chunk) partial is written before it is read
+  if (dtype == HYP_F64)
+    HYP_LAUNCH("k_pool_grad", k_pool_grad<double>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0, st,
+               S->dev(), ops, (const double*)psi, (const double*)sigma, nullptr, nullptr, part, rec);
+  else
+    HYP_LAUNCH("k_pool_grad", k_pool_grad<float>, dim3((unsigned)n_ops, kPairChunks), dim3(kPairThreads), 0, st,
+               S->dev(), ops, (const float*)psi, (const float*)sigma, nullptr, nullptr, part, rec);
+  HYP_LAUNCH("k_sum_chunks", k_sum_chunks, dim3((unsigned)((n_ops + 255) / 256)), dim3(256), 0, st, part, n_ops,
+             2.0, grad);
+  HYP_HIP(hipGetLastError());
+  return HYP_OK;
+}
+
 hyp_status hyp_pool_check(void* stream) {
   hipStream_t st = (hipStream_t)stream;
   int* rec = bad_exc_record();
