@@ -173,6 +173,14 @@ hyp_status hyp_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* si
  * is 0 or 1. */
 hyp_status hyp_set_support_skip(int on);
 
+/* Same-spin part of hyp_apply_h with FP64 storage: 1 (default) over grouped
+ * lists, where each wave takes 8 consecutive output strings and loads every
+ * source amplitude their rows share once (the union of their sources, each
+ * with the 8 rows' coefficients); 0 over per-row lists, one output string
+ * per wave.  Equal results up to summation order.  FP32 storage always uses
+ * the per-row lists.  Process-wide; HYP_ERR_ARG unless on is 0 or 1. */
+hyp_status hyp_set_same_spin_groups(int on);
+
 /* Materialised sector Hamiltonian in CSR form, the paper's storage of H
  * ("Sparse State-Vector Emulation", Table 1 gives its size), kept as a
  * comparison for the matrix-free product.  Every row holds the same L
@@ -452,10 +460,16 @@ hyp_status hyp_occupations(hyp_sector s, hyp_dtype dtype, const void* psi_dev, d
                            double* work_dev, void* stream);
 /* Feature rows: static part stat_dev[n][32] (FP32) with slots 11..14 set to
  * <n_q> of the operator's spin-orbitals qidx_dev[n][4] (-1: 0), slot 15 to
- * log10(|g_prev| + 1e-12), slot 16 to min(age, 50) / 10; output BF16. */
+ * log10(|g_prev| + 1e-12), slot 16 to min(age, 50) / 10, and against the
+ * last selected operator (last_qidx: its four qubit indices in the qidx
+ * layout, host array read at the call; all -1 before the first selection):
+ * slot 18 = 1 for that operator itself, 19 = shared spin-orbitals / 4,
+ * 20 = shared spatial orbitals / 4, 21 = log10(|last_g| + 1e-12) (0 with no
+ * selection); output BF16.  HYP_ERR_ARG: NULL, n_orb outside 1..16 or a
+ * last_qidx entry outside -1..2 n_orb - 1. */
 hyp_status hyp_features(const float* stat_dev, const int32_t* qidx_dev, const double* occ_dev,
-                        const double* gprev_dev, const int32_t* age_dev, int64_t n, uint16_t* X_dev,
-                        void* stream);
+                        const double* gprev_dev, const int32_t* age_dev, int64_t n, int n_orb,
+                        const int32_t* last_qidx, double last_g, uint16_t* X_dev, void* stream);
 /* Screen bookkeeping: for every k with g_dev[k] not NaN, gprev[k] = g[k]
  * and age[k] = 0; every other age grows by one. */
 hyp_status hyp_screen_update(const double* g_dev, int64_t n, double* gprev_dev, int32_t* age_dev,

@@ -134,13 +134,27 @@ def static_features(n_orb, cre, ann, cls, h, g):
     return F, Q
 
 
-def features(F_static, Q, occ, gprev, age):
-    """Full feature rows (FP64; the GPU rounds FP32 values to BF16)."""
+def features(F_static, Q, occ, gprev, age, n_orb=None, last=None, last_g=0.0):
+    """Full feature rows (FP64; the GPU rounds FP32 values to BF16).  With
+    the last selected operator's four qubit indices `last` (qidx layout):
+    slot 18 marks that operator, 19 and 20 count the spin-orbitals and the
+    spatial orbitals it shares with each operator (/ 4), 21 is
+    log10(|last_g| + 1e-12); all four are 0 when there is no selection."""
     X = np.array(F_static, dtype=np.float64)
     for i in range(4):
         X[:, 11 + i] = np.where(Q[:, i] >= 0, occ[np.maximum(Q[:, i], 0)], 0.0)
     X[:, 15] = np.log10(np.abs(gprev) + 1e-12)
     X[:, 16] = np.minimum(age, 50) / 10.0
+    if last is not None and any(int(q) >= 0 for q in last):
+        M = int(n_orb)
+        lq = set(int(q) for q in last if int(q) >= 0)
+        ls = set(q % M for q in lq)
+        for k in range(X.shape[0]):
+            kq = set(int(q) for q in Q[k] if int(q) >= 0)
+            X[k, 18] = 1.0 if [int(q) for q in Q[k]] == [int(q) for q in last] else 0.0
+            X[k, 19] = len(kq & lq) / 4.0
+            X[k, 20] = len(set(q % M for q in kq) & ls) / 4.0
+            X[k, 21] = math.log10(abs(last_g) + 1e-12)
     return X
 
 

@@ -80,6 +80,7 @@ SIGNATURES = {
     "hyp_set_sweep_mode": (_ci, [_ci]),
     "hyp_set_row_staging": (_ci, [_ci]),
     "hyp_set_support_skip": (_ci, [_ci]),
+    "hyp_set_same_spin_groups": (_ci, [_ci]),
     "hyp_set_pool_kind": (_ci, [_ci]),
     "hyp_apply_excitations": (_ci, [_vp, _ci, _vp, _vp, _i64, _vp, _vp]),
     "hyp_csr_build": (_ci, [_vp, _vp, ctypes.POINTER(_vp)]),
@@ -99,7 +100,7 @@ SIGNATURES = {
     "hyp_mlp_set_state": (_ci, [_vp, _vp]),
     "hyp_screen_static": (_ci, [_ci, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "hyp_occupations": (_ci, [_vp, _ci, _vp, _vp, _vp, _vp]),
-    "hyp_features": (_ci, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "hyp_features": (_ci, [_vp, _vp, _vp, _vp, _vp, _i64, _ci, _vp, _d, _vp, _vp]),
     "hyp_screen_update": (_ci, [_vp, _i64, _vp, _vp, _vp]),
     "hyp_screen_base": (_ci, [_vp, _i64, ctypes.c_float, _vp, _vp]),
     "hyp_screen_batch": (_ci, [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp, _vp, _vp]),

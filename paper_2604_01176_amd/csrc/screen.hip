@@ -90,20 +90,46 @@ __global__ void k_occ_final(const double* part, int M, int db, const uint32_t* b
 //   11..14  <n_q> of the operator's spin-orbitals (qidx, -1 -> 0)
 //   15      log10(|g_prev| + 1e-12)
 //   16      min(age, 50) / 10
+struct LastSel {
+  int q[4];      // qubit indices of the last selected operator (-1 padding; all -1: none)
+  float logg;    // log10(|g| + 1e-12) it was selected with
+  int M;         // orbitals
+};
+
 __global__ void k_features(const float* stat, const int* qidx, const double* occ,
-                           const double* gprev, const int* age, int64_t n, uint16_t* X) {
+                           const double* gprev, const int* age, int64_t n, LastSel last, uint16_t* X) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   float f[32];
 #pragma unroll
   for (int i = 0; i < 32; ++i) f[i] = stat[k * 32 + i];
+  uint32_t mk = 0, sk = 0, ml = 0, sl = 0;  // spin-orbital and spatial masks
+  bool same = true, any = false;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int q = qidx[k * 4 + i];
     f[11 + i] = q >= 0 ? (float)occ[q] : 0.0f;
+    if (q >= 0) {
+      mk |= 1u << q;
+      sk |= 1u << (q % last.M);
+    }
+    const int ql = last.q[i];
+    if (ql >= 0) {
+      ml |= 1u << ql;
+      sl |= 1u << (ql % last.M);
+      any = true;
+    }
+    same = same && q == ql;
   }
   f[15] = (float)log10(fabs(gprev[k]) + 1e-12);
   f[16] = (float)min(age[k], 50) / 10.0f;
+  // the operator against the last selected one: the same operator, the
+  // spin-orbitals and the spatial orbitals the two share, the size of the
+  // last selection's gradient (0 before the first selection)
+  f[18] = (any && same) ? 1.0f : 0.0f;
+  f[19] = (float)__popc(mk & ml) / 4.0f;
+  f[20] = (float)__popc(sk & sl) / 4.0f;
+  f[21] = any ? last.logg : 0.0f;
 #pragma unroll
   for (int i = 0; i < 32; ++i) X[k * 32 + i] = f2bf(f[i]);
 }
@@ -577,13 +603,21 @@ hyp_status hyp_occupations(hyp_sector sh, hyp_dtype dt, const void* psi, double*
 }
 
 hyp_status hyp_features(const float* stat_dev, const int32_t* qidx_dev, const double* occ_dev,
-                        const double* gprev_dev, const int32_t* age_dev, int64_t n, uint16_t* X_dev,
-                        void* stream) {
-  if (!stat_dev || !qidx_dev || !occ_dev || !gprev_dev || !age_dev || !X_dev || n < 0)
+                        const double* gprev_dev, const int32_t* age_dev, int64_t n, int n_orb,
+                        const int32_t* last_qidx, double last_g, uint16_t* X_dev, void* stream) {
+  if (!stat_dev || !qidx_dev || !occ_dev || !gprev_dev || !age_dev || !X_dev || !last_qidx || n < 0)
     return fail(HYP_ERR_ARG, "hyp_features: NULL argument");
+  if (n_orb < 1 || n_orb > kMaxOrb) return fail(HYP_ERR_ARG, "hyp_features: n_orb out of range");
+  LastSel last;
+  for (int i = 0; i < 4; ++i) {
+    if (last_qidx[i] < -1 || last_qidx[i] >= 2 * n_orb) return fail(HYP_ERR_ARG, "hyp_features: bad last_qidx");
+    last.q[i] = last_qidx[i];
+  }
+  last.logg = (float)std::log10(std::fabs(last_g) + 1e-12);
+  last.M = n_orb;
   if (n == 0) return HYP_OK;
   HYP_LAUNCH("k_features", k_features, dim3(g1(n)), dim3(256), 0, (hipStream_t)stream, stat_dev, qidx_dev,
-             occ_dev, gprev_dev, age_dev, n, X_dev);
+             occ_dev, gprev_dev, age_dev, n, last, X_dev);
   HYP_HIP(hipGetLastError());
   return HYP_OK;
 }

@@ -94,6 +94,20 @@ def test_occupations_and_features(hyp, scr):
     diff = np.abs(got - ref)
     assert np.all(diff <= np.abs(ref) * 2 ** -7 + 1e-30)
     assert np.mean(diff == 0) > 0.999
+    assert np.all(got[:, 18:22] == 0.0)  # no selection yet
+    # after a selection (an alpha-beta double): the last-selection slots, and
+    # the selected operator's known gradient (0) with age 0
+    k_sel = int(np.nonzero(cls == 4)[0][37])
+    fs.note_selected(k_sel, 0.0123)
+    X = fs.features(torch.from_numpy(psi).cuda()).cpu().numpy()
+    gp[k_sel], age[k_sel] = 0.0, 0
+    ref = om.bf16(om.features(F, Q, occ_ref, gp, age, n_orb=M, last=Q[k_sel], last_g=0.0123))
+    got = (X.view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    diff = np.abs(got - ref)
+    assert np.all(diff <= np.abs(ref) * 2 ** -7 + 1e-30)
+    assert np.mean(diff == 0) > 0.999
+    assert got[k_sel, 18] == 1.0 and np.count_nonzero(got[:, 18]) == 1
+    assert np.count_nonzero(got[:, 19]) > 100 and got[:, 19].max() == 1.0
 
 
 def test_mlp_state_roundtrip_and_clone(scr):
@@ -193,54 +207,82 @@ def test_training_rows_and_floored_targets(hyp, scr):
 
 
 def test_ablation_recall(hyp, scr, trained):
-    """Held-out problems: where the true argmax |g| ranks under the trained
-    network, under the no-learning heuristic (|g_prev|) and at random."""
+    """Held-out problems (the 16-qubit workload, batch instance 3 and two
+    problems from other seeds): where the true argmax |g| ranks under the
+    trained network (base + network output), under the no-learning
+    heuristic (|g_prev|, the base alone) and at random, over 52 iterations.
+    Both know the last selection's own gradient (zero after the re-optimisation).
+    The network must rank the argmax at most 3/4 as deep on average as the
+    heuristic, with recall@32 and the count of ranks past K + audit no worse;
+    the measured figures are in the design notes."""
     net = trained
     K = 32
     hits = {"mlp": 0, "heuristic": 0, "random": 0}
+    ranks = {"mlp": [], "heuristic": []}
     total = 0
     rng = np.random.default_rng(9)
-    for w in (synth.WORKLOADS["h8_16q"], synth.INSTANCES[3]):
+    held_out = (synth.WORKLOADS["h8_16q"], synth.INSTANCES[3],
+                synth.Workload("heldout_M10", 10, 5, 5, 1042), synth.Workload("heldout_M11", 11, 6, 5, 2042))
+    for w in held_out:
         x, z, c, h, g = synth.hamiltonian(w)
         cre, ann, cls = synth.canonical_pool(w.n_orb)
         S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
         H = hyp.Hamiltonian(S, x, z, c)
-        A = hyp.Adapt(H, cre, ann, max_iter=12)
+        A = hyp.Adapt(H, cre, ann, max_iter=16)
         stat, qidx = scr.static_features(w.n_orb, cre, ann, cls, h, g)
         fs = scr.FeatureState(S, stat, qidx)
         psi = None
-        for it in range(10):
+        for it in range(14):
             psi = A.state(psi)
             X = fs.features(psi)
-            heur = fs.gprev.abs().cpu().numpy()
-            y = net.forward(X).cpu().numpy() + fs.base.cpu().numpy()
+            base = fs.base.cpu().numpy()
+            y = net.forward(X).cpu().numpy() + base
             A.gradients(None)
             gfull = A.last_gradients()
             fs.update(gfull)
-            A.select_optimize()
+            sel = A.select_optimize()["selected"]
+            if sel < 0:
+                break
+            fs.note_selected(sel, gfull[sel])
             if it == 0:
                 continue  # no g_prev yet
             kstar = int(np.argmax(np.abs(gfull)))
             total += 1
-            hits["mlp"] += kstar in set(np.argsort(-y, kind="stable")[:K].tolist())
-            hits["heuristic"] += kstar in set(np.argsort(-heur, kind="stable")[:K].tolist())
+            o_mlp = np.argsort(-y, kind="stable")
+            o_heu = np.argsort(-base, kind="stable")
+            ranks["mlp"].append(int(np.nonzero(o_mlp == kstar)[0][0]))
+            ranks["heuristic"].append(int(np.nonzero(o_heu == kstar)[0][0]))
+            hits["mlp"] += ranks["mlp"][-1] < K
+            hits["heuristic"] += ranks["heuristic"][-1] < K
             hits["random"] += kstar in set(rng.choice(len(cre), K, replace=False).tolist())
     rec = {k: v / total for k, v in hits.items()}
-    print(f"recall@32 of the exact argmax over {total} iterations:", rec)
-    assert total >= 16
-    assert rec["mlp"] >= 0.75
+    print(f"recall@32 of the exact argmax over {total} held-out iterations:", rec)
+    print("rank of the exact argmax, network:", ranks["mlp"])
+    print("rank of the exact argmax, |g_prev|:", ranks["heuristic"])
+    print("mean rank network / heuristic:", np.mean(ranks["mlp"]), np.mean(ranks["heuristic"]),
+          " max:", max(ranks["mlp"]), max(ranks["heuristic"]))
+    miss = {k: sum(r >= 512 + 256 for r in v) for k, v in ranks.items()}
+    print("argmax ranked past K + audit = 768: network", miss["mlp"], "heuristic", miss["heuristic"])
+    assert total >= 40
     assert rec["mlp"] > rec["random"] + 0.5
-    assert rec["mlp"] >= rec["heuristic"] - 1.0 / total
+    assert rec["mlp"] >= rec["heuristic"]
+    # the gain: the argmax ranks at most 3/4 as deep on average, and no more
+    # often past the K + audit candidates
+    assert np.mean(ranks["mlp"]) <= 0.75 * np.mean(ranks["heuristic"])
+    assert miss["mlp"] <= miss["heuristic"]
 
 
-@pytest.mark.parametrize("K,audit,online,min_agree", [(512, 256, True, 9), (512, 256, False, 6),
-                                                      (128, 64, True, 6)])
-def test_screened_adapt_fp32_vs_full_sweep(hyp, scr, trained, K, audit, online, min_agree):
-    """Screened FP32 ADAPT on the 16-qubit workload (pool 2,044; top-K plus
-    an audit sample, judge every 5th iteration), judged by the full sweep on
-    its own state at every iteration, and its energy trajectory against a
-    plain FP64 full-sweep run from the same start.  K = 512 + 256 is the
-    deployed setting; K = 128 + 64 (9% of the pool) is the harder check."""
+@pytest.mark.parametrize("K,audit,online", [(512, 256, False), (128, 64, False)])
+def test_screened_adapt_fp32_vs_full_sweep(hyp, scr, trained, K, audit, online):
+    """Screened FP32 ADAPT on the 16-qubit workload (pool 2,044; top-K_t, the
+    band below it and a uniform audit, judge every 5th iteration), judged by
+    the full sweep on its own state at every iteration: every selection must
+    lie in that sweep's tie set, and after an FP64 polish of its ansatz the
+    final energy must be within 1e-6 Ha of a plain FP64 full-sweep run from
+    the same start.  K = 512 + 256 is the deployed setting; K = 128 + 64 (9%
+    of the pool) is the harder check (the fallback and the widening of the
+    top then carry more of the selection).  The network is the offline-trained
+    one (online steps are off by default)."""
     w = synth.WORKLOADS["h8_16q"]
     x, z, c, h, g = synth.hamiltonian(w)
     cre, ann, cls = synth.canonical_pool(w.n_orb)
@@ -263,22 +305,50 @@ def test_screened_adapt_fp32_vs_full_sweep(hyp, scr, trained, K, audit, online, 
         e32.append(info["energy"])
         e64.append(r64["energy"])
     print("screened picks in the full sweep's tie set on the same state:", agree_own, "/", n_iter)
-    print("per iteration (judge, fallback, true argmax in candidates, its rank by score):",
-          [(r["judge"], r["fallback"], r.get("shadow_in_candidates"), r.get("shadow_rank")) for r in sc.log])
+    print("per iteration (judge, fallback, top size, true argmax in candidates, its rank by score, "
+          "its rank by |g_prev|):",
+          [(r["judge"], r["fallback"], r["k_top"], r.get("shadow_in_candidates"), r.get("shadow_rank"),
+            r.get("shadow_rank_heuristic")) for r in sc.log])
     print("screened picks equal to the plain FP64 run's:", agree_plain, "/", n_iter)
     print("energy trajectories (screened FP32, plain FP64):", list(zip(e32, e64)))
-    assert agree_own >= min_agree
+    assert agree_own == n_iter
     assert e32[-1] < e32[0] - 1.0           # the screened run makes progress
-    if agree_own == n_iter:                 # same picks on every state: same trajectory
-        assert abs(e32[-1] - e64[-1]) <= 1e-4
-    if agree_plain == n_iter:
-        assert abs(A32.energy_fp64() - A64.energy_fp64()) < 1e-6
-    # the oracle's energy of the screened ansatz (plain definition, FP64)
+    # FP64 polish of the screened ansatz against the plain FP64 run
     ops, th = A32.ansatz()
+    Ap = hyp.Adapt(H, cre, ann, max_iter=n_iter + 1)
+    Ap.set_ansatz(ops, th)
+    rp = Ap.optimize()
+    print("final energies: plain FP64", A64.energy_fp64(), "screened FP32 polished in FP64", rp["energy"])
+    assert abs(rp["energy"] - A64.energy_fp64()) <= 1e-6
+    # the oracle's energy of the screened ansatz (plain definition, FP64)
     from oracle.adapt import SectorProblem
     prob = SectorProblem(w.n_orb, w.n_alpha, w.n_beta, x, z, c, cre, ann)
     psi = prob.state(list(ops), th)
     e_orc = oracle.dot(psi, prob.hpsi(psi))
     assert abs(A32.energy_fp64() - e_orc) < 1e-9
     n_exact = [r["n_exact"] for r in sc.log]
-    assert min(n_exact) <= K + audit < len(cre)
+    print("exact gradients per iteration:", n_exact)
+    assert min(n_exact) < len(cre)  # at least one iteration was screened
+
+
+def test_screened_adapt_online_training_diagnostic(hyp, scr, trained):
+    """The screen with one online Adam step per iteration (not deployed):
+    its picks against the full sweep on its own state, reported; the run must
+    stay valid (a pick every iteration, energy falling)."""
+    w = synth.WORKLOADS["h8_16q"]
+    x, z, c, h, g = synth.hamiltonian(w)
+    cre, ann, cls = synth.canonical_pool(w.n_orb)
+    S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    A32 = hyp.Adapt(H, cre, ann, dtype="f32", max_iter=11)
+    stat, qidx = scr.static_features(w.n_orb, cre, ann, cls, h, g)
+    sc = scr.Screen(A32, S, stat, qidx, trained.clone(), K=512, audit=256, judge_every=5, seed=42, online=True,
+                    cost_policy=False)
+    e = []
+    for it in range(10):
+        info = sc.iterate(it, shadow=True)
+        assert info["selected"] >= 0
+        e.append(info["energy"])
+    print("online training: picks in the full sweep's tie set:", sum(r["shadow_agree"] for r in sc.log), "/ 10;",
+          "ranks by score:", [r.get("shadow_rank") for r in sc.log])
+    assert e[-1] < e[0] - 1.0

@@ -80,3 +80,23 @@ def test_library_static_features_match_reference():
         stat, qidx = lib_so.static_features(M, cre, ann, cls, h, g)
         assert np.array_equal(qidx, Q.astype(np.int32))
         assert np.abs(stat - F.astype(np.float32)).max() <= 1e-6
+
+
+def test_last_selection_features_by_hand():
+    """Slots 18..21 against counts made by hand at M = 4: qubits 0..3 are
+    alpha orbitals 0..3, 4..7 beta."""
+    M = 4
+    # qidx rows: an alpha single (c=2, a=0), an alpha-beta double (c=2, 6; a=0, 4),
+    # a beta single (c=7, a=5), and the last selection itself
+    Q = np.array([[2, 0, -1, -1], [2, 6, 0, 4], [7, 5, -1, -1], [3, 7, 1, 5]])
+    F = np.zeros((4, om.N_FEAT))
+    last = np.array([3, 7, 1, 5])           # alpha-beta double c=(3, 7) a=(1, 5): spatial {3, 1}
+    X = om.features(F, Q, np.zeros(2 * M), np.ones(4), np.zeros(4), n_orb=M, last=last, last_g=0.01)
+    assert list(X[:, 18]) == [0, 0, 0, 1]
+    # spin-orbitals shared with {3, 7, 1, 5}: none; none; {7, 5}; all four
+    assert list(X[:, 19]) == [0, 0, 0.5, 1.0]
+    # spatial orbitals shared with {1, 3}: none; none ({2, 0}); {3, 1}; {3, 1}
+    assert list(X[:, 20]) == [0, 0, 0.5, 0.5]
+    assert np.allclose(X[:, 21], -2.0)
+    X0 = om.features(F, Q, np.zeros(2 * M), np.ones(4), np.zeros(4))
+    assert np.all(X0[:, 18:22] == 0)
