@@ -173,13 +173,15 @@ hyp_status hyp_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* si
  * is 0 or 1. */
 hyp_status hyp_set_support_skip(int on);
 
-/* Same-spin part of hyp_apply_h with FP64 storage: 1 (default) over grouped
- * lists, where each wave takes 8 consecutive output strings and loads every
- * source amplitude their rows share once (the union of their sources, each
- * with the 8 rows' coefficients); 0 over per-row lists, one output string
- * per wave.  Equal results up to summation order.  FP32 storage always uses
- * the per-row lists.  Process-wide; HYP_ERR_ARG unless on is 0 or 1. */
-hyp_status hyp_set_same_spin_groups(int on);
+/* Same-spin part of hyp_apply_h with FP64 storage.  tiles = 1, 2 or 4
+ * (default 2): grouped lists, where each wave takes 8 consecutive output
+ * strings and 64 columns and loads every source amplitude their rows share
+ * once (the union of their sources, each with the 8 rows' coefficients), and
+ * a four-wave workgroup holds `tiles` neighbouring column tiles of 4 / tiles
+ * consecutive groups; 0: per-row lists, one output string per wave.  Equal
+ * results up to summation order.  FP32 storage always uses the per-row
+ * lists.  Process-wide; HYP_ERR_ARG for other values. */
+hyp_status hyp_set_same_spin_groups(int tiles);
 
 /* Materialised sector Hamiltonian in CSR form, the paper's storage of H
  * ("Sparse State-Vector Emulation", Table 1 gives its size), kept as a

@@ -307,6 +307,15 @@ def set_support_skip(on: bool = True):
     check(_lib.load().hyp_set_support_skip(1 if on else 0))
 
 
+def set_same_spin_groups(tiles=2):
+    """hyp_set_same_spin_groups: FP64 same-spin pass over grouped lists (8
+    output strings per wave sharing their source loads; `tiles` = 1, 2 or 4
+    column tiles per four-wave workgroup; True = the default 2) or, for
+    0 / False, per-row lists."""
+    t = 2 if tiles is True else (0 if tiles is False else int(tiles))
+    check(_lib.load().hyp_set_same_spin_groups(t))
+
+
 def profile_enable(on: bool = True):
     check(_lib.load().hyp_profile_enable(1 if on else 0))
 

@@ -270,6 +270,17 @@ struct HamWork {
   int* cb_rank = nullptr;
   double* cb_coef = nullptr;
   int* cb_n = nullptr;
+  // grouped same-spin lists (FP64 pass): per spin [0] alpha rows, [1] beta
+  // rows: group offsets, union source ranks and coefficient rows, and their
+  // support-restricted copies with per-group lengths
+  int g_n[2] = {0, 0};
+  int64_t* g_off[2] = {nullptr, nullptr};
+  int* g_rank[2] = {nullptr, nullptr};
+  double* g_coef[2] = {nullptr, nullptr};
+  int* gc_rank[2] = {nullptr, nullptr};
+  double* gc_coef[2] = {nullptr, nullptr};
+  int* gc_cnt[2] = {nullptr, nullptr};
+  bool g_ok = false;
   // compact staging tables of the mixed pass (768-column chunks); c_ok when
   // every chunk fits a buffer
   uint16_t* c_bpos = nullptr;

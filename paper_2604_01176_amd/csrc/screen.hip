@@ -15,8 +15,8 @@
 
 namespace hyp {
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 // FP32 -> BF16, round to nearest even (NaN kept quiet)
 __device__ __host__ inline uint16_t f2bf(float f) {
@@ -148,53 +148,62 @@ struct GemmArgs {
 };
 
 // 64x64 output tile per 256-thread workgroup; each wave a 32x32 sub-tile of
-// four 16x16x16 bf16 MFMAs per k-step.  Lane l of a 16x16x16 MFMA holds
-// A[l%16][4(l/16)..+3], B[4(l/16)..+3][l%16] and D[4(l/16)+i][l%16].
+// four 16x16x32 BF16 MFMAs (gfx950) per 32-wide k-chunk.  The chunk's A tile
+// (64 rows x 32 k) and B tile (32 k x 64 columns, stored column-major) are
+// staged in LDS with k contiguous, so a lane's 8 operand values are one
+// 16-byte LDS read: lane l of an MFMA supplies A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16] for j < 8 (the same k slots on both sides, which
+// is all the reduction needs) and holds D[4 (l / 16) + i][l % 16].  Rows of
+// the LDS tiles are padded to 40 elements (80 bytes) against bank conflicts;
+// k past K and rows or columns past M, N are staged as zeros.
+constexpr int kGemmLd = 40;
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int m_base = blockIdx.y * 64 + (wave >> 1) * 32;
-  const int n_base = blockIdx.x * 64 + (wave & 1) * 32;
-  const int li = lane & 15, lk = (lane >> 4) * 4;
+  __shared__ __align__(16) uint16_t As[64 * kGemmLd];
+  __shared__ __align__(16) uint16_t Bs[64 * kGemmLd];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int mw = (wave >> 1) * 32, nw = (wave & 1) * 32;
+  const int li = lane & 15, lg = lane >> 4;
   float4_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
-    short4_t a[2], b[2];
+  for (int k0 = 0; k0 < g.K; k0 += 32) {
+    // stage: 64 x 32 elements of each operand, 8 per thread
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int m = m_base + i * 16 + li;
-      short4_t v;
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        v[t] = (m < g.M) ? (short)g.A[(int64_t)m * g.sam + (int64_t)(k0 + lk + t) * g.sak] : (short)0;
-      a[i] = v;
+    for (int t = 0; t < 8; ++t) {
+      const int e = t * 256 + tid;
+      const int r = e >> 5, k = e & 31;
+      const int kk = k0 + k;
+      const int m = m0 + r, n = n0 + r;
+      As[r * kGemmLd + k] = (m < g.M && kk < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)kk * g.sak] : (uint16_t)0;
+      Bs[r * kGemmLd + k] = (n < g.N && kk < g.K) ? g.B[(int64_t)kk * g.sbk + (int64_t)n * g.sbn] : (uint16_t)0;
     }
+    __syncthreads();
+    bf16x8_t a[2], b[2];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int n = n_base + j * 16 + li;
-      short4_t v;
+    for (int i = 0; i < 2; ++i)
+      a[i] = *(const bf16x8_t*)&As[(mw + i * 16 + li) * kGemmLd + lg * 8];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        v[t] = (n < g.N) ? (short)g.B[(int64_t)(k0 + lk + t) * g.sbk + (int64_t)n * g.sbn] : (short)0;
-      b[j] = v;
-    }
+    for (int j = 0; j < 2; ++j)
+      b[j] = *(const bf16x8_t*)&Bs[(nw + j * 16 + li) * kGemmLd + lg * 8];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int n = n_base + j * 16 + li;
+      const int n = n0 + nw + j * 16 + li;
       if (n >= g.N) continue;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int m = m_base + i * 16 + lk + t;
+        const int m = m0 + mw + i * 16 + lg * 4 + t;
         if (m >= g.M) continue;
         float v = acc[i][j][t] + (g.bias ? g.bias[n] : 0.f);
         if (g.C) g.C[(int64_t)m * g.N + n] = v;

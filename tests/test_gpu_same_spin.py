@@ -1,0 +1,94 @@
+"""The FP64 same-spin pass over grouped lists (8 consecutive output strings
+per wave sharing their source loads) against the oracle and against the
+per-row lists, with support skipping on and off: sectors whose string counts
+are and are not multiples of the group size, empty and full spins, and the
+32-qubit workload on its sparse input (every entry) and on sampled rows of
+the dense state."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hyp():
+    import paper_2604_01176_amd as hyp
+    return hyp
+
+
+def _ham(hyp, M, na, nb, seed):
+    h, g = synth.integrals(M, seed)
+    x, z, c = synth.jw_pauli_list(h, g)
+    S = hyp.Sector(M, na, nb)
+    H = hyp.Hamiltonian(S, x, z, c)
+    return S, H, (x, z, c)
+
+
+@pytest.mark.parametrize("M,na,nb", [(4, 2, 2), (5, 3, 2), (6, 3, 3), (7, 2, 5), (8, 4, 4), (9, 5, 4),
+                                     (10, 5, 5), (3, 0, 2), (4, 4, 1), (11, 6, 5)])
+@pytest.mark.parametrize("skip", [True, False])
+def test_grouped_equals_oracle_and_per_row(hyp, M, na, nb, skip):
+    S, H, (x, z, c) = _ham(hyp, M, na, nb, 300 + M)
+    assert H.structured
+    idx, val = synth.sparse_state(S.dim, S.da, n_random=max(1, S.dim // 50))
+    states = [synth.random_state(S.dim, 7), np.zeros(S.dim)]
+    states[1][idx] = val
+    hyp.set_support_skip(skip)
+    try:
+        for psi in states:
+            d = torch.from_numpy(psi).cuda()
+            hyp.set_same_spin_groups(False)
+            per_row = H.apply(d).cpu().numpy()
+            ref = oracle.apply_h(M, na, nb, x, z, c, psi)
+            nrm = max(np.linalg.norm(ref), 1e-300)
+            for tiles in (1, 2, 4):  # the workgroup shapes of the grouped kernel
+                hyp.set_same_spin_groups(tiles)
+                got = H.apply(d).cpu().numpy()
+                assert np.linalg.norm(got - ref) <= 1e-12 * nrm, tiles
+                assert np.linalg.norm(got - per_row) <= 1e-14 * nrm, tiles
+    finally:
+        hyp.set_same_spin_groups(True)
+        hyp.set_support_skip(True)
+
+
+def test_grouped_32q(hyp):
+    w = synth.WORKLOADS["h16_32q"]
+    x, z, c, _, _ = synth.hamiltonian(w)
+    S = hyp.Sector(w.n_orb, w.n_alpha, w.n_beta)
+    H = hyp.Hamiltonian(S, x, z, c)
+    idx, val = synth.sparse_state(S.dim, S.da)
+    ref = oracle.apply_h_sparse(w.n_orb, w.n_alpha, w.n_beta, x, z, c, idx, val)
+    d = torch.zeros(S.dim, dtype=torch.float64, device="cuda")
+    d[torch.from_numpy(idx).cuda()] = torch.from_numpy(val).cuda()
+    for skip in (True, False):
+        hyp.set_support_skip(skip)
+        try:
+            print(f"[same-spin] 32 qubits, sparse input, skipping {skip}", flush=True)
+            got = H.apply(d).cpu().numpy()
+        finally:
+            hyp.set_support_skip(True)
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+        assert np.count_nonzero(got[ref == 0.0]) == 0
+    # dense benchmark state: grouped against per-row on every entry, the
+    # oracle on sampled rows (first and last rows of groups and tiles)
+    psi_h = synth.random_state(S.dim, 7)
+    dp = torch.from_numpy(psi_h).cuda()
+    got = H.apply(dp)
+    hyp.set_same_spin_groups(False)
+    try:
+        per_row = H.apply(dp)
+    finally:
+        hyp.set_same_spin_groups(True)
+    rel = (torch.linalg.norm(got - per_row) / torch.linalg.norm(per_row)).item()
+    print(f"[same-spin] dense 32 qubits: grouped vs per-row relative difference {rel:.2e}", flush=True)
+    assert rel <= 1e-14
+    da = S.da
+    rows = np.array([0, 7, 8, 255, 256, da - 1, da, 8 * da + 63, 12864 * da + 12865, S.dim - 1], dtype=np.int64)
+    ref_rows = oracle.apply_h(w.n_orb, w.n_alpha, w.n_beta, x, z, c, psi_h, out_idx=rows)
+    g_rows = got[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert np.abs(g_rows - ref_rows).max() <= 1e-12 * np.abs(ref_rows).max()
