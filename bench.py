@@ -90,8 +90,9 @@ def roofline(name, ms, m):
 
 # source file of each kernel whose counters are committed
 KERNEL_SOURCES = {"k_mixed": "hamiltonian.hip", "k_ss_apply": "hamiltonian.hip", "k_transpose": "hamiltonian.hip",
-                  "k_tdens_rows": "sweep.hip", "k_tdens_rows_final": "sweep.hip", "k_gram_grad": "sweep.hip",
-                  "k_rotate": "pool.hip", "k_dot_partial_f64": "sector.hip"}
+                  "k_ssg_compact": "hamiltonian.hip", "k_tdens_rows": "sweep.hip", "k_tdens_rows_final": "sweep.hip",
+                  "k_gram_grad": "sweep.hip", "k_core_gram_a": "core_gram.hip", "k_core_gram_b": "core_gram.hip",
+                  "k_gram_transpose": "core_gram.hip", "k_rotate": "pool.hip", "k_dot_partial_f64": "sector.hip"}
 
 
 def source_digest(kernel=None):
