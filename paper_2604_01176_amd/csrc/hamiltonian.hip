@@ -417,7 +417,7 @@ __global__ void __launch_bounds__(256) k_ssg_compact(const int64_t* __restrict__
 }
 
 struct SSGArgs {
-  const double* in;         // [nrow][ncol]
+  const void* in;           // [nrow][ncol] storage T
   double* out;              // [nrow][ncol] FP64 partial
   const int64_t* off;       // [ngroups + 1] list offsets
   const int* urank;         // union source ranks
@@ -434,7 +434,7 @@ struct SSGArgs {
 // groups.  XCD-aware like k_ss_apply: an XCD's consecutive blocks take
 // consecutive groups of one tile group, so that the tile group's slab of the
 // input stays in that XCD's L2 as long as it can.
-template <int kW>
+template <typename T, int kW>
 __global__ void __launch_bounds__(256) k_ss_apply_g(SSGArgs a) {
   constexpr int kGq = 4 / kW;  // groups per workgroup
   const int b = blockIdx.x;
@@ -456,13 +456,14 @@ __global__ void __launch_bounds__(256) k_ss_apply_g(SSGArgs a) {
   double acc[kSSG];
 #pragma unroll
   for (int j = 0; j < kSSG; ++j) acc[j] = 0.0;
+  const T* __restrict__ in = (const T*)a.in;
   int u = 0;
   for (; u + 8 <= n; u += 8) {  // eight independent loads in flight per wave
     double v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int r = __builtin_amdgcn_readfirstlane(rk[u + i]);
-      v[i] = a.in[(int64_t)r * a.ncol + colc];
+      v[i] = (double)in[(int64_t)r * a.ncol + colc];
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i)
@@ -471,7 +472,7 @@ __global__ void __launch_bounds__(256) k_ss_apply_g(SSGArgs a) {
   }
   for (; u < n; ++u) {
     const int r = __builtin_amdgcn_readfirstlane(rk[u]);
-    const double v = a.in[(int64_t)r * a.ncol + colc];
+    const double v = (double)in[(int64_t)r * a.ncol + colc];
 #pragma unroll
     for (int j = 0; j < kSSG; ++j) acc[j] = fma(cf[u * kSSG + j], v, acc[j]);
   }
@@ -1198,7 +1199,8 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   HYP_LAUNCH("k_transpose", k_transpose<T>, tg, dim3(256), 0, st, (const T*)psi, (T*)W->psi_t, db, da, nz_b,
              nz_a);
   if (sizeof(T) == 8 && g_ss_groups != 0 && W->g_ok) {
-    // FP64: grouped lists (support-restricted copies when skipping)
+    // FP64: grouped lists (support-restricted copies when skipping); FP32
+    // storage keeps the per-row lists (measured: 35 against 29 ms at 32 qubits)
     for (int sp = 0; sp < 2; ++sp) {
       const int ng = W->g_n[sp];
       if (skip)
@@ -1206,7 +1208,7 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
                    W->g_rank[sp], W->g_coef[sp], ng, sp == 0 ? nz_a : nz_b, W->gc_rank[sp], W->gc_coef[sp],
                    W->gc_cnt[sp]);
       SSGArgs ga;
-      ga.in = sp == 0 ? (const double*)W->psi_t : (const double*)psi;
+      ga.in = sp == 0 ? (const void*)W->psi_t : psi;
       ga.out = sp == 0 ? W->part_a : W->part_b;
       ga.off = W->g_off[sp];
       ga.urank = skip ? W->gc_rank[sp] : W->g_rank[sp];
@@ -1220,11 +1222,11 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
       const int ngq = (ng + 4 / kw - 1) / (4 / kw);
       const int64_t nblk = (int64_t)8 * ((ga.ntq + 7) / 8) * ngq;
       if (kw == 4)
-        HYP_LAUNCH("k_ss_apply", k_ss_apply_g<4>, dim3((unsigned)nblk), dim3(256), 0, st, ga);
+        HYP_LAUNCH("k_ss_apply", (k_ss_apply_g<T, 4>), dim3((unsigned)nblk), dim3(256), 0, st, ga);
       else if (kw == 2)
-        HYP_LAUNCH("k_ss_apply", k_ss_apply_g<2>, dim3((unsigned)nblk), dim3(256), 0, st, ga);
+        HYP_LAUNCH("k_ss_apply", (k_ss_apply_g<T, 2>), dim3((unsigned)nblk), dim3(256), 0, st, ga);
       else
-        HYP_LAUNCH("k_ss_apply", k_ss_apply_g<1>, dim3((unsigned)nblk), dim3(256), 0, st, ga);
+        HYP_LAUNCH("k_ss_apply", (k_ss_apply_g<T, 1>), dim3((unsigned)nblk), dim3(256), 0, st, ga);
     }
     return run_mixed<T>(Hm, W, psi, sigma, nz_b, st);
   }

@@ -6,8 +6,6 @@
 // pool-gradient kernels.
 #include "hyp_internal.h"
 
-#include <hipcub/hipcub.hpp>
-
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -287,6 +285,90 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 __global__ void k_cast_bf16(const float* a, int64_t n, uint16_t* b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = f2bf(a[i]);
+}
+
+// Stable sort of n scores, descending (ties keep index order): one
+// workgroup, least-significant-digit radix sort over 8 passes of 4 bits of
+// an order-reversing integer image of the FP32 key (keys negated in order:
+// descending scores become ascending images; -0 is taken as +0).  Thread t
+// owns the index range [t n / T, (t + 1) n / T): per pass it counts its
+// digits, an exclusive scan in (digit, thread) order gives every thread its
+// first position per digit, and the thread scatters its range in order, so
+// equal digits keep their order and the sort is stable.  Keys and indices
+// alternate between (uA, iA) and (uB, iB); after the eighth pass they are
+// back in (uA, iA), iA being the output order.
+constexpr int kSortThreads = 1024;
+__global__ void __launch_bounds__(kSortThreads) k_rank_sort(const float* __restrict__ y, const float* __restrict__ base,
+                                                           int64_t n, uint32_t* uA, int* iA, uint32_t* uB, int* iB) {
+  __shared__ int cnt[16 * kSortThreads];  // [digit][thread], then first positions
+  __shared__ int wsum[kSortThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t lo = (int64_t)t * n / kSortThreads, hi = (int64_t)(t + 1) * n / kSortThreads;
+  for (int64_t i = lo; i < hi; ++i) {
+    float f = y[i] + (base ? base[i] : 0.f);
+    uint32_t b = __float_as_uint(f);
+    if (b == 0x80000000u) b = 0u;                     // -0 as +0
+    b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);   // ascending image of the float order
+    uA[i] = ~b;                                       // descending scores first
+    iA[i] = (int)i;
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 8; ++pass) {
+    const uint32_t* us = (pass & 1) ? uB : uA;
+    const int* is = (pass & 1) ? iB : iA;
+    uint32_t* ud = (pass & 1) ? uA : uB;
+    int* id = (pass & 1) ? iA : iB;
+    const int sh = 4 * pass;
+    int c[16];
+#pragma unroll
+    for (int d = 0; d < 16; ++d) c[d] = 0;
+    for (int64_t i = lo; i < hi; ++i) {
+      const int d = (us[i] >> sh) & 15;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) c[e] += (d == e) ? 1 : 0;
+    }
+#pragma unroll
+    for (int d = 0; d < 16; ++d) cnt[d * kSortThreads + t] = c[d];
+    __syncthreads();
+    // exclusive scan of cnt in flattened (digit, thread) order: thread t owns
+    // entries [16 t, 16 t + 16)
+    int v[16], s = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      v[j] = cnt[16 * t + j];
+      s += v[j];
+    }
+    int inc = s;  // inclusive scan of the per-thread sums across the workgroup
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += u;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int before = 0;
+    for (int j = 0; j < w; ++j) before += wsum[j];
+    int run = before + inc - s;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      cnt[16 * t + j] = run;
+      run += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < 16; ++d) c[d] = cnt[d * kSortThreads + t];
+    for (int64_t i = lo; i < hi; ++i) {
+      const uint32_t u = us[i];
+      const int d = (u >> sh) & 15;
+      int pos = 0;
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        if (d == e) pos = c[e]++;
+      ud[pos] = u;
+      id[pos] = is[i];
+    }
+    __syncthreads();  // this pass's scatter complete before the next pass reads it
+  }
 }
 
 __global__ void k_iota(int* v, int64_t n) {
@@ -667,31 +749,21 @@ hyp_status hyp_rank_scores(hyp_mlp m, const float* y_dev, const float* base_dev,
   hipStream_t st = (hipStream_t)stream;
   if (n > m->sort_cap) {
     HYP_HIP(hipDeviceSynchronize());
-    (void)hipFree(m->sort_tmp);
     (void)hipFree(m->keys_out);
     (void)hipFree(m->idx_in);
-    m->sort_tmp = nullptr;
-    size_t bytes = 0;
-    HYP_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, bytes, (const float*)nullptr, (float*)nullptr,
-                                                         (const int*)nullptr, (int*)nullptr, (int)n));
-    HYP_HIP(hipMalloc(&m->sort_tmp, bytes));
-    HYP_HIP(hipMalloc(&m->keys_out, sizeof(float) * n));
-    HYP_HIP(hipMalloc(&m->idx_in, sizeof(int) * n));
     (void)hipFree(m->keys_in);
+    m->keys_out = nullptr;
+    m->idx_in = nullptr;
     m->keys_in = nullptr;
-    HYP_HIP(hipMalloc(&m->keys_in, sizeof(float) * n));
-    m->sort_tmp_bytes = bytes;
+    m->sort_cap = 0;
+    HYP_HIP(hipMalloc(&m->keys_in, sizeof(uint32_t) * n));
+    HYP_HIP(hipMalloc(&m->keys_out, sizeof(uint32_t) * n));
+    HYP_HIP(hipMalloc(&m->idx_in, sizeof(int) * n));
     m->sort_cap = n;
   }
-  HYP_LAUNCH("k_iota", k_iota, dim3(g1(n)), dim3(256), 0, st, m->idx_in, n);
-  const float* keys = y_dev;
-  if (base_dev) {
-    HYP_LAUNCH("k_add_base", k_add_base, dim3(g1(n)), dim3(256), 0, st, y_dev, base_dev, n, m->keys_in);
-    keys = m->keys_in;
-  }
-  size_t bytes = m->sort_tmp_bytes;
-  HYP_HIP(hipcub::DeviceRadixSort::SortPairsDescending(m->sort_tmp, bytes, keys, m->keys_out, m->idx_in,
-                                                       (int*)order_dev, (int)n, 0, 32, st));
+  HYP_LAUNCH("k_rank_sort", k_rank_sort, dim3(1), dim3(kSortThreads), 0, st, y_dev, base_dev, n,
+             (uint32_t*)m->keys_in, (int*)order_dev, (uint32_t*)m->keys_out, m->idx_in);
+  HYP_HIP(hipGetLastError());
   return HYP_OK;
 }
 

@@ -138,6 +138,24 @@ def test_rank_scores(scr):
     assert np.array_equal(order, np.argsort(-y, kind="stable"))
 
 
+@pytest.mark.parametrize("n", [1, 7, 1023, 1025, 39960, 100003])
+def test_rank_scores_sizes_ties_and_signed_zeros(scr, n):
+    """The hand-written radix ranking against numpy's stable argsort: sizes
+    below, at and past the workgroup width, the 32-qubit pool, ties, both
+    zeros, large magnitudes, and y + base summed in FP32."""
+    rng = np.random.default_rng(n)
+    y = np.round(rng.standard_normal(n) * 3, 1).astype(np.float32)
+    y[rng.choice(n, max(1, n // 10))] = np.float32(-0.0)
+    y[rng.choice(n, max(1, n // 10))] = np.float32(0.0)
+    y[rng.choice(n, max(1, n // 50))] = np.float32(3e38)
+    y[rng.choice(n, max(1, n // 50))] = np.float32(-3e38)
+    base = np.round(rng.standard_normal(n), 1).astype(np.float32)
+    net = scr.MLP(synth.mlp_init(0), 64)
+    order = net.rank(torch.from_numpy(y).cuda(), torch.from_numpy(base).cuda()).cpu().numpy()
+    key = (y + base).astype(np.float32)
+    assert np.array_equal(order, np.argsort(-key, kind="stable"))
+
+
 def _train_on(hyp, scr, workloads, n_iter, epochs, seed=0):
     Xs, ts = [], []
     for i, w in enumerate(workloads):
