@@ -282,8 +282,16 @@ def main():
     if not args.no_extras:
         sup, asm = extras(hyp, torch, np, synth, S, H, ops, grad, w, M, na, nb)
 
-    hpsi_kernels = ("k_clear_u32", "k_transpose", "k_ss_compact", "k_ssg_compact", "k_ss_apply", "k_mixed")
-    hpsi_ms = sum(prof.get(k, (0.0, 0))[0] for k in hpsi_kernels) / args.steps
+    # H psi wall time on the caller's stream (the same-spin pass overlaps the
+    # mixed pass on a side stream, so summed kernel times would overcount)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        hyp.hyp_apply_h(H, psi, sig)
+    e1.record()
+    torch.cuda.synchronize()
+    hpsi_ms = e0.elapsed_time(e1) / 3
     hpsi_bytes = hpsi_gather_bytes(m)
     value = hpsi_bytes / (hpsi_ms * 1e-3) / 1e9
     sweep_kernels = ("k_pool_grad", "k_sum_chunks", "k_tdens", "k_tdens_reduce_ab", "k_tdens_reduce_a",
