@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
-FP64_VECTOR_TFLOPS = 78.6    # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz
+FP64_VECTOR_TFLOPS = 78.6    # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz; the FP64 matrix peak is the same
 
 
 def model(M, na, nb, T, pool):
@@ -61,7 +61,7 @@ def kernel_flops(name, m):
         N = m["na"] if name.endswith("_a") else m["nb"]
         K = m["db"] if name.endswith("_a") else m["da"]
         S = math.comb(M - N + 2, 2)
-        return 2.0 * math.comb(M, N - 2) * S * S * K, "alu"
+        return 2.0 * math.comb(M, N - 2) * S * S * K, "mfma"
     if name == "k_pool_grad":
         return 4.0 * m["pairs"], "alu"
     return 2.0 * m["nnz"], "alu"

@@ -18,13 +18,16 @@
 // against 6% of the full string-space Gram.
 //
 // Kernel: one workgroup of 256 threads (4 waves) per (core, 48 x 48 tile of
-// the block); each lane holds a 6 x 6 sub-tile (slots r + 8a, c + 8b of lane
-// r + 8c), the four waves take interleaved quarters of every 32-column chunk
-// and add their tiles in LDS at the end.  Chunks of the 96 rows are staged by
-// direct global->LDS copies into two alternating buffers, the next copy in
-// flight while the current one is multiplied; rows are padded to 34 doubles
-// so that the 16-byte reads of 8 consecutive slots fall in distinct banks.
-// FP64 fused multiply-adds on the vector ALU.
+// the block).  Each wave holds the whole tile as 3 x 3 FP64 MFMA blocks
+// (v_mfma_f64_16x16x4_f64: per 4 columns one 8-byte operand per lane for
+// each 16-slot row block of X and of Y) over its quarter of every 32-column
+// chunk, and the four waves add their tiles in LDS at the end.  Chunks of
+// the 96 rows are staged by direct global->LDS copies into two alternating
+// buffers, the next copy in flight while the current one is multiplied;
+// rows are padded to 34 doubles.  A dense contraction, so the matrix cores:
+// the same FP64 peak as the vector ALU on this chip, but a third of the
+// registers of a 6 x 6 per-lane register tile, hence more resident waves to
+// cover the copies, and 6 LDS reads per 9 MFMAs.
 #include "hyp_internal.h"
 
 #include <algorithm>
@@ -42,6 +45,7 @@ constexpr int kGThreads = 256;
 constexpr int kGPer = (kGPieces + kGThreads - 1) / kGThreads;
 constexpr uint32_t kGLdsBytes = 2 * kGBufBytes + kGRows * 4 + 16;
 typedef double f64x2 __attribute__((ext_vector_type(2)));  // one 16-byte LDS read or write
+typedef double f64x4 __attribute__((ext_vector_type(4)));  // a lane's part of a 16 x 16 MFMA block
 
 struct GramArgs {
   const double* X;        // dense FP64 rows (sigma), row r at X + r * ld
@@ -65,7 +69,7 @@ struct GramArgs {
 __device__ inline bool gram_gathered(const GramArgs& a) { return a.klist && 2 * (*a.kcount) <= a.K; }
 
 template <typename T>
-__global__ void __launch_bounds__(kGThreads) k_core_gram(GramArgs a) {
+__global__ void __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(3))) k_core_gram(GramArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   int* s_row = (int*)(smem + 2 * kGBufBytes);
   int* s_any = s_row + kGRows;
@@ -97,41 +101,43 @@ __global__ void __launch_bounds__(kGThreads) k_core_gram(GramArgs a) {
     return;
   }
   // this thread's pieces of a buffer: LDS piece q = j * 256 + tid holds
-  // columns 2 col, 2 col + 1 of staged row q / 17 (col = q % 17; col 16 pads)
-  int prow[kGPer], pcol[kGPer];
+  // columns 2 col, 2 col + 1 of staged row q / 17 (col = q % 17; col 16
+  // pads), rows below kGT from X, the others from Y; off[j] = the piece's
+  // first element in its operand (row * ld + 2 col), -1 for no piece (a pad
+  // column or a row without a slot)
+  int off[kGPer];
 #pragma unroll
   for (int j = 0; j < kGPer; ++j) {
     const int q = j * kGThreads + tid;
     const int row = q / (kGLd / 2), col = q - row * (kGLd / 2);
     const bool act = q < kGPieces && col < kGC / 2 && s_row[row] >= 0;
-    prow[j] = act ? row : -1;
-    pcol[j] = col;
+    off[j] = act ? (int)((int64_t)s_row[row] * a.ld + 2 * col) : -1;
   }
   const uint32_t buf0 = lds_addr(smem), buf1 = buf0 + kGBufBytes;
-  const int r = lane & 7, c = lane >> 3;
-  double acc[6][6];
+  // MFMA operands: lane l supplies row (l & 15) of a 16-slot block at column
+  // (l >> 4) of each 4-column step; block (bi, bj) of the result holds
+  // Gc[16 bi + (l >> 4) + 4 e][16 bj + (l & 15)] in element e of lane l
+  const int mr = lane & 15, mk = lane >> 4;
+  f64x4 acc[3][3];
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < 3; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
   auto compute = [&](uint32_t buf) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const uint32_t kb = (uint32_t)(8 * w + 2 * s) * 8u;
-      f64x2 x[6], y[6];
+    for (int s = 0; s < 2; ++s) {
+      const uint32_t kb = (uint32_t)(8 * w + 4 * s + mk) * 8u;
+      double x[3], y[3];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        x[i] = lds_load<f64x2>(buf + (uint32_t)((r + 8 * i) * kGLd) * 8u + kb);
-        y[i] = lds_load<f64x2>(buf + (uint32_t)((kGT + c + 8 * i) * kGLd) * 8u + kb);
+      for (int i = 0; i < 3; ++i) {
+        x[i] = lds_load<double>(buf + (uint32_t)((16 * i + mr) * kGLd) * 8u + kb);
+        y[i] = lds_load<double>(buf + (uint32_t)((kGT + 16 * i + mr) * kGLd) * 8u + kb);
       }
 #pragma unroll
-      for (int i = 0; i < 6; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          acc[i][j] = fma(x[i].x, y[j].x, acc[i][j]);
-          acc[i][j] = fma(x[i].y, y[j].y, acc[i][j]);
-        }
+        for (int j = 0; j < 3; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i], y[j], acc[i][j], 0, 0, 0);
     }
   };
   // columns [k0, k0 + kn) through registers, zeros past kn and on rows
@@ -140,11 +146,12 @@ __global__ void __launch_bounds__(kGThreads) k_core_gram(GramArgs a) {
 #pragma unroll
     for (int j = 0; j < kGPer; ++j) {
       const int q = j * kGThreads + tid;
-      if (q < kGPieces && pcol[j] < kGC / 2) {
+      const int row = q / (kGLd / 2), col = q - row * (kGLd / 2);
+      if (q < kGPieces && col < kGC / 2) {
         double v0 = 0.0, v1 = 0.0;
-        if (prow[j] >= 0) {
-          const int row = prow[j], k = 2 * pcol[j];
-          const int64_t rr = s_row[row];
+        const int64_t rr = s_row[row];
+        if (rr >= 0) {
+          const int k = 2 * col;
           if (kl) {
             const T* base = (const T*)(row < kGT ? a.Xs : a.Ys);
             if (k < kn) v0 = (double)base[rr * a.rs + (int64_t)kl[k0 + k] * a.cs];
@@ -172,18 +179,15 @@ __global__ void __launch_bounds__(kGThreads) k_core_gram(GramArgs a) {
     }
   } else {
     const int nfull = a.dma ? a.K / kGC : 0;
-    // piece sources of the direct copies (column 0 of the chunk)
-    const double* src[kGPer];
-#pragma unroll
-    for (int j = 0; j < kGPer; ++j)
-      src[j] = prow[j] >= 0 ? (prow[j] < kGT ? a.X : a.Y) + (int64_t)s_row[prow[j]] * a.ld + 2 * pcol[j] : a.X;
     auto issue = [&](uint32_t buf, int k0) {
 #pragma unroll
       for (int j = 0; j < kGPer; ++j) {
         const int base = j * kGThreads + w * 64;  // wave-uniform first piece
         if (base < kGPieces) {
           const uint32_t dst = (uint32_t)__builtin_amdgcn_readfirstlane(buf + (uint32_t)base * 16u);
-          if (prow[j] >= 0) dma16(dst, src[j] + k0);
+          // pieces of rows below kGT come from X (base + lane below 17 kGT)
+          const double* op = (j * kGThreads + tid) < kGT * (kGLd / 2) ? a.X : a.Y;
+          if (off[j] >= 0) dma16(dst, op + off[j] + k0);
         }
       }
     };
@@ -217,19 +221,21 @@ __global__ void __launch_bounds__(kGThreads) k_core_gram(GramArgs a) {
   for (int ww = 0; ww < 4; ++ww) {
     if (w == ww) {
 #pragma unroll
-      for (int i = 0; i < 6; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          const int li = r + 8 * i, lj = c + 8 * j;
-          double v = acc[i][j];
-          if (ww > 0) v += red[li * kGT + lj];
-          if (ww < 3) {
-            red[li * kGT + lj] = v;
-          } else {
-            const int gi = ti * kGT + li, gj = tj * kGT + lj;
-            if (gi < a.S && gj < a.S) Gt[(int64_t)gi * a.S + gj] = v;
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int li = 16 * i + mk + 4 * e, lj = 16 * j + mr;
+            double v = acc[i][j][e];
+            if (ww > 0) v += red[li * kGT + lj];
+            if (ww < 3) {
+              red[li * kGT + lj] = v;
+            } else {
+              const int gi = ti * kGT + li, gj = tj * kGT + lj;
+              if (gi < a.S && gj < a.S) Gt[(int64_t)gi * a.S + gj] = v;
+            }
           }
-        }
     }
     __syncthreads();
   }
