@@ -183,6 +183,22 @@ hyp_status hyp_set_support_skip(int on);
  * lists.  Process-wide; HYP_ERR_ARG for other values. */
 hyp_status hyp_set_same_spin_groups(int tiles);
 
+/* Same-spin doubles of hyp_apply_h with FP64 storage through the strings'
+ * cores (the paper's "Sparse State-Vector Emulation" product; the doubles
+ * are 784 of the 849 same-spin entries of a row at 16 orbitals and 8
+ * electrons).  Two strings joined by a same-spin double share exactly one
+ * core, an (N-2)-electron string, so for each core K the doubles are a dense
+ * S x S product (S = C(M - N + 2, 2) slots) of the core's rows, Y_K = W_K
+ * psi_K, formed on FP64 MFMA in column bands, and each output row adds its
+ * C(N, 2) cores' rows of Y in a fixed order (deterministic) beside its
+ * singles and diagonal, which keep the per-row lists.  on = 1 (default)
+ * where the tables were built with the Hamiltonian (every core of both spins
+ * with at most 48 slots; a band of Y takes at most 4 GiB of device memory,
+ * allocated with the Hamiltonian); 0 the grouped or per-row lists of
+ * hyp_set_same_spin_groups.  Equal results up to summation order.
+ * Process-wide; HYP_ERR_ARG unless on is 0 or 1. */
+hyp_status hyp_set_same_spin_cores(int on);
+
 /* Materialised sector Hamiltonian in CSR form, the paper's storage of H
  * ("Sparse State-Vector Emulation", Table 1 gives its size), kept as a
  * comparison for the matrix-free product.  Every row holds the same L

@@ -316,6 +316,13 @@ def set_same_spin_groups(tiles=2):
     check(_lib.load().hyp_set_same_spin_groups(t))
 
 
+def set_same_spin_cores(on: bool = True):
+    """hyp_set_same_spin_cores: FP64 same-spin doubles as per-core dense
+    products on the matrix cores (default) or through the lists of
+    set_same_spin_groups."""
+    check(_lib.load().hyp_set_same_spin_cores(1 if on else 0))
+
+
 def profile_enable(on: bool = True):
     check(_lib.load().hyp_profile_enable(1 if on else 0))
 

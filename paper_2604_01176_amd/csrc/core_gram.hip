@@ -305,9 +305,43 @@ CoreSpace core_space(int M, int N) {
   return cs;
 }
 
-// Slot table of the string space (M, N): rows[core][slot] = rank of the
+// Host tables of the string space (M, N): rows[core][slot] = rank of the
 // string core | p | q, cores in colex order (increasing masks), slot
-// w (w - 1) / 2 + u for the u-th < w-th orbital outside the core.
+// w (w - 1) / 2 + u for the u-th < w-th orbital outside the core, and
+// masks[core] = the core's orbitals.
+hyp_status core_tables_host(int M, int N, const RankTables& R, std::vector<int>& rows,
+                            std::vector<uint32_t>& masks) {
+  const CoreSpace cs = core_space(M, N);
+  try {
+    rows.assign((size_t)cs.ncore * cs.S, 0);
+    masks.assign((size_t)cs.ncore, 0u);
+  } catch (...) {
+    return fail(HYP_ERR_NOMEM, "core tables: host allocation failed");
+  }
+  const uint32_t full = (1u << M) - 1u;
+  const int k = N - 2;
+  uint32_t core = (k == 0) ? 0u : ((1u << k) - 1u);
+  for (int64_t ci = 0; ci < cs.ncore; ++ci) {
+    masks[(size_t)ci] = core;
+    int comp[16];
+    int nf = 0;
+    for (int o = 0; o < M; ++o)
+      if (!(core >> o & 1u)) comp[nf++] = o;
+    for (int wv = 1; wv < nf; ++wv)
+      for (int u = 0; u < wv; ++u) {
+        const uint32_t s = core | (1u << comp[u]) | (1u << comp[wv]);
+        rows[(size_t)ci * cs.S + wv * (wv - 1) / 2 + u] = R.lo[s & 255u] + R.hi[(s >> 8) & 255u];
+      }
+    if (k > 0) {  // next mask with k bits (Gosper)
+      const uint32_t lo = core & (~core + 1u), rip = core + lo;
+      core = (((rip ^ core) >> 2) / lo) | rip;
+      if (ci + 1 < cs.ncore && (core & ~full)) return fail(HYP_ERR_HIP, "core enumeration overflow");
+    }
+  }
+  return HYP_OK;
+}
+
+// Device copy of the slot table of (M, N), cached per device.
 static hyp_status slot_rows(int M, int N, const RankTables& R, const int** out) {
   int dev = 0;
   HYP_HIP(hipGetDevice(&dev));
@@ -320,30 +354,9 @@ static hyp_status slot_rows(int M, int N, const RankTables& R, const int** out) 
     }
   const CoreSpace cs = core_space(M, N);
   std::vector<int> h;
-  try {
-    h.resize((size_t)cs.ncore * cs.S);
-  } catch (...) {
-    return fail(HYP_ERR_NOMEM, "core Gram slot table: host allocation failed");
-  }
-  const uint32_t full = (1u << M) - 1u;
-  const int k = N - 2;
-  uint32_t core = (k == 0) ? 0u : ((1u << k) - 1u);
-  for (int64_t ci = 0; ci < cs.ncore; ++ci) {
-    int comp[16];
-    int nf = 0;
-    for (int o = 0; o < M; ++o)
-      if (!(core >> o & 1u)) comp[nf++] = o;
-    for (int wv = 1; wv < nf; ++wv)
-      for (int u = 0; u < wv; ++u) {
-        const uint32_t s = core | (1u << comp[u]) | (1u << comp[wv]);
-        h[(size_t)ci * cs.S + wv * (wv - 1) / 2 + u] = R.lo[s & 255u] + R.hi[(s >> 8) & 255u];
-      }
-    if (k > 0) {  // next mask with k bits (Gosper)
-      const uint32_t lo = core & (~core + 1u), rip = core + lo;
-      core = (((rip ^ core) >> 2) / lo) | rip;
-      if (ci + 1 < cs.ncore && (core & ~full)) return fail(HYP_ERR_HIP, "core enumeration overflow");
-    }
-  }
+  std::vector<uint32_t> hm;
+  hyp_status rt = core_tables_host(M, N, R, h, hm);
+  if (rt != HYP_OK) return rt;
   SlotTab& t = cc.tab[cc.next];
   if (t.rows) {
     HYP_HIP(hipDeviceSynchronize());  // queued launches may still read the replaced table

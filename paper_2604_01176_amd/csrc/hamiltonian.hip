@@ -100,20 +100,21 @@ __global__ void k_clear_u32(uint32_t* p, int n) {
 // entries whose source row has a nonzero flag; c_n[r] = their count.  One
 // wave per row.
 __global__ void __launch_bounds__(256) k_ss_compact(const int* __restrict__ rank, const double* __restrict__ coef,
-                                                    int nent, int nrow, const uint32_t* __restrict__ src_nz,
+                                                    int nent, int nuse, int nrow, const uint32_t* __restrict__ src_nz,
                                                     int* __restrict__ c_rank, double* __restrict__ c_coef,
                                                     int* __restrict__ c_n) {
+  // rows of nent entries (the stride), of which the first nuse are compacted
   const int row = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
   if (row >= nrow) return;
   const int lane = threadIdx.x & 63;
   const int64_t base = (int64_t)row * nent;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   int n = 0;
-  for (int e0 = 0; e0 < nent; e0 += 64) {
+  for (int e0 = 0; e0 < nuse; e0 += 64) {
     const int e = e0 + lane;
     int r = 0;
     bool keep = false;
-    if (e < nent) {
+    if (e < nuse) {
       r = rank[base + e];
       keep = src_nz[r] != 0u;
     }
@@ -269,9 +270,19 @@ struct SSApplyArgs {
   double* out;              // [nrow][ncol] FP64 partial
   const int* list_rank;
   const double* list_coef;
-  const int* list_n;        // per-row entry counts (support-restricted lists), or null: nent each
-  int nent, nrow, ncol;
+  const int* list_n;        // per-row entry counts (support-restricted lists), or null: nuse each
+  int nent, nrow, ncol;     // nent: the lists' row stride
+  int nuse;                 // entries used per row (all nent, or the singles and diagonal head)
   int ntiles, nrb;          // 64-column tiles, 4-row blocks
+  // columns [c0, c0 + nc) (a band; 0, ncol for all) and, for the core path,
+  // the band's per-core products: row r adds Y[yoff[r][m] * ldy + c - c0]
+  // over its npair cores m (skipped where cnz flags a core as zero)
+  int c0, nc;
+  const double* Y;
+  int64_t ldy;
+  const int* yoff;
+  int npair, S;
+  const int* cnz;
 };
 
 // out[r][c] = sum_e coef[r][e] in[rank[r][e]][c].  Each wave owns one output
@@ -280,7 +291,7 @@ struct SSApplyArgs {
 // the 8 XCDs round-robin, so block b runs on XCD b % 8; consecutive blocks
 // of one XCD take consecutive row blocks of the same 64-column tile, and the
 // tile's slab of the input (nrow x 64 amplitudes) stays in that XCD's L2.
-template <typename T>
+template <typename T, bool kY>
 __global__ void __launch_bounds__(256) k_ss_apply(SSApplyArgs a) {
   const int b = blockIdx.x;
   const int xcd = b & 7, j = b >> 3;
@@ -289,13 +300,13 @@ __global__ void __launch_bounds__(256) k_ss_apply(SSApplyArgs a) {
   if (tile >= a.ntiles) return;
   const int row = rb * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (row >= a.nrow) return;
-  const int col = tile * 64 + (threadIdx.x & 63);
-  const bool live = col < a.ncol;
-  const int colc = live ? col : 0;
+  const int col = a.c0 + tile * 64 + (threadIdx.x & 63);
+  const bool live = col < a.c0 + a.nc && col < a.ncol;
+  const int colc = live ? col : a.c0;
   const int* __restrict__ rk = a.list_rank + (int64_t)row * a.nent;
   const double* __restrict__ cf = a.list_coef + (int64_t)row * a.nent;
   const T* __restrict__ in = (const T*)a.in;
-  const int nent = a.list_n ? __builtin_amdgcn_readfirstlane(a.list_n[row]) : a.nent;
+  const int nent = a.list_n ? __builtin_amdgcn_readfirstlane(a.list_n[row]) : a.nuse;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   int e = 0;
   // eight independent loads in flight per wave
@@ -313,8 +324,236 @@ __global__ void __launch_bounds__(256) k_ss_apply(SSApplyArgs a) {
     const int r = __builtin_amdgcn_readfirstlane(rk[e]);
     acc[0] += Acc<T>::prod(cf[e], in[(int64_t)r * a.ncol + colc]);
   }
-  const double acc0 = acc[0] + acc[2], acc1 = acc[1] + acc[3];
-  if (live) a.out[(int64_t)row * a.ncol + col] = acc0 + acc1;
+  double sum = (acc[0] + acc[2]) + (acc[1] + acc[3]);
+  if constexpr (kY) {
+    // the row's same-spin doubles: its npair cores' product rows, in order
+    const int* __restrict__ yo = a.yoff + (int64_t)row * a.npair;
+    const int64_t cy = colc - a.c0;
+    int m = 0;
+    for (; m + 8 <= a.npair; m += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int o = __builtin_amdgcn_readfirstlane(yo[m + u]);
+        const bool z = a.cnz && a.cnz[o / a.S] == 0;
+        v[u] = z ? 0.0 : a.Y[(int64_t)o * a.ldy + cy];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sum += v[u];
+    }
+    for (; m < a.npair; ++m) {
+      const int o = __builtin_amdgcn_readfirstlane(yo[m]);
+      if (!(a.cnz && a.cnz[o / a.S] == 0)) sum += a.Y[(int64_t)o * a.ldy + cy];
+    }
+  }
+  if (live) a.out[(int64_t)row * a.ncol + col] = sum;
+}
+
+// ---------------------------------------------------------------- same-spin doubles through cores
+//
+// Every same-spin double pairs two strings that share exactly one core: the
+// (N - 2)-electron string K = I & J, the two strings being K plus two
+// disjoint pairs of the F = M - N + 2 orbitals outside K (the core's S =
+// C(F, 2) slots; tables of core_gram.hip).  So the doubles part of the
+// same-spin product, sum over r' of H[r][r'] in[r'][c], is for each core a
+// small dense product
+//   Y_K[i][c] = sum_j W_K[i][j] in[K + slot j][c],
+// W_K[i][j] the coefficient of the double from K + slot j into K + slot i
+// (zero unless the slots are disjoint), and row r = K + slot i gathers
+// Y_K[i] over its C(N, 2) cores (k_ss_apply with kY).  A row's 784 gathered
+// sources (16 orbitals, 8 electrons) become 28 rows of Y, and each source
+// row is read once per core that holds it.
+//
+// k_ss_core: one 256-thread workgroup per core and column band.  W_K (S <=
+// 48, padded to 48) is evaluated from the folded double tables into
+// registers as FP64 MFMA A operands (lane l: row 16 b + (l & 15), column 4 s
+// + (l >> 4)); the band's 64-column chunks of the core's S source rows are
+// copied into two alternating LDS buffers (direct copies, the next chunk in
+// flight) and wave w forms the 48 x 16 block of Y for chunk columns
+// 16 w .. 16 w + 15 with v_mfma_f64_16x16x4_f64 (element e of lane l holds
+// row 16 b + (l >> 4) + 4 e, column l & 15).
+struct SSCoreArgs {
+  const double* in;        // [nrow][ld] FP64 rows (psi, or psi^T for the alpha rows)
+  int64_t ld;
+  int dma;                 // 1: in 16-byte aligned, ld and c0 even (direct copies)
+  const int* rows;         // [ncore][S] source row of each slot
+  const uint32_t* masks;   // [ncore] the core's orbitals
+  int ncore, S, M, spin;
+  int64_t per_xcd;         // ceil(ncore / 8): consecutive cores on one XCD
+  const uint32_t* wJ;      // folded same-spin double tables (HamDev)
+  const double* wF;
+  int c0, nc;              // the band's columns
+  double* Y;               // [ncore][S][ldy]
+  int64_t ldy;
+  const uint32_t* rflag;   // support skipping: flags of the source rows (null: every row)
+  int* cnz;                // [ncore] 1 if some source row of the core is flagged
+};
+constexpr int kCoreC = 64;                          // columns per staged chunk
+constexpr int kCoreLd = kCoreC + 2;                 // LDS row stride in doubles
+constexpr int kCorePieces = 48 * (kCoreLd / 2);     // 16-byte pieces per buffer
+constexpr uint32_t kCoreBuf = kCorePieces * 16u;    // 25,344 bytes
+constexpr int kCorePer = (kCorePieces + 255) / 256;
+
+__global__ void __launch_bounds__(256) k_ss_core(SSCoreArgs a) {
+  typedef double f64x4 __attribute__((ext_vector_type(4)));
+  typedef double f64x2 __attribute__((ext_vector_type(2)));
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_row[48];
+  __shared__ int s_comp[16];
+  __shared__ int s_any;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t b = blockIdx.x;
+  const int64_t core = (b & 7) * a.per_xcd + (b >> 3);
+  if (core >= a.ncore) return;
+  const int S = a.S;
+  const uint32_t K = a.masks[core];
+  if (tid < 48) s_row[tid] = tid < S ? a.rows[core * S + tid] : -1;
+  if (tid == 0) {
+    int nf = 0;
+    for (int o = 0; o < a.M; ++o)
+      if (!(K >> o & 1u)) s_comp[nf++] = o;
+    s_any = a.rflag ? 0 : 1;
+  }
+  __syncthreads();
+  if (a.rflag && tid < S && a.rflag[s_row[tid]] != 0u) s_any = 1;
+  __syncthreads();
+  if (a.rflag && tid == 0) a.cnz[core] = s_any;
+  if (!s_any) return;  // no source row in the support: the rows' gatherers skip this core
+  // W_K as MFMA A operands
+  const int mr = lane & 15, mk = lane >> 4;
+  const int off = a.spin * a.M;
+  auto slot_pair = [&](int i, int& p, int& q) {
+    int wv = 1;
+    while ((wv + 1) * wv / 2 <= i) ++wv;
+    p = s_comp[i - wv * (wv - 1) / 2];
+    q = s_comp[wv];
+  };
+  double wreg[3][12];
+#pragma unroll
+  for (int bi = 0; bi < 3; ++bi)
+#pragma unroll
+    for (int st = 0; st < 12; ++st) {
+      const int i = 16 * bi + mr, j = 4 * st + mk;
+      double v = 0.0;
+      if (i < S && j < S) {
+        int p, q, sa, sb;
+        slot_pair(i, p, q);
+        slot_pair(j, sa, sb);
+        if (p != sa && p != sb && q != sa && q != sb) {
+          int q4[4] = {p, q, sa, sb};
+#pragma unroll
+          for (int x = 1; x < 4; ++x)
+#pragma unroll
+            for (int y = x; y > 0; --y)
+              if (q4[y - 1] > q4[y]) {
+                const int t = q4[y];
+                q4[y] = q4[y - 1];
+                q4[y - 1] = t;
+              }
+          int O4 = 0;
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+            if (q4[x] == p || q4[x] == q) O4 |= 1 << x;
+          const int base = a.spin * kMaxQuads + quad_id(q4[0], q4[1], q4[2], q4[3]);
+          const uint32_t J = a.wJ[base] >> off;
+          v = flip(a.wF[(size_t)base * 16 + O4], __popc(J & (K | (1u << p) | (1u << q))));
+        }
+      }
+      wreg[bi][st] = v;
+    }
+  // staging pieces: LDS piece q = j * 256 + tid holds columns 2 col, 2 col + 1
+  // of slot row q / 33 (col = q % 33; col 32 pads)
+  int poff[kCorePer];
+#pragma unroll
+  for (int j = 0; j < kCorePer; ++j) {
+    const int q = j * 256 + tid;
+    const int row = q / (kCoreLd / 2), col = q - row * (kCoreLd / 2);
+    const bool act = q < kCorePieces && col < kCoreC / 2 && s_row[row] >= 0;
+    poff[j] = act ? (int)((int64_t)s_row[row] * a.ld + 2 * col) : -1;
+  }
+  const uint32_t buf0 = lds_addr(smem), buf1 = buf0 + kCoreBuf;
+  // columns [k0, k0 + kn) of the slot rows through registers, zeros past kn
+  // and on rows without a slot
+  auto stage_regs = [&](uint32_t buf, int k0, int kn) {
+#pragma unroll
+    for (int j = 0; j < kCorePer; ++j) {
+      const int q = j * 256 + tid;
+      const int row = q / (kCoreLd / 2), col = q - row * (kCoreLd / 2);
+      if (q < kCorePieces && col < kCoreC / 2) {
+        f64x2 v = {0.0, 0.0};
+        if (s_row[row] >= 0) {
+          const double* src = a.in + (int64_t)s_row[row] * a.ld + k0;
+          if (2 * col < kn) v.x = src[2 * col];
+          if (2 * col + 1 < kn) v.y = src[2 * col + 1];
+        }
+        *(__attribute__((address_space(3))) f64x2*)(uintptr_t)(buf + (uint32_t)q * 16u) = v;
+      }
+    }
+  };
+  auto issue = [&](uint32_t buf, int k0) {
+#pragma unroll
+    for (int j = 0; j < kCorePer; ++j) {
+      const int base = j * 256 + w * 64;  // wave-uniform first piece
+      if (base < kCorePieces) {
+        const uint32_t dst = (uint32_t)__builtin_amdgcn_readfirstlane(buf + (uint32_t)base * 16u);
+        if (poff[j] >= 0) dma16(dst, a.in + poff[j] + k0);
+      }
+    }
+  };
+  f64x4 acc[3];
+  auto compute = [&](uint32_t buf) {
+#pragma unroll
+    for (int bi = 0; bi < 3; ++bi) acc[bi] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < 12; ++st) {
+      const double bv = lds_load<double>(buf + (uint32_t)((4 * st + mk) * kCoreLd + 16 * w + mr) * 8u);
+#pragma unroll
+      for (int bi = 0; bi < 3; ++bi) acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(wreg[bi][st], bv, acc[bi], 0, 0, 0);
+    }
+  };
+  // Y rows of the chunk at column k0 (kn valid columns)
+  auto store = [&](int k0, int kn) {
+    const int cc = 16 * w + mr;
+    if (cc < kn) {
+#pragma unroll
+      for (int bi = 0; bi < 3; ++bi)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = 16 * bi + mk + 4 * e;
+          if (i < S) a.Y[(core * S + i) * a.ldy + (k0 - a.c0) + cc] = acc[bi][e];
+        }
+    }
+  };
+  const int nfull = a.dma ? a.nc / kCoreC : 0;
+  // every piece of both buffers cleared once: rows without a slot and pad
+  // columns stay zero under the direct copies (their W columns are zero)
+  stage_regs(buf0, 0, 0);
+  stage_regs(buf1, 0, 0);
+  __syncthreads();
+  if (nfull > 0) {
+    issue(buf0, a.c0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  }
+  for (int ch = 0; ch < nfull; ++ch) {
+    const uint32_t cur = (ch & 1) ? buf1 : buf0, nxt = (ch & 1) ? buf0 : buf1;
+    if (ch + 1 < nfull) issue(nxt, a.c0 + (ch + 1) * kCoreC);
+    // chunk ch - 1's rows of Y, stored here so that they and the copy are
+    // in flight during this chunk's products
+    if (ch > 0) store(a.c0 + (ch - 1) * kCoreC, kCoreC);
+    compute(cur);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();  // chunk ch + 1 copied by every wave; chunk ch's reads done
+  }
+  if (nfull > 0) store(a.c0 + (nfull - 1) * kCoreC, kCoreC);
+  for (int k0 = a.c0 + nfull * kCoreC; k0 < a.c0 + a.nc; k0 += kCoreC) {
+    const int kn = min(kCoreC, a.c0 + a.nc - k0);
+    stage_regs(buf0, k0, kn);
+    __syncthreads();
+    compute(buf0);
+    store(k0, kn);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------- grouped same-spin rows
@@ -1085,6 +1324,7 @@ __global__ void k_generic(GenericArgs a) {
 
 
 static int g_support_skip = 1;  // process-wide: restrict H psi to psi's row and column support
+static int g_ss_cores = 1;      // process-wide: FP64 same-spin doubles through the cores (where built)
 static int g_ss_groups = 2;     // process-wide: FP64 same-spin pass over grouped lists with this many
                                 // 64-column tiles per four-wave workgroup (1, 2 or 4); 0: per-row lists
 
@@ -1173,6 +1413,92 @@ static hyp_status build_same_spin(Ham* Hm, HamWork* W, hipStream_t st) {
   return HYP_OK;
 }
 
+// Tables of the core path of the same-spin doubles (both spins) and the Y
+// band buffer: the slot table and core masks of each string space, each
+// row's C(N, 2) Y offsets (its cores in a fixed order: pairs a < b of its
+// occupied orbitals, b ascending, then a), nonzero-core flags, and the band
+// width, chosen so that one band of Y (ncore * S rows) takes at most
+// kCoreYBytes.  Not built (the grouped lists serve) where a core has more
+// than 48 slots.
+constexpr size_t kCoreYBytes = size_t(4) << 30;
+
+static hyp_status build_core_path(Ham* Hm, HamWork* W, hipStream_t st) {
+  Sector* S = Hm->sec;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int N = sp == 0 ? S->na : S->nb;
+    if (N >= 2 && S->M - N >= 2 && core_space(S->M, N).S > 48) return HYP_OK;
+  }
+  size_t ybytes = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int N = sp == 0 ? S->na : S->nb;
+    const int nrow = (int)(sp == 0 ? S->da : S->db), ncol = (int)(sp == 0 ? S->db : S->da);
+    const RankTables& R = sp == 0 ? S->h_arank : S->h_brank;
+    const std::vector<uint32_t>& str = sp == 0 ? S->h_astr : S->h_bstr;
+    W->k_nuse[sp] = 1 + N * (S->M - N);
+    const CoreSpace cs = core_space(S->M, N);
+    W->k_band[sp] = ncol;
+    if (cs.ncore == 0) continue;  // no same-spin double
+    std::vector<int> rows;
+    std::vector<uint32_t> masks;
+    hyp_status r = core_tables_host(S->M, N, R, rows, masks);
+    if (r != HYP_OK) return r;
+    const int npair = N * (N - 1) / 2;
+    std::vector<int> yoff((size_t)nrow * npair);
+    // colex rank of an (N - 2)-subset: sum over its sorted orbitals o_t of C(o_t, t + 1)
+    auto binom = [](int n, int k) -> int64_t {
+      if (k < 0 || n < k) return 0;
+      int64_t v = 1;
+      for (int i = 1; i <= k; ++i) v = v * (n - k + i) / i;
+      return v;
+    };
+    for (int row = 0; row < nrow; ++row) {
+      const uint32_t sv = str[(size_t)row];
+      int occ[16], no = 0;
+      for (int o = 0; o < S->M; ++o)
+        if (sv >> o & 1u) occ[no++] = o;
+      int m = 0;
+      for (int bi = 1; bi < no; ++bi)
+        for (int ai = 0; ai < bi; ++ai) {
+          const int oa = occ[ai], ob = occ[bi];
+          const uint32_t K = sv & ~(1u << oa) & ~(1u << ob);
+          int64_t crank = 0;
+          int t = 0;
+          for (int o = 0; o < S->M; ++o)
+            if (K >> o & 1u) crank += binom(o, ++t);
+          int u = -1, wv = -1, c = 0;
+          for (int o = 0; o < S->M; ++o)
+            if (!(K >> o & 1u)) {
+              if (o == oa) u = c;
+              if (o == ob) wv = c;
+              ++c;
+            }
+          yoff[(size_t)row * npair + m++] = (int)(crank * cs.S + wv * (wv - 1) / 2 + u);
+        }
+    }
+    W->k_ncore[sp] = (int)cs.ncore;
+    W->k_S[sp] = cs.S;
+    W->k_npair[sp] = npair;
+    HYP_HIP(hipMalloc(&W->k_rows[sp], rows.size() * sizeof(int)));
+    HYP_HIP(hipMalloc(&W->k_mask[sp], masks.size() * sizeof(uint32_t)));
+    HYP_HIP(hipMalloc(&W->k_yoff[sp], yoff.size() * sizeof(int)));
+    HYP_HIP(hipMalloc(&W->k_cnz[sp], (size_t)cs.ncore * sizeof(int)));
+    HYP_HIP(hipMemcpy(W->k_rows[sp], rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice));
+    HYP_HIP(hipMemcpy(W->k_mask[sp], masks.data(), masks.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HYP_HIP(hipMemcpy(W->k_yoff[sp], yoff.data(), yoff.size() * sizeof(int), hipMemcpyHostToDevice));
+    // bands: multiples of 64 columns, one band of Y within kCoreYBytes
+    const size_t yrow = (size_t)cs.ncore * cs.S * sizeof(double);
+    const int64_t maxc = std::max<int64_t>(64, (int64_t)(kCoreYBytes / yrow) / 64 * 64);
+    const int nband = (int)((ncol + maxc - 1) / maxc);
+    const int bw = (int)(((ncol + nband - 1) / nband + 63) / 64 * 64);
+    W->k_band[sp] = bw;
+    ybytes = std::max(ybytes, yrow * (size_t)bw);
+  }
+  (void)st;
+  if (ybytes > 0) HYP_HIP(hipMalloc(&W->k_Y, ybytes));
+  W->k_ok = true;
+  return HYP_OK;
+}
+
 // threads per mixed-kernel workgroup: one per alpha column, at most 1024 (a
 // 16-wave workgroup leaves 128 registers per lane; the kernel needs about
 // 105).  FP32 rows take half the LDS, so two 512-wide workgroups fit on a CU
@@ -1198,6 +1524,72 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   dim3 tg((da + 63) / 64, (db + 63) / 64);
   HYP_LAUNCH("k_transpose", k_transpose<T>, tg, dim3(256), 0, st, (const T*)psi, (T*)W->psi_t, db, da, nz_b,
              nz_a);
+  if (sizeof(T) == 8 && g_ss_cores && W->k_ok) {
+    // FP64: the singles and diagonal from the heads of the per-row lists,
+    // the doubles through the cores, one column band at a time
+    for (int sp = 0; sp < 2; ++sp) {
+      const int nrow = sp == 0 ? da : db, ncol = sp == 0 ? db : da;
+      const int nent = sp == 0 ? W->a_nent : W->b_nent;
+      const uint32_t* flags = sp == 0 ? nz_a : nz_b;
+      if (skip)
+        HYP_LAUNCH("k_ss_compact", k_ss_compact, dim3((unsigned)((nrow + 3) / 4)), dim3(256), 0, st,
+                   sp == 0 ? W->a_rank : W->b_rank, sp == 0 ? W->a_coef : W->b_coef, nent, W->k_nuse[sp], nrow,
+                   flags, sp == 0 ? W->ca_rank : W->cb_rank, sp == 0 ? W->ca_coef : W->cb_coef,
+                   sp == 0 ? W->ca_n : W->cb_n);
+      const void* in = sp == 0 ? (const void*)W->psi_t : psi;
+      SSApplyArgs sa{};
+      sa.in = in;
+      sa.out = sp == 0 ? W->part_a : W->part_b;
+      sa.list_rank = skip ? (sp == 0 ? W->ca_rank : W->cb_rank) : (sp == 0 ? W->a_rank : W->b_rank);
+      sa.list_coef = skip ? (sp == 0 ? W->ca_coef : W->cb_coef) : (sp == 0 ? W->a_coef : W->b_coef);
+      sa.list_n = skip ? (sp == 0 ? W->ca_n : W->cb_n) : nullptr;
+      sa.nent = nent;
+      sa.nuse = W->k_nuse[sp];
+      sa.nrow = nrow;
+      sa.ncol = ncol;
+      sa.nrb = (nrow + 3) / 4;
+      sa.Y = W->k_Y;
+      sa.ldy = W->k_band[sp];
+      sa.yoff = W->k_yoff[sp];
+      sa.npair = W->k_npair[sp];
+      sa.S = std::max(1, W->k_S[sp]);
+      sa.cnz = skip ? W->k_cnz[sp] : nullptr;
+      SSCoreArgs ca{};
+      ca.in = (const double*)in;
+      ca.ld = ncol;
+      ca.rows = W->k_rows[sp];
+      ca.masks = W->k_mask[sp];
+      ca.ncore = W->k_ncore[sp];
+      ca.S = W->k_S[sp];
+      ca.M = S->M;
+      ca.spin = sp;
+      ca.per_xcd = (ca.ncore + 7) / 8;
+      ca.wJ = Hm->dev.wJ;
+      ca.wF = Hm->dev.wF;
+      ca.Y = W->k_Y;
+      ca.ldy = W->k_band[sp];
+      ca.rflag = flags;
+      ca.cnz = W->k_cnz[sp];
+      const int bw = W->k_band[sp];
+      for (int c0 = 0; c0 < ncol; c0 += bw) {
+        const int nc = std::min(bw, ncol - c0);
+        if (ca.ncore > 0) {
+          ca.c0 = c0;
+          ca.nc = nc;
+          ca.dma = (((uintptr_t)in & 15u) == 0 && ncol % 2 == 0 && c0 % 2 == 0) ? 1 : 0;
+          HYP_HIP(hipFuncSetAttribute((const void*)k_ss_core, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)(2 * kCoreBuf)));
+          HYP_LAUNCH("k_ss_core", k_ss_core, dim3((unsigned)(8 * ca.per_xcd)), dim3(256), 2 * kCoreBuf, st, ca);
+        }
+        sa.c0 = c0;
+        sa.nc = nc;
+        sa.ntiles = (nc + 63) / 64;
+        const int64_t nblk = (int64_t)8 * ((sa.ntiles + 7) / 8) * sa.nrb;
+        HYP_LAUNCH("k_ss_apply", (k_ss_apply<T, true>), dim3((unsigned)nblk), dim3(256), 0, st, sa);
+      }
+    }
+    return run_mixed<T>(Hm, W, psi, sigma, nz_b, st);
+  }
   if (sizeof(T) == 8 && g_ss_groups != 0 && W->g_ok) {
     // FP64: grouped lists (support-restricted copies when skipping); FP32
     // storage keeps the per-row lists (measured: 35 against 29 ms at 32 qubits)
@@ -1233,24 +1625,27 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   if (skip) {
     // same-spin matrices restricted to source rows in the support
     HYP_LAUNCH("k_ss_compact", k_ss_compact, dim3((unsigned)((da + 3) / 4)), dim3(256), 0, st, W->a_rank,
-               W->a_coef, W->a_nent, da, nz_a, W->ca_rank, W->ca_coef, W->ca_n);
+               W->a_coef, W->a_nent, W->a_nent, da, nz_a, W->ca_rank, W->ca_coef, W->ca_n);
     HYP_LAUNCH("k_ss_compact", k_ss_compact, dim3((unsigned)((db + 3) / 4)), dim3(256), 0, st, W->b_rank,
-               W->b_coef, W->b_nent, db, nz_b, W->cb_rank, W->cb_coef, W->cb_n);
+               W->b_coef, W->b_nent, W->b_nent, db, nz_b, W->cb_rank, W->cb_coef, W->cb_n);
   }
   // alpha rows (over psi^T): rows = alpha strings, columns = beta strings
-  SSApplyArgs sa;
+  SSApplyArgs sa{};
   sa.in = W->psi_t;
   sa.out = W->part_a;
   sa.list_rank = skip ? W->ca_rank : W->a_rank;
   sa.list_coef = skip ? W->ca_coef : W->a_coef;
   sa.list_n = skip ? W->ca_n : nullptr;
   sa.nent = W->a_nent;
+  sa.nuse = W->a_nent;
   sa.nrow = da;
   sa.ncol = db;
+  sa.c0 = 0;
+  sa.nc = db;
   sa.ntiles = (db + 63) / 64;
   sa.nrb = (da + 3) / 4;
   int64_t nb_a = (int64_t)8 * ((sa.ntiles + 7) / 8) * sa.nrb;
-  HYP_LAUNCH("k_ss_apply", k_ss_apply<T>, dim3((unsigned)nb_a), dim3(256), 0, st, sa);
+  HYP_LAUNCH("k_ss_apply", (k_ss_apply<T, false>), dim3((unsigned)nb_a), dim3(256), 0, st, sa);
   // beta rows (over psi), the constant (identity) term folded into their diagonal
   sa.in = psi;
   sa.out = W->part_b;
@@ -1258,12 +1653,15 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
   sa.list_coef = skip ? W->cb_coef : W->b_coef;
   sa.list_n = skip ? W->cb_n : nullptr;
   sa.nent = W->b_nent;
+  sa.nuse = W->b_nent;
   sa.nrow = db;
   sa.ncol = da;
+  sa.c0 = 0;
+  sa.nc = da;
   sa.ntiles = (da + 63) / 64;
   sa.nrb = (db + 3) / 4;
   int64_t nb_b = (int64_t)8 * ((sa.ntiles + 7) / 8) * sa.nrb;
-  HYP_LAUNCH("k_ss_apply", k_ss_apply<T>, dim3((unsigned)nb_b), dim3(256), 0, st, sa);
+  HYP_LAUNCH("k_ss_apply", (k_ss_apply<T, false>), dim3((unsigned)nb_b), dim3(256), 0, st, sa);
   return run_mixed<T>(Hm, W, psi, sigma, nz_b, st);
 }
 
@@ -1645,6 +2043,7 @@ hyp_status hyp_build_hamiltonian(hyp_sector sh, const uint32_t* x_mask, const ui
     if (e == hipSuccess) e = hipMalloc(&hh->w.nz, sizeof(uint32_t) * (size_t)(S->da + S->db));
     if (e != hipSuccess) return cleanup_fail(e, "hyp_build_hamiltonian: workspace");
     hyp_status rb = build_same_spin(&H, &hh->w, st);
+    if (rb == HYP_OK) rb = build_core_path(&H, &hh->w, st);
     if (rb != HYP_OK) {
       hyp_ham_destroy(hh);
       return rb;
@@ -1700,6 +2099,13 @@ hyp_status hyp_ham_destroy(hyp_ham hh) {
     (void)hipFree(hh->w.gc_coef[sp]);
     (void)hipFree(hh->w.gc_cnt[sp]);
   }
+  for (int sp = 0; sp < 2; ++sp) {
+    (void)hipFree(hh->w.k_rows[sp]);
+    (void)hipFree(hh->w.k_mask[sp]);
+    (void)hipFree(hh->w.k_yoff[sp]);
+    (void)hipFree(hh->w.k_cnz[sp]);
+  }
+  (void)hipFree(hh->w.k_Y);
   (void)hipFree(hh->w.c_bpos);
   (void)hipFree(hh->w.c_blist);
   (void)hipFree(hh->w.c_nb);
@@ -1762,6 +2168,12 @@ hyp_status hyp_set_same_spin_groups(int tiles) {
   if (tiles != 0 && tiles != 1 && tiles != 2 && tiles != 4)
     return fail(HYP_ERR_ARG, "hyp_set_same_spin_groups: tiles must be 0, 1, 2 or 4");
   g_ss_groups = tiles;
+  return HYP_OK;
+}
+
+hyp_status hyp_set_same_spin_cores(int on) {
+  if (on != 0 && on != 1) return fail(HYP_ERR_ARG, "hyp_set_same_spin_cores: on must be 0 or 1");
+  g_ss_cores = on;
   return HYP_OK;
 }
 

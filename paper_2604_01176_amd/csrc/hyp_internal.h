@@ -281,6 +281,23 @@ struct HamWork {
   double* gc_coef[2] = {nullptr, nullptr};
   int* gc_cnt[2] = {nullptr, nullptr};
   bool g_ok = false;
+  // same-spin doubles through cores (FP64; hamiltonian.hip): per spin [0]
+  // alpha rows, [1] beta rows: cores, slots per core, singles-and-diagonal
+  // entries at the head of each per-row list, cores per row (C(N, 2)), the
+  // slot table [ncore][S], core masks, each row's Y offsets core * S + slot
+  // [nrow][npair], the nonzero-core flags of support skipping, and the band
+  // width (columns per launch); Y holds one band of the per-core products
+  int k_ncore[2] = {0, 0};
+  int k_S[2] = {0, 0};
+  int k_nuse[2] = {0, 0};
+  int k_npair[2] = {0, 0};
+  int* k_rows[2] = {nullptr, nullptr};
+  uint32_t* k_mask[2] = {nullptr, nullptr};
+  int* k_yoff[2] = {nullptr, nullptr};
+  int* k_cnz[2] = {nullptr, nullptr};
+  int k_band[2] = {0, 0};
+  double* k_Y = nullptr;
+  bool k_ok = false;
   // compact staging tables of the mixed pass (768-column chunks); c_ok when
   // every chunk fits a buffer
   uint16_t* c_bpos = nullptr;
@@ -369,5 +386,8 @@ struct CoreGramCall {
   double* G;                  // core_gram_doubles(M, N) doubles
 };
 hyp_status launch_core_gram(const CoreGramCall& g, hipStream_t st);
+// Host slot table rows[core][slot] (string ranks) and core masks of (M, N).
+hyp_status core_tables_host(int M, int N, const RankTables& R, std::vector<int>& rows,
+                            std::vector<uint32_t>& masks);
 
 }  // namespace hyp

@@ -1,9 +1,12 @@
-"""The FP64 same-spin pass over grouped lists (8 consecutive output strings
-per wave sharing their source loads) against the oracle and against the
-per-row lists, with support skipping on and off: sectors whose string counts
-are and are not multiples of the group size, empty and full spins, and the
-32-qubit workload on its sparse input (every entry) and on sampled rows of
-the dense state."""
+"""The FP64 same-spin pass, its three forms against the oracle and against
+each other, with support skipping on and off: the per-row lists, the grouped
+lists (8 consecutive output strings per wave sharing their source loads),
+and the doubles through the strings' cores (per-core dense products on the
+matrix cores, each row adding its cores' rows), on sectors whose string
+counts are and are not multiples of the group size, empty and full spins,
+spins without doubles, cores with more than 48 slots (no core tables: the
+grouped lists serve), and the 32-qubit workload on its sparse input (every
+entry) and on sampled rows of the dense state."""
 import numpy as np
 import pytest
 
@@ -41,6 +44,7 @@ def test_grouped_equals_oracle_and_per_row(hyp, M, na, nb, skip):
     try:
         for psi in states:
             d = torch.from_numpy(psi).cuda()
+            hyp.set_same_spin_cores(False)
             hyp.set_same_spin_groups(False)
             per_row = H.apply(d).cpu().numpy()
             ref = oracle.apply_h(M, na, nb, x, z, c, psi)
@@ -50,9 +54,37 @@ def test_grouped_equals_oracle_and_per_row(hyp, M, na, nb, skip):
                 got = H.apply(d).cpu().numpy()
                 assert np.linalg.norm(got - ref) <= 1e-12 * nrm, tiles
                 assert np.linalg.norm(got - per_row) <= 1e-14 * nrm, tiles
+            # the doubles through the cores
+            hyp.set_same_spin_cores(True)
+            got = H.apply(d).cpu().numpy()
+            assert np.linalg.norm(got - ref) <= 1e-12 * nrm
+            assert np.linalg.norm(got - per_row) <= 1e-14 * nrm
+            assert np.abs(got - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300)
+            assert torch.equal(H.apply(d), H.apply(d))  # fixed summation order
     finally:
+        hyp.set_same_spin_cores(True)
         hyp.set_same_spin_groups(True)
         hyp.set_support_skip(True)
+
+
+@pytest.mark.parametrize("M,na,nb", [(12, 2, 3), (11, 2, 9)])
+def test_cores_beyond_48_slots_fall_back(hyp, M, na, nb):
+    """An alpha space with 2 electrons in 12 (11) orbitals has cores of
+    C(12, 2) = 66 (55) slots: no core tables, the grouped lists serve, and
+    switching the core path on or off changes nothing."""
+    S, H, (x, z, c) = _ham(hyp, M, na, nb, 900 + M)
+    psi = synth.random_state(S.dim, 11)
+    d = torch.from_numpy(psi).cuda()
+    ref = oracle.apply_h(M, na, nb, x, z, c, psi)
+    try:
+        hyp.set_same_spin_cores(True)
+        a = H.apply(d)
+        hyp.set_same_spin_cores(False)
+        b = H.apply(d)
+    finally:
+        hyp.set_same_spin_cores(True)
+    assert torch.equal(a, b)
+    assert np.linalg.norm(a.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
 def test_grouped_32q(hyp):
@@ -64,31 +96,42 @@ def test_grouped_32q(hyp):
     ref = oracle.apply_h_sparse(w.n_orb, w.n_alpha, w.n_beta, x, z, c, idx, val)
     d = torch.zeros(S.dim, dtype=torch.float64, device="cuda")
     d[torch.from_numpy(idx).cuda()] = torch.from_numpy(val).cuda()
-    for skip in (True, False):
-        hyp.set_support_skip(skip)
-        try:
-            print(f"[same-spin] 32 qubits, sparse input, skipping {skip}", flush=True)
-            got = H.apply(d).cpu().numpy()
-        finally:
-            hyp.set_support_skip(True)
-        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
-        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
-        assert np.count_nonzero(got[ref == 0.0]) == 0
-    # dense benchmark state: grouped against per-row on every entry, the
-    # oracle on sampled rows (first and last rows of groups and tiles)
+    for cores in (True, False):
+        for skip in (True, False):
+            hyp.set_support_skip(skip)
+            hyp.set_same_spin_cores(cores)
+            try:
+                print(f"[same-spin] 32 qubits, sparse input, cores {cores}, skipping {skip}", flush=True)
+                got = H.apply(d).cpu().numpy()
+            finally:
+                hyp.set_support_skip(True)
+                hyp.set_same_spin_cores(True)
+            assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+            assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+            assert np.count_nonzero(got[ref == 0.0]) == 0
+    # dense benchmark state: cores and grouped lists against the per-row
+    # lists on every entry, the oracle on sampled rows (first and last rows
+    # of groups, tiles and column bands)
     psi_h = synth.random_state(S.dim, 7)
     dp = torch.from_numpy(psi_h).cuda()
-    got = H.apply(dp)
-    hyp.set_same_spin_groups(False)
     try:
+        hyp.set_same_spin_cores(True)
+        got_c = H.apply(dp)
+        hyp.set_same_spin_cores(False)
+        got = H.apply(dp)
+        hyp.set_same_spin_groups(False)
         per_row = H.apply(dp)
     finally:
         hyp.set_same_spin_groups(True)
-    rel = (torch.linalg.norm(got - per_row) / torch.linalg.norm(per_row)).item()
-    print(f"[same-spin] dense 32 qubits: grouped vs per-row relative difference {rel:.2e}", flush=True)
-    assert rel <= 1e-14
+        hyp.set_same_spin_cores(True)
+    for name, g in (("grouped", got), ("cores", got_c)):
+        rel = (torch.linalg.norm(g - per_row) / torch.linalg.norm(per_row)).item()
+        print(f"[same-spin] dense 32 qubits: {name} vs per-row relative difference {rel:.2e}", flush=True)
+        assert rel <= 1e-14
     da = S.da
-    rows = np.array([0, 7, 8, 255, 256, da - 1, da, 8 * da + 63, 12864 * da + 12865, S.dim - 1], dtype=np.int64)
+    rows = np.array([0, 7, 8, 255, 256, 1471, 1472, da - 1, da, 8 * da + 63, 8 * da + 1472, 12864 * da + 12865,
+                     S.dim - 1], dtype=np.int64)
     ref_rows = oracle.apply_h(w.n_orb, w.n_alpha, w.n_beta, x, z, c, psi_h, out_idx=rows)
-    g_rows = got[torch.from_numpy(rows).cuda()].cpu().numpy()
-    assert np.abs(g_rows - ref_rows).max() <= 1e-12 * np.abs(ref_rows).max()
+    for g in (got, got_c):
+        g_rows = g[torch.from_numpy(rows).cuda()].cpu().numpy()
+        assert np.abs(g_rows - ref_rows).max() <= 1e-12 * np.abs(ref_rows).max()
