@@ -90,6 +90,7 @@ def roofline(name, ms, m):
 
 # source file of each kernel whose counters are committed
 KERNEL_SOURCES = {"k_mixed": "hamiltonian.hip", "k_ss_apply": "hamiltonian.hip", "k_transpose": "hamiltonian.hip",
+                  "k_ss_core": "hamiltonian.hip",
                   "k_ssg_compact": "hamiltonian.hip", "k_tdens_rows": "sweep.hip", "k_tdens_rows_final": "sweep.hip",
                   "k_gram_grad": "sweep.hip", "k_core_gram_a": "core_gram.hip", "k_core_gram_b": "core_gram.hip",
                   "k_gram_transpose": "core_gram.hip", "k_rotate": "pool.hip", "k_dot_partial_f64": "sector.hip"}
@@ -316,10 +317,13 @@ def main():
     # H psi's measured HBM bytes (committed counter table) over its time: the
     # DRAM-counter fraction of the HBM peak (null when a kernel's table entry
     # is missing or stale)
-    hb = [measured_traffic(w.name, k) for k in ("k_mixed", "k_ss_apply", "k_transpose")]
+    # (bytes per launch of each H psi kernel x its launches per product; the
+    # same-spin pass runs in column bands, several launches per product)
+    hk = [k for k in ("k_mixed", "k_ss_core", "k_ss_apply", "k_transpose") if k in prof]
+    hb = {k: measured_traffic(w.name, k) for k in hk}
     hpsi_hbm = None
-    if all(v is not None for v in hb):
-        bytes_per_hpsi = hb[0] + 2 * hb[1] + hb[2]
+    if hk and all(v is not None for v in hb.values()):
+        bytes_per_hpsi = sum(hb[k] * prof[k][1] / args.steps for k in hk)
         hpsi_hbm = {"bytes": round(bytes_per_hpsi), "gbs": round(bytes_per_hpsi / (hpsi_ms * 1e-3) / 1e9, 1),
                     "frac": round(bytes_per_hpsi / (hpsi_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     cpu = None
