@@ -283,6 +283,8 @@ struct SSApplyArgs {
   const int* yoff;
   int npair, S;
   const int* cnz;
+  const int* row_any;       // support skipping: 0 where the row has nothing (written as zeros)
+  const int* sel;           // support skipping: run only where *sel == 1 (the core path is selected)
 };
 
 // out[r][c] = sum_e coef[r][e] in[rank[r][e]][c].  Each wave owns one output
@@ -306,6 +308,11 @@ __global__ void __launch_bounds__(256) k_ss_apply(SSApplyArgs a) {
   const int* __restrict__ rk = a.list_rank + (int64_t)row * a.nent;
   const double* __restrict__ cf = a.list_coef + (int64_t)row * a.nent;
   const T* __restrict__ in = (const T*)a.in;
+  if (kY && a.sel && *a.sel != 1) return;
+  if (kY && a.row_any && __builtin_amdgcn_readfirstlane(a.row_any[row]) == 0) {
+    if (live) a.out[(int64_t)row * a.ncol + col] = 0.0;
+    return;
+  }
   const int nent = a.list_n ? __builtin_amdgcn_readfirstlane(a.list_n[row]) : a.nuse;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   int e = 0;
@@ -385,9 +392,51 @@ struct SSCoreArgs {
   int c0, nc;              // the band's columns
   double* Y;               // [ncore][S][ldy]
   int64_t ldy;
-  const uint32_t* rflag;   // support skipping: flags of the source rows (null: every row)
-  int* cnz;                // [ncore] 1 if some source row of the core is flagged
+  const int* cnz;          // support skipping: [ncore] 0 for a core with no row in the support (null: every core)
+  const int* sel;          // support skipping: run only where *sel == 1
 };
+
+// Support skipping, per spin and product: the core path where at least a
+// quarter of the source rows are in psi's support, else the grouped lists
+// (which then compact to few sources per group while every core still forms
+// its whole band).  One workgroup: *sel = (4 * flagged rows >= nrow).
+__global__ void __launch_bounds__(1024) k_ss_select(const uint32_t* __restrict__ flags, int nrow,
+                                                    int* __restrict__ sel) {
+  __shared__ int s_n[16];
+  int n = 0;
+  for (int r = threadIdx.x; r < nrow; r += blockDim.x) n += flags[r] != 0u ? 1 : 0;
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_down(n, o, 64);
+  if ((threadIdx.x & 63) == 0) s_n[threadIdx.x >> 6] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_n[w];
+    *sel = 4 * t >= nrow ? 1 : 0;
+  }
+}
+
+// Support skipping, once per spin and product: cnz[core] = 1 if some source
+// row of the core is in psi's support (one thread per core) ...
+__global__ void __launch_bounds__(256) k_core_flags(const int* __restrict__ rows, int ncore, int S,
+                                                    const uint32_t* __restrict__ rflag, int* __restrict__ cnz) {
+  const int core = blockIdx.x * blockDim.x + threadIdx.x;
+  if (core >= ncore) return;
+  int any = 0;
+  for (int j = 0; j < S && !any; ++j) any = rflag[rows[(int64_t)core * S + j]] != 0u;
+  cnz[core] = any;
+}
+
+// ... and row_any[r] = 1 if row r keeps a single or diagonal entry or one
+// of its cores is flagged (one thread per row).
+__global__ void __launch_bounds__(256) k_row_any(const int* __restrict__ yoff, int npair, int S,
+                                                 const int* __restrict__ cnz, const int* __restrict__ list_n,
+                                                 int nrow, int* __restrict__ row_any) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nrow) return;
+  int any = list_n[row] > 0;
+  for (int m = 0; m < npair && !any; ++m) any = cnz[yoff[(int64_t)row * npair + m] / S] != 0;
+  row_any[row] = any;
+}
 constexpr int kCoreC = 64;                          // columns per staged chunk
 constexpr int kCoreLd = kCoreC + 2;                 // LDS row stride in doubles
 constexpr int kCorePieces = 48 * (kCoreLd / 2);     // 16-byte pieces per buffer
@@ -400,11 +449,14 @@ __global__ void __launch_bounds__(256) k_ss_core(SSCoreArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_row[48];
   __shared__ int s_comp[16];
-  __shared__ int s_any;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t b = blockIdx.x;
   const int64_t core = (b & 7) * a.per_xcd + (b >> 3);
   if (core >= a.ncore) return;
+  // support skipping: a core none of whose rows is in psi's support (flags
+  // of k_core_flags) has a zero product; its gatherers skip it
+  if (a.sel && *a.sel != 1) return;
+  if (a.cnz && a.cnz[core] == 0) return;
   const int S = a.S;
   const uint32_t K = a.masks[core];
   if (tid < 48) s_row[tid] = tid < S ? a.rows[core * S + tid] : -1;
@@ -412,13 +464,8 @@ __global__ void __launch_bounds__(256) k_ss_core(SSCoreArgs a) {
     int nf = 0;
     for (int o = 0; o < a.M; ++o)
       if (!(K >> o & 1u)) s_comp[nf++] = o;
-    s_any = a.rflag ? 0 : 1;
   }
   __syncthreads();
-  if (a.rflag && tid < S && a.rflag[s_row[tid]] != 0u) s_any = 1;
-  __syncthreads();
-  if (a.rflag && tid == 0) a.cnz[core] = s_any;
-  if (!s_any) return;  // no source row in the support: the rows' gatherers skip this core
   // W_K as MFMA A operands
   const int mr = lane & 15, mk = lane >> 4;
   const int off = a.spin * a.M;
@@ -664,6 +711,7 @@ struct SSGArgs {
   const int* cnt;           // per-group list lengths (support-restricted lists), or null: off differences
   int nrow, ncol, ngroups;
   int ntq;                  // tile groups of kW 64-column tiles (one tile per wave)
+  const int* sel;           // with support skipping beside the core path: run only where *sel == 0
 };
 
 // out[g*kSSG + j][c] = sum_u ucoef[u][j] in[urank[u]][c] over group g's
@@ -675,6 +723,7 @@ struct SSGArgs {
 // input stays in that XCD's L2 as long as it can.
 template <typename T, int kW>
 __global__ void __launch_bounds__(256) k_ss_apply_g(SSGArgs a) {
+  if (a.sel && *a.sel != 0) return;
   constexpr int kGq = 4 / kW;  // groups per workgroup
   const int b = blockIdx.x;
   const int xcd = b & 7, j0 = b >> 3;
@@ -1437,6 +1486,7 @@ static hyp_status build_core_path(Ham* Hm, HamWork* W, hipStream_t st) {
     W->k_nuse[sp] = 1 + N * (S->M - N);
     const CoreSpace cs = core_space(S->M, N);
     W->k_band[sp] = ncol;
+    HYP_HIP(hipMalloc(&W->k_rowany[sp], (size_t)std::max(1, nrow) * sizeof(int)));
     if (cs.ncore == 0) continue;  // no same-spin double
     std::vector<int> rows;
     std::vector<uint32_t> masks;
@@ -1495,6 +1545,7 @@ static hyp_status build_core_path(Ham* Hm, HamWork* W, hipStream_t st) {
   }
   (void)st;
   if (ybytes > 0) HYP_HIP(hipMalloc(&W->k_Y, ybytes));
+  HYP_HIP(hipMalloc(&W->k_sel, 2 * sizeof(int)));
   W->k_ok = true;
   return HYP_OK;
 }
@@ -1531,11 +1582,26 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
       const int nrow = sp == 0 ? da : db, ncol = sp == 0 ? db : da;
       const int nent = sp == 0 ? W->a_nent : W->b_nent;
       const uint32_t* flags = sp == 0 ? nz_a : nz_b;
-      if (skip)
+      if (skip) {
         HYP_LAUNCH("k_ss_compact", k_ss_compact, dim3((unsigned)((nrow + 3) / 4)), dim3(256), 0, st,
                    sp == 0 ? W->a_rank : W->b_rank, sp == 0 ? W->a_coef : W->b_coef, nent, W->k_nuse[sp], nrow,
                    flags, sp == 0 ? W->ca_rank : W->cb_rank, sp == 0 ? W->ca_coef : W->cb_coef,
                    sp == 0 ? W->ca_n : W->cb_n);
+        if (W->k_ncore[sp] > 0)
+          HYP_LAUNCH("k_core_flags", k_core_flags, dim3((unsigned)((W->k_ncore[sp] + 255) / 256)), dim3(256), 0, st,
+                     W->k_rows[sp], W->k_ncore[sp], W->k_S[sp], flags, W->k_cnz[sp]);
+        HYP_LAUNCH("k_row_any", k_row_any, dim3((unsigned)((nrow + 255) / 256)), dim3(256), 0, st, W->k_yoff[sp],
+                   W->k_npair[sp], std::max(1, W->k_S[sp]), W->k_cnz[sp], sp == 0 ? W->ca_n : W->cb_n, nrow,
+                   W->k_rowany[sp]);
+        if (W->g_ok) {
+          // a sparse support takes the grouped lists (selected on the device)
+          HYP_LAUNCH("k_ss_select", k_ss_select, dim3(1), dim3(1024), 0, st, flags, nrow, W->k_sel + sp);
+          HYP_LAUNCH("k_ssg_compact", k_ssg_compact, dim3((unsigned)((W->g_n[sp] + 3) / 4)), dim3(256), 0, st,
+                     W->g_off[sp], W->g_rank[sp], W->g_coef[sp], W->g_n[sp], flags, W->gc_rank[sp], W->gc_coef[sp],
+                     W->gc_cnt[sp]);
+        }
+      }
+      const int* sel = (skip && W->g_ok) ? W->k_sel + sp : nullptr;
       const void* in = sp == 0 ? (const void*)W->psi_t : psi;
       SSApplyArgs sa{};
       sa.in = in;
@@ -1554,6 +1620,8 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
       sa.npair = W->k_npair[sp];
       sa.S = std::max(1, W->k_S[sp]);
       sa.cnz = skip ? W->k_cnz[sp] : nullptr;
+      sa.row_any = skip ? W->k_rowany[sp] : nullptr;
+      sa.sel = sel;
       SSCoreArgs ca{};
       ca.in = (const double*)in;
       ca.ld = ncol;
@@ -1568,8 +1636,8 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
       ca.wF = Hm->dev.wF;
       ca.Y = W->k_Y;
       ca.ldy = W->k_band[sp];
-      ca.rflag = flags;
-      ca.cnz = W->k_cnz[sp];
+      ca.cnz = skip ? W->k_cnz[sp] : nullptr;
+      ca.sel = sel;
       const int bw = W->k_band[sp];
       for (int c0 = 0; c0 < ncol; c0 += bw) {
         const int nc = std::min(bw, ncol - c0);
@@ -1586,6 +1654,22 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
         sa.ntiles = (nc + 63) / 64;
         const int64_t nblk = (int64_t)8 * ((sa.ntiles + 7) / 8) * sa.nrb;
         HYP_LAUNCH("k_ss_apply", (k_ss_apply<T, true>), dim3((unsigned)nblk), dim3(256), 0, st, sa);
+      }
+      if (sel) {
+        SSGArgs ga;
+        ga.in = in;
+        ga.out = sp == 0 ? W->part_a : W->part_b;
+        ga.off = W->g_off[sp];
+        ga.urank = W->gc_rank[sp];
+        ga.ucoef = W->gc_coef[sp];
+        ga.cnt = W->gc_cnt[sp];
+        ga.nrow = nrow;
+        ga.ncol = ncol;
+        ga.ngroups = W->g_n[sp];
+        ga.sel = sel;
+        ga.ntq = (ncol + 127) / 128;
+        const int64_t nblk = (int64_t)8 * ((ga.ntq + 7) / 8) * ((ga.ngroups + 1) / 2);
+        HYP_LAUNCH("k_ss_apply", (k_ss_apply_g<T, 2>), dim3((unsigned)nblk), dim3(256), 0, st, ga);
       }
     }
     return run_mixed<T>(Hm, W, psi, sigma, nz_b, st);
@@ -1609,6 +1693,7 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
       ga.nrow = sp == 0 ? da : db;
       ga.ncol = sp == 0 ? db : da;
       ga.ngroups = ng;
+      ga.sel = nullptr;
       const int kw = g_ss_groups;  // tiles per workgroup: 1, 2 or 4
       ga.ntq = (ga.ncol + 64 * kw - 1) / (64 * kw);
       const int ngq = (ng + 4 / kw - 1) / (4 / kw);
@@ -2104,8 +2189,10 @@ hyp_status hyp_ham_destroy(hyp_ham hh) {
     (void)hipFree(hh->w.k_mask[sp]);
     (void)hipFree(hh->w.k_yoff[sp]);
     (void)hipFree(hh->w.k_cnz[sp]);
+    (void)hipFree(hh->w.k_rowany[sp]);
   }
   (void)hipFree(hh->w.k_Y);
+  (void)hipFree(hh->w.k_sel);
   (void)hipFree(hh->w.c_bpos);
   (void)hipFree(hh->w.c_blist);
   (void)hipFree(hh->w.c_nb);

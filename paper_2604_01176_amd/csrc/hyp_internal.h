@@ -295,6 +295,8 @@ struct HamWork {
   uint32_t* k_mask[2] = {nullptr, nullptr};
   int* k_yoff[2] = {nullptr, nullptr};
   int* k_cnz[2] = {nullptr, nullptr};
+  int* k_rowany[2] = {nullptr, nullptr};  // support skipping: row has a kept single or a nonzero core
+  int* k_sel = nullptr;                   // support skipping, per spin: 1 core path, 0 grouped lists
   int k_band[2] = {0, 0};
   double* k_Y = nullptr;
   bool k_ok = false;
