@@ -195,8 +195,12 @@ hyp_status hyp_set_same_spin_groups(int tiles);
  * where the tables were built with the Hamiltonian (every core of both spins
  * with at most 48 slots; a band of Y takes at most 4 GiB of device memory,
  * allocated with the Hamiltonian); 0 the grouped or per-row lists of
- * hyp_set_same_spin_groups.  Equal results up to summation order.
- * Process-wide; HYP_ERR_ARG unless on is 0 or 1. */
+ * hyp_set_same_spin_groups.  With support skipping (hyp_set_support_skip)
+ * the choice is made per spin on the device: the core path where at least a
+ * quarter of the spin's strings carry amplitude, the grouped lists below
+ * that (the other path's kernels exit at once; no host synchronisation).
+ * Equal results up to summation order.  Process-wide; HYP_ERR_ARG unless on
+ * is 0 or 1. */
 hyp_status hyp_set_same_spin_cores(int on);
 
 /* Materialised sector Hamiltonian in CSR form, the paper's storage of H
