@@ -191,17 +191,19 @@ hyp_status hyp_set_same_spin_groups(int tiles);
  * S x S product (S = C(M - N + 2, 2) slots) of the core's rows, Y_K = W_K
  * psi_K, formed on FP64 MFMA in column bands, and each output row adds its
  * C(N, 2) cores' rows of Y in a fixed order (deterministic) beside its
- * singles and diagonal, which keep the per-row lists.  on = 1 (default)
- * where the tables were built with the Hamiltonian (every core of both spins
- * with at most 48 slots; a band of Y takes at most 4 GiB of device memory,
- * allocated with the Hamiltonian); 0 the grouped or per-row lists of
- * hyp_set_same_spin_groups.  With support skipping (hyp_set_support_skip)
- * the choice is made per spin on the device: the core path where at least a
- * quarter of the spin's strings carry amplitude, the grouped lists below
- * that (the other path's kernels exit at once; no host synchronisation).
- * Equal results up to summation order.  Process-wide; HYP_ERR_ARG unless on
- * is 0 or 1. */
-hyp_status hyp_set_same_spin_cores(int on);
+ * singles and diagonal, which keep the per-row lists.  mode = 2 (default)
+ * takes it where the tables were built with the Hamiltonian (every core of
+ * both spins with at most 48 slots; a band of Y takes at most 4 GiB of
+ * device memory, allocated with the Hamiltonian) and the FP64 state vector
+ * exceeds 256 MiB, the size of the Infinity Cache, below which the grouped
+ * lists are faster; 1 wherever the tables were built; 0 never (the grouped
+ * or per-row lists of hyp_set_same_spin_groups).  With support skipping
+ * (hyp_set_support_skip) the core path's choice is then made per spin on
+ * the device: the core path where at least a quarter of the spin's strings
+ * carry amplitude, the grouped lists below that (the other path's kernels
+ * exit at once; no host synchronisation).  Equal results up to summation
+ * order.  Process-wide; HYP_ERR_ARG unless mode is 0, 1 or 2. */
+hyp_status hyp_set_same_spin_cores(int mode);
 
 /* Materialised sector Hamiltonian in CSR form, the paper's storage of H
  * ("Sparse State-Vector Emulation", Table 1 gives its size), kept as a

@@ -316,11 +316,13 @@ def set_same_spin_groups(tiles=2):
     check(_lib.load().hyp_set_same_spin_groups(t))
 
 
-def set_same_spin_cores(on: bool = True):
+def set_same_spin_cores(mode="auto"):
     """hyp_set_same_spin_cores: FP64 same-spin doubles as per-core dense
-    products on the matrix cores (default) or through the lists of
-    set_same_spin_groups."""
-    check(_lib.load().hyp_set_same_spin_cores(1 if on else 0))
+    products on the matrix cores: "auto" (default; where the FP64 state
+    exceeds the 256 MiB Infinity Cache), True (wherever built) or False
+    (the lists of set_same_spin_groups)."""
+    m = 2 if mode == "auto" else (1 if mode else 0)
+    check(_lib.load().hyp_set_same_spin_cores(m))
 
 
 def profile_enable(on: bool = True):

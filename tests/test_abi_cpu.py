@@ -49,3 +49,21 @@ def test_last_error_without_gpu():
     assert lib.hyp_sector_create(17, 1, 1, ctypes.byref(out)) == 2  # n_orb > 16 -> HYP_ERR_SECTOR
     assert b"n_orb" in lib.hyp_last_error()
     assert lib.hyp_sector_create(4, 5, 1, ctypes.byref(out)) == 2
+
+
+def test_switch_argument_checks_without_gpu():
+    """The process-wide switches validate their argument before any device
+    call (HYP_ERR_ARG = 1), and accept every documented value."""
+    lib = ctypes.CDLL(LIB)
+    cases = (("hyp_set_same_spin_cores", (0, 1, 2), (-1, 3), 2),
+             ("hyp_set_same_spin_groups", (0, 1, 2, 4), (-1, 3, 8), 2),
+             ("hyp_set_row_staging", (0, 1), (-1, 2), 0),
+             ("hyp_set_support_skip", (0, 1), (-1, 2), 1))
+    for name, good, bad, default in cases:
+        f = getattr(lib, name)
+        f.argtypes = [ctypes.c_int]
+        for v in bad:
+            assert f(v) == 1, (name, v)
+        for v in good:
+            assert f(v) == 0, (name, v)
+        assert f(default) == 0

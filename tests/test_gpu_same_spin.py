@@ -62,7 +62,7 @@ def test_grouped_equals_oracle_and_per_row(hyp, M, na, nb, skip):
             assert np.abs(got - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300)
             assert torch.equal(H.apply(d), H.apply(d))  # fixed summation order
     finally:
-        hyp.set_same_spin_cores(True)
+        hyp.set_same_spin_cores()
         hyp.set_same_spin_groups(True)
         hyp.set_support_skip(True)
 
@@ -82,7 +82,7 @@ def test_cores_beyond_48_slots_fall_back(hyp, M, na, nb):
         hyp.set_same_spin_cores(False)
         b = H.apply(d)
     finally:
-        hyp.set_same_spin_cores(True)
+        hyp.set_same_spin_cores()
     assert torch.equal(a, b)
     assert np.linalg.norm(a.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
 
@@ -105,7 +105,7 @@ def test_grouped_32q(hyp):
                 got = H.apply(d).cpu().numpy()
             finally:
                 hyp.set_support_skip(True)
-                hyp.set_same_spin_cores(True)
+                hyp.set_same_spin_cores()
             assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
             assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
             assert np.count_nonzero(got[ref == 0.0]) == 0
@@ -123,7 +123,7 @@ def test_grouped_32q(hyp):
         per_row = H.apply(dp)
     finally:
         hyp.set_same_spin_groups(True)
-        hyp.set_same_spin_cores(True)
+        hyp.set_same_spin_cores()
     for name, g in (("grouped", got), ("cores", got_c)):
         rel = (torch.linalg.norm(g - per_row) / torch.linalg.norm(per_row)).item()
         print(f"[same-spin] dense 32 qubits: {name} vs per-row relative difference {rel:.2e}", flush=True)
