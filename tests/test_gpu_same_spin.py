@@ -135,3 +135,42 @@ def test_grouped_32q(hyp):
     for g in (got, got_c):
         g_rows = g[torch.from_numpy(rows).cuda()].cpu().numpy()
         assert np.abs(g_rows - ref_rows).max() <= 1e-12 * np.abs(ref_rows).max()
+
+
+@pytest.mark.parametrize("skip", [True, False])
+def test_core_path_in_captured_graph(hyp, skip):
+    """H psi with the core path (forced on a small sector) captured in a HIP
+    graph and replayed with eager work in between: every replay equals the
+    eager product of the buffer's current state, for dense states (core path)
+    and, with support skipping, sparse ones (the device-side choice takes the
+    grouped lists) alternating."""
+    M, na, nb = 10, 5, 4
+    S, H, (x, z, c) = _ham(hyp, M, na, nb, 77)
+    idx, val = synth.sparse_state(S.dim, S.da, n_random=3)
+    sparse = np.zeros(S.dim)
+    sparse[idx] = val
+    states = [synth.random_state(S.dim, 5), sparse, synth.random_state(S.dim, 6), sparse * 0.5]
+    try:
+        hyp.set_same_spin_cores(True)
+        hyp.set_support_skip(skip)
+        psi = torch.from_numpy(states[0]).cuda()
+        sig = torch.empty_like(psi)
+        H.apply(psi, sig)  # eager call first: scratch and tables
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            H.apply(psi, sig)
+        for k, st in enumerate(states):
+            p = torch.from_numpy(st).cuda()
+            ref = H.apply(p).clone()
+            torch.cuda.synchronize()
+            psi.copy_(p)
+            sig.fill_(-1.0)
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(sig, ref), k
+            o = oracle.apply_h(M, na, nb, x, z, c, st)
+            assert np.linalg.norm(sig.cpu().numpy() - o) <= 1e-12 * max(np.linalg.norm(o), 1e-300), k
+    finally:
+        hyp.set_same_spin_cores()
+        hyp.set_support_skip(True)
