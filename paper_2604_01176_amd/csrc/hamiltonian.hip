@@ -343,14 +343,14 @@ __global__ void __launch_bounds__(256) k_ss_apply(SSApplyArgs a) {
       for (int u = 0; u < 8; ++u) {
         const int o = __builtin_amdgcn_readfirstlane(yo[m + u]);
         const bool z = a.cnz && a.cnz[o / a.S] == 0;
-        v[u] = z ? 0.0 : a.Y[(int64_t)o * a.ldy + cy];
+        v[u] = z ? 0.0 : __builtin_nontemporal_load(&a.Y[(int64_t)o * a.ldy + cy]);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) sum += v[u];
     }
     for (; m < a.npair; ++m) {
       const int o = __builtin_amdgcn_readfirstlane(yo[m]);
-      if (!(a.cnz && a.cnz[o / a.S] == 0)) sum += a.Y[(int64_t)o * a.ldy + cy];
+      if (!(a.cnz && a.cnz[o / a.S] == 0)) sum += __builtin_nontemporal_load(&a.Y[(int64_t)o * a.ldy + cy]);
     }
   }
   if (live) a.out[(int64_t)row * a.ncol + col] = sum;
@@ -567,7 +567,7 @@ __global__ void __launch_bounds__(256) k_ss_core(SSCoreArgs a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int i = 16 * bi + mk + 4 * e;
-          if (i < S) a.Y[(core * S + i) * a.ldy + (k0 - a.c0) + cc] = acc[bi][e];
+          if (i < S) __builtin_nontemporal_store(acc[bi][e], &a.Y[(core * S + i) * a.ldy + (k0 - a.c0) + cc]);
         }
     }
   };
@@ -678,7 +678,10 @@ __global__ void __launch_bounds__(256) k_ssg_fill(const int* __restrict__ rank, 
 __global__ void __launch_bounds__(256) k_ssg_compact(const int64_t* __restrict__ off, const int* __restrict__ urank,
                                                      const double* __restrict__ ucoef, int ngroups,
                                                      const uint32_t* __restrict__ src_nz, int* __restrict__ crank,
-                                                     double* __restrict__ ccoef, int* __restrict__ ccnt) {
+                                                     double* __restrict__ ccoef, int* __restrict__ ccnt,
+                                                     const int* __restrict__ sel) {
+  // sel: beside the core path, compact only where the grouped lists are selected
+  if (sel && *sel != 0) return;
   const int g = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
   if (g >= ngroups) return;
   const int lane = threadIdx.x & 63;
@@ -1605,7 +1608,7 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
           HYP_LAUNCH("k_ss_select", k_ss_select, dim3(1), dim3(1024), 0, st, flags, nrow, W->k_sel + sp);
           HYP_LAUNCH("k_ssg_compact", k_ssg_compact, dim3((unsigned)((W->g_n[sp] + 3) / 4)), dim3(256), 0, st,
                      W->g_off[sp], W->g_rank[sp], W->g_coef[sp], W->g_n[sp], flags, W->gc_rank[sp], W->gc_coef[sp],
-                     W->gc_cnt[sp]);
+                     W->gc_cnt[sp], (const int*)(W->k_sel + sp));
         }
       }
       const int* sel = (skip && W->g_ok) ? W->k_sel + sp : nullptr;
@@ -1689,7 +1692,7 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
       if (skip)
         HYP_LAUNCH("k_ssg_compact", k_ssg_compact, dim3((unsigned)((ng + 3) / 4)), dim3(256), 0, st, W->g_off[sp],
                    W->g_rank[sp], W->g_coef[sp], ng, sp == 0 ? nz_a : nz_b, W->gc_rank[sp], W->gc_coef[sp],
-                   W->gc_cnt[sp]);
+                   W->gc_cnt[sp], (const int*)nullptr);
       SSGArgs ga;
       ga.in = sp == 0 ? (const void*)W->psi_t : psi;
       ga.out = sp == 0 ? W->part_a : W->part_b;
