@@ -193,8 +193,9 @@ hyp_status hyp_set_same_spin_groups(int tiles);
  * C(N, 2) cores' rows of Y in a fixed order (deterministic) beside its
  * singles and diagonal, which keep the per-row lists.  mode = 2 (default)
  * takes it where the tables were built with the Hamiltonian (every core of
- * both spins with at most 48 slots; a band of Y takes at most 4 GiB of
- * device memory, allocated with the Hamiltonian) and the FP64 state vector
+ * both spins with at most 48 slots; a band of Y takes at most 20 GiB or an
+ * eighth of the device memory, allocated with the Hamiltonian: 18.6 GB in
+ * two bands at 32 qubits) and the FP64 state vector
  * exceeds 256 MiB, the size of the Infinity Cache, below which the grouped
  * lists are faster; 1 wherever the tables were built; 0 never (the grouped
  * or per-row lists of hyp_set_same_spin_groups).  With support skipping
