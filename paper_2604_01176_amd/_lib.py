@@ -82,6 +82,7 @@ SIGNATURES = {
     "hyp_set_support_skip": (_ci, [_ci]),
     "hyp_set_same_spin_groups": (_ci, [_ci]),
     "hyp_set_same_spin_cores": (_ci, [_ci]),
+    "hyp_set_mixed_matrix_cores": (_ci, [_ci]),
     "hyp_set_pool_kind": (_ci, [_ci]),
     "hyp_apply_excitations": (_ci, [_vp, _ci, _vp, _vp, _i64, _vp, _vp]),
     "hyp_csr_build": (_ci, [_vp, _vp, ctypes.POINTER(_vp)]),

@@ -1332,6 +1332,278 @@ __global__ void __launch_bounds__(768) k_mixed_c(MixedArgs a, const uint16_t* __
   }
 }
 
+// ------------------------------------------------ mixed pass on matrix cores
+//
+// The alpha-beta part of one beta row I_b as dense products.  Stage the row's
+// kept beta-single sources J_k (k < K <= 64) as a K x D_a matrix
+// P[k][t] = psi[J_k][t].  An alpha single takes source string t to output
+// string s = t - e + i (e occupied in t, i empty in t), so every alpha-beta
+// double of the row is
+//   sigma[I_b][s] += (-1)^{popc(abJa[(i,e)] & s)} Z_e[i][t],
+//   Z_e[i][t] = sum_k A_e[i][k] P[k][t],
+//   A_e[i][k] = (beta sign of k) abF[(i,e)][pair of k][i > e][orientation of k],
+// and the beta singles' alpha-occupation dressing is row i = e of the same
+// product, A_e[e][k] being the dressing coefficient of orbital e for stage k
+// (target s = t).  For one orbital e that is a (16 x K) x (K x |{t : e in t}|)
+// product on v_mfma_f64_16x16x4_f64: wave e keeps A_e in registers (one A
+// operand per 4 stages) and takes a 64-column chunk's columns with e occupied,
+// 16 at a time, as B operands from LDS (element q of lane l holds row
+// (l >> 4) + 4q of Z_e, column l & 15).  The own row (the alpha singles' beta
+// dressing and the alpha-beta diagonal) is a rank-one term on the same targets.
+// Each target is added to the output row, held whole in LDS, with ds_add_f64.
+// The waves' additions land in no fixed order, so this form reproduces sigma
+// to rounding, not bit for bit (k_mixed and k_mixed_c are the bitwise-
+// reproducible forms).  Products and sums in FP64 for either storage type.
+constexpr int kMMCols = 64;  // source columns per chunk
+struct MixedMMLds {
+  double P[65][kMMCols];      // rows < 64: kept beta-single sources (zero past them); row 64: own row
+  uint32_t lst[16][kMMCols];  // per wave: chunk column | alpha string << 8, columns with the wave's orbital occupied
+  int32_t rlo[256], rhi[256]; // alpha rank tables
+  int2 stage[64];
+  int nstage;
+  int own;
+};
+constexpr size_t kMMLdsMax = 160 * 1024;  // LDS per workgroup
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_mixed_m(MixedArgs a) {
+  typedef double f64x4 __attribute__((ext_vector_type(4)));
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ MixedMMLds L;
+  double* sig = (double*)smem;  // [da]: the row's alpha-beta part
+  const int M = a.M, da = a.da;
+  const uint32_t amask = (1u << M) - 1u;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const HamDev& H = a.H;
+  const int brow = blockIdx.x;
+  const uint32_t bs = a.bstr[brow];
+
+  // stage table, as in k_mixed
+  const int nbemp = M - a.nb;
+  const int nbs = a.nb * nbemp;
+  if (tid < 64) {
+    const int jb = tid;
+    bool keep = false;
+    int2 ent = make_int2(0, 0);
+    if (jb < nbs) {
+      const int io = jb / nbemp, ie = jb % nbemp;
+      uint32_t occ = bs, emp = ~bs & amask;
+      for (int j = 0; j < io; ++j) occ &= occ - 1;
+      for (int j = 0; j < ie; ++j) emp &= emp - 1;
+      const int i = __ffs(occ) - 1, e = __ffs(emp) - 1;
+      const int p = min(i, e), q = max(i, e);
+      const int pb = pair_id(p, q);
+      const uint32_t bs2 = bs ^ (1u << i) ^ (1u << e);
+      const uint32_t jsb = H.sJ[kMaxPairs + pb] >> M;
+      const uint32_t sgn_s = __popc(jsb & bs) & 1u;
+      const uint32_t sgn_ab = __popc((H.abJb[pb] >> M) & bs) & 1u;
+      const int r2 = a.brank->lo[bs2 & 255u] + a.brank->hi[(bs2 >> 8) & 255u];
+      ent = make_int2(r2, pb | ((i == q) ? 1 << 16 : 0) | (int)(sgn_s << 17) | (int)(sgn_ab << 18));
+      keep = !a.row_nz || a.row_nz[r2] != 0u;
+    }
+    const uint64_t m = __ballot(keep);
+    const uint64_t below = (jb == 0) ? 0ull : (~0ull >> (64 - jb));
+    if (keep) L.stage[__popcll(m & below)] = ent;
+    if (jb == 0) {
+      L.nstage = __popcll(m);
+      L.own = (!a.row_nz || a.row_nz[brow] != 0u) ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  const int nst = L.nstage;
+  const bool own = L.own != 0;
+  if (nst == 0 && !own) {
+    for (int c = tid; c < da; c += 1024) {
+      const double v = a.pb[(int64_t)brow * da + c] + a.pa_t[(int64_t)c * a.db + brow];
+      ((T*)a.sigma)[(int64_t)brow * da + c] = (T)v;
+    }
+    return;
+  }
+  for (int c = tid; c < da; c += 1024) sig[c] = 0.0;
+  if (tid < 256) {
+    L.rlo[tid] = a.arank->lo[tid];
+    L.rhi[tid] = a.arank->hi[tid];
+  }
+  // source rows past the kept ones stay zero, and so does the own row when
+  // it is not taken
+  for (int x = tid; x < 65 * kMMCols; x += 1024) {
+    const int r = x / kMMCols;
+    if ((r >= nst && r < 64) || (r == 64 && !own)) L.P[r][x % kMMCols] = 0.0;
+  }
+  const int nks = (nst + 3) >> 2;  // MFMA steps of 4 stages
+
+  // wave w: alpha orbital e = w; its A operands (lane l: row l & 15, stage
+  // 4 step + (l >> 4))
+  const int e = w;
+  const bool ew = e < M;
+  double areg[16];
+  {
+    const int i = lane & 15;
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      const int k = 4 * st + (lane >> 4);
+      double v = 0.0;
+      if (ew && i < M && k < nst) {
+        const int info = L.stage[k].y;
+        const int pb = info & 0xffff, Ob = (info >> 16) & 1;
+        if (i == e) {
+          const double d = H.sB[(size_t)((kMaxPairs + pb) * 2 + Ob) * 32 + e];
+          v = ((info >> 17) & 1) ? -d : d;
+        } else {
+          const int pid = pair_id(min(i, e), max(i, e));
+          const double f = H.abF[((size_t)pid * kMaxPairs + pb) * 4 + (i > e ? 2 : 0) + Ob];
+          v = ((info >> 18) & 1) ? -f : f;
+        }
+      }
+      areg[st] = v;
+    }
+  }
+  // per output element q of a lane (row i = (l >> 4) + 4q of Z_e): the
+  // target is s = t ^ flip, kept where t & excl == 0 (i empty in t; never for
+  // i >= M); the alpha-beta and single-dressing sign masks of the pair (i, e)
+  // and the own row's coefficient (the alpha single's beta dressing, or for
+  // i = e, where flip = 0 and the masks are 0, the alpha-beta diagonal of e)
+  uint32_t mab[4], msg[4], flip[4], excl[4];
+  double cown[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = (lane >> 4) + 4 * q;
+    mab[q] = 0u;
+    msg[q] = 0u;
+    cown[q] = 0.0;
+    flip[q] = (i < M && i != e) ? (1u << e) ^ (1u << i) : 0u;
+    excl[q] = (!ew || i >= M) ? ~0u : (i == e ? 0u : 1u << i);
+    if (ew && i < M && i != e) {
+      const int pid = pair_id(min(i, e), max(i, e));
+      mab[q] = H.abJa[pid];
+      msg[q] = H.sJ[pid];
+      if (own) {
+        const double* B = H.sB + (size_t)(pid * 2 + (i > e ? 1 : 0)) * 32;
+        double v = 0.0;
+        uint32_t o = bs;
+        while (o) {
+          const int l = __ffs(o) - 1;
+          o &= o - 1;
+          v += B[l + M];
+        }
+        cown[q] = v;
+      }
+    }
+  }
+  double dmix_e = 0.0;
+  if (ew && own) {
+    uint32_t o = bs;
+    while (o) {
+      const int l = __ffs(o) - 1;
+      o &= o - 1;
+      dmix_e += H.dC[e * 32 + (l + M)];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if ((lane >> 4) + 4 * q == e) cown[q] = dmix_e;
+  // the set-up loads complete here, not behind the chunk loop's prefetches
+#pragma unroll
+  for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(mab[q]), "+v"(msg[q]), "+v"(cown[q]));
+#pragma unroll
+  for (int st = 0; st < 16; ++st) asm volatile("" : "+v"(areg[st]));
+
+  // prefetch into registers: thread -> source row tid >> 4, columns
+  // 4 (tid & 15) .. + 3; threads < 16 also the own row; every wave the
+  // chunk's alpha strings
+  const T* psi = (const T*)a.psi;
+  const int pr = tid >> 4, pc = (tid & 15) * 4;
+  const T* srow = psi + (pr < nst ? (int64_t)L.stage[pr].x * da : 0);
+  const T* orow = psi + (int64_t)brow * da;
+  double pv[4], po[4];
+  uint32_t tv = 0u;
+  auto fetch = [&](int c) {
+    const int c0 = c * kMMCols;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int col = c0 + pc + u;
+      pv[u] = (pr < nst && col < da) ? (double)srow[col] : 0.0;
+      po[u] = (own && tid < 16 && col < da) ? (double)orow[col] : 0.0;
+    }
+    tv = (c0 + lane < da) ? a.astr[c0 + lane] : 0u;
+  };
+  // registers into LDS; the wave's list of columns with its orbital occupied
+  auto put = [&](int c) -> int {
+    if (pr < nst) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) L.P[pr][pc + u] = pv[u];
+    }
+    if (own && tid < 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) L.P[64][pc + u] = po[u];
+    }
+    const bool bit = ew && (c * kMMCols + lane < da) && ((tv >> e) & 1u);
+    const uint64_t m = __ballot(bit);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (bit) L.lst[w][__popcll(m & below)] = (uint32_t)lane | (tv << 8);
+    return __popcll(m);
+  };
+
+  const int nch = (da + kMMCols - 1) / kMMCols;
+  const uint32_t pbase0 = lds_addr(&L.P[lane >> 4][0]);
+  fetch(0);
+  for (int c = 0; c < nch; ++c) {
+    const int n = put(c);
+    __syncthreads();  // chunk c and the lists in LDS
+    if (c + 1 < nch) fetch(c + 1);
+    if (ew) {
+      const int c0 = c * kMMCols;
+      const int ntile = (n + 15) >> 4;
+      for (int j = 0; j < ntile; ++j) {
+        const int slot = 16 * j + (lane & 15);
+        const bool valid = slot < n;
+        const uint32_t ent = L.lst[w][valid ? slot : 0];
+        const int col = (int)(ent & 63u);
+        const uint32_t t = ent >> 8;
+        const uint32_t pb = pbase0 + (uint32_t)col * 8u;
+        f64x4 z0 = {0.0, 0.0, 0.0, 0.0}, z1 = {0.0, 0.0, 0.0, 0.0};
+        if (nks == 16) {
+          // every stage kept: B operands read ahead of the products
+          double bv[16];
+#pragma unroll
+          for (int st = 0; st < 16; ++st) bv[st] = lds_load<double>(pb + st * 4 * kMMCols * 8);
+#pragma unroll
+          for (int st = 0; st < 16; st += 2) {
+            z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st], bv[st], z0, 0, 0, 0);
+            z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st + 1], bv[st + 1], z1, 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int st = 0; st < 16; st += 2) {
+            if (st < nks)
+              z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st], lds_load<double>(pb + st * 4 * kMMCols * 8), z0,
+                                                        0, 0, 0);
+            if (st + 1 < nks)
+              z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                  areg[st + 1], lds_load<double>(pb + (st + 1) * 4 * kMMCols * 8), z1, 0, 0, 0);
+          }
+        }
+        const f64x4 z = z0 + z1;
+        const double pown = L.P[64][col];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t s2 = t ^ flip[q];
+          const int r = L.rlo[s2 & 255u] + L.rhi[(s2 >> 8) & 255u];
+          const double zz = (__popc(mab[q] & s2) & 1) ? -z[q] : z[q];
+          const double cc = (__popc(msg[q] & s2) & 1) ? -cown[q] : cown[q];
+          const double v = zz + cc * pown;
+          if (valid && (t & excl[q]) == 0u) atomicAdd(&sig[r], v);
+        }
+      }
+    }
+    __syncthreads();  // chunk c's reads done before chunk c + 1 overwrites it
+  }
+  for (int c = tid; c < da; c += 1024) {
+    const double v = sig[c] + a.pb[(int64_t)brow * da + c] + a.pa_t[(int64_t)c * a.db + brow];
+    ((T*)a.sigma)[(int64_t)brow * da + c] = (T)v;
+  }
+}
+
 // ---------------------------------------------------------------- generic
 
 struct GenericArgs {
@@ -1378,6 +1650,9 @@ __global__ void k_generic(GenericArgs a) {
 static int g_support_skip = 1;  // process-wide: restrict H psi to psi's row and column support
 static int g_ss_cores = 2;      // process-wide: FP64 same-spin doubles through the cores: 0 off, 1 where
                                 // built, 2 where built and the FP64 state exceeds kCoreAutoBytes
+static int g_mixed_mm = 2;      // process-wide: mixed pass on the matrix cores (k_mixed_m): 0 off, 1 where
+                                // the row fits LDS, 2 where it fits and the state exceeds kMMAutoBytes
+constexpr size_t kMMAutoBytes = size_t(256) << 20;
 static int g_ss_groups = 2;     // process-wide: FP64 same-spin pass over grouped lists with this many
                                 // 64-column tiles per four-wave workgroup (1, 2 or 4); 0: per-row lists
 
@@ -1792,6 +2067,14 @@ static hyp_status run_mixed(Ham* Hm, HamWork* W, const void* psi, void* sigma, u
   ma.row_nz = nz_b;
   const int nt = Hm->threads[sizeof(T) == 4 ? 1 : 0];
   ma.nchunk = (da + nt - 1) / nt;
+  const size_t mshm = (size_t)da * 8;  // the output row in FP64
+  if (g_mixed_mm != 0 && da > 0 && db > 0 && S->M <= kMaxOrb && mshm + sizeof(MixedMMLds) <= kMMLdsMax &&
+      (g_mixed_mm == 1 || (size_t)S->dim * 8 > kMMAutoBytes)) {
+    HYP_HIP(hipFuncSetAttribute((const void*)k_mixed_m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mshm));
+    HYP_LAUNCH("k_mixed", k_mixed_m<T>, dim3((unsigned)db), dim3(1024), mshm, st, ma);
+    HYP_HIP(hipGetLastError());
+    return HYP_OK;
+  }
   if (sizeof(T) == 8 && nt == kCMixedThreads && row_staging_compact() && W->c_ok && (da % 2) == 0 &&
       ((uintptr_t)psi & 15u) == 0) {
     // compact, double-buffered staging (buffer 0 | buffer 1 at kCBuf1, each
@@ -2280,6 +2563,12 @@ hyp_status hyp_set_same_spin_groups(int tiles) {
 hyp_status hyp_set_same_spin_cores(int mode) {
   if (mode < 0 || mode > 2) return fail(HYP_ERR_ARG, "hyp_set_same_spin_cores: mode must be 0, 1 or 2");
   g_ss_cores = mode;
+  return HYP_OK;
+}
+
+hyp_status hyp_set_mixed_matrix_cores(int mode) {
+  if (mode < 0 || mode > 2) return fail(HYP_ERR_ARG, "hyp_set_mixed_matrix_cores: mode must be 0, 1 or 2");
+  g_mixed_mm = mode;
   return HYP_OK;
 }
 

@@ -56,6 +56,7 @@ def test_switch_argument_checks_without_gpu():
     call (HYP_ERR_ARG = 1), and accept every documented value."""
     lib = ctypes.CDLL(LIB)
     cases = (("hyp_set_same_spin_cores", (0, 1, 2), (-1, 3), 2),
+             ("hyp_set_mixed_matrix_cores", (0, 1, 2), (-1, 3), 2),
              ("hyp_set_same_spin_groups", (0, 1, 2, 4), (-1, 3, 8), 2),
              ("hyp_set_row_staging", (0, 1), (-1, 2), 0),
              ("hyp_set_support_skip", (0, 1), (-1, 2), 1))

@@ -141,13 +141,17 @@ def test_compact_staging_32q(hyp):
 
 
 def _apply(hyp, H, psi, staging):
+    # the two staging forms of k_mixed / k_mixed_c (the matrix-core form,
+    # which reproduces sigma to rounding only, switched off)
     try:
+        hyp.set_mixed_matrix_cores(False)
         hyp.set_row_staging(staging)
         out = H.apply(psi)
         torch.cuda.synchronize()
         return out
     finally:
         hyp.set_row_staging("compact")
+        hyp.set_mixed_matrix_cores()
 
 
 @pytest.mark.parametrize("M,na,nb", CASES)
@@ -207,10 +211,12 @@ def test_compact_mixed_pass_32q(hyp):
     for staging in ("compact", "rows"):
         out[staging] = _apply(hyp, H, psi, staging)
         t0 = time.perf_counter()
+        hyp.set_mixed_matrix_cores(False)
         hyp.set_row_staging(staging)
         H.apply(psi, out[staging])
         torch.cuda.synchronize()
         hyp.set_row_staging("compact")
+        hyp.set_mixed_matrix_cores()
         times[staging] = (time.perf_counter() - t0) * 1e3
     print(f"[staging] 32q H psi (768 threads): compact {times['compact']:.1f} ms, whole rows {times['rows']:.1f} ms",
           flush=True)
