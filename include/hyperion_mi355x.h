@@ -214,8 +214,9 @@ hyp_status hyp_set_same_spin_cores(int mode);
  * strings with e occupied (A_e: 16 x K, the row's alpha-beta coefficients
  * for the pairs (i, e) and the dressing of e), each element added to its
  * output string s = t - e + i of the row held in LDS.  mode = 2 (default)
- * takes it where the output row fits LDS (D_a <= 15,000 at M <= 16) and the
- * FP64 state exceeds 256 MiB; 1 wherever the row fits; 0 never (k_mixed /
+ * takes it where the output row fits LDS (D_a <= 14,000 at M <= 16) and the
+ * FP64 state exceeds 64 MiB (28 qubits and up); 1 wherever the row fits; 0
+ * never (k_mixed /
  * k_mixed_c of hyp_set_row_staging).  The additions into the row land in no
  * fixed order, so this form reproduces sigma to rounding, not bit for bit;
  * mode 0 restores bitwise reproducibility.  Process-wide; HYP_ERR_ARG

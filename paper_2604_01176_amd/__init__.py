@@ -328,7 +328,7 @@ def set_same_spin_cores(mode="auto"):
 def set_mixed_matrix_cores(mode="auto"):
     """hyp_set_mixed_matrix_cores: the mixed alpha-beta pass as dense
     products on the matrix cores: "auto" (default; where the output row fits
-    LDS and the FP64 state exceeds 256 MiB), True (wherever the row fits) or
+    LDS and the FP64 state exceeds 64 MiB), True (wherever the row fits) or
     False (the bitwise-reproducible k_mixed / k_mixed_c)."""
     m = 2 if mode == "auto" else (1 if mode else 0)
     check(_lib.load().hyp_set_mixed_matrix_cores(m))

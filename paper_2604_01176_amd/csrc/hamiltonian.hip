@@ -1346,30 +1346,95 @@ __global__ void __launch_bounds__(768) k_mixed_c(MixedArgs a, const uint16_t* __
 // product, A_e[e][k] being the dressing coefficient of orbital e for stage k
 // (target s = t).  For one orbital e that is a (16 x K) x (K x |{t : e in t}|)
 // product on v_mfma_f64_16x16x4_f64: wave e keeps A_e in registers (one A
-// operand per 4 stages) and takes a 64-column chunk's columns with e occupied,
-// 16 at a time, as B operands from LDS (element q of lane l holds row
-// (l >> 4) + 4q of Z_e, column l & 15).  The own row (the alpha singles' beta
-// dressing and the alpha-beta diagonal) is a rank-one term on the same targets.
-// Each target is added to the output row, held whole in LDS, with ds_add_f64.
-// The waves' additions land in no fixed order, so this form reproduces sigma
-// to rounding, not bit for bit (k_mixed and k_mixed_c are the bitwise-
-// reproducible forms).  Products and sums in FP64 for either storage type.
-constexpr int kMMCols = 64;  // source columns per chunk
+// operand per 4 stages) and takes a chunk's columns with e occupied, 16 at a
+// time, as B operands from LDS (element q of lane l holds row (l >> 4) + 4q
+// of Z_e, column l & 15).  The own row (the alpha singles' beta dressing and
+// the alpha-beta diagonal) is a rank-one term on the same targets.  Each
+// target is added to the output row, held whole in LDS, with ds_add_f64.
+// Which columns a wave takes and where and with which signs each element
+// lands depend on the alpha strings only: k_mm_tables lists them once per
+// Hamiltonian.  The waves' additions land in no fixed order, so this form
+// reproduces sigma to rounding, not bit for bit (k_mixed and k_mixed_c are
+// the bitwise-reproducible forms).  Products and sums in FP64 for either
+// storage type.
+constexpr int kMMSeg = 16;                 // columns per segment (one 128-byte line at FP64)
+constexpr int kMMSegs = 3;                 // segments per chunk, from three regions of the alpha space
+constexpr int kMMCols = kMMSeg * kMMSegs;  // source columns per chunk
+constexpr int kMMTiles = (kMMCols + 15) / 16;
+constexpr uint32_t kMMNone = 0x3fffu;      // target code: no element
+// A chunk takes segment c of each of the kMMSegs equal regions of the alpha
+// columns, so that every chunk mixes strings of all occupations and the
+// 16 waves' (orbitals') column counts stay close; chunks alternate between
+// two buffers filled by direct global->LDS copies.
+__host__ __device__ inline int mm_column(int c, int l, int qr) {
+  return (l / kMMSeg) * qr + c * kMMSeg + l % kMMSeg;
+}
+
+// The row-independent tables: one wave per (chunk c, orbital e).  Its
+// columns with e occupied in chunk order fill 16-slot tiles; lane
+// l = 16 g + u of tile j takes slot 16 j + u and rows i = g + 4q.
+__global__ void __launch_bounds__(64) k_mm_tables(int M, int da, int qr, const uint32_t* __restrict__ astr,
+                                                  const RankTables* __restrict__ arank,
+                                                  const uint32_t* __restrict__ abJa, const uint32_t* __restrict__ sJ,
+                                                  uint32_t* __restrict__ ent, uint64_t* __restrict__ code,
+                                                  uint8_t* __restrict__ nt) {
+  __shared__ uint32_t lst[64];
+  const int ce = blockIdx.x, c = ce >> 4, e = ce & 15, lane = threadIdx.x;
+  const int g = mm_column(c, lane, qr);
+  const uint32_t t0 = (lane < kMMCols && g < da) ? astr[g] : 0u;
+  const bool bit = e < M && ((t0 >> e) & 1u);
+  const uint64_t m = __ballot(bit);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if (bit) lst[__popcll(m & below)] = (uint32_t)lane | (t0 << 8);
+  __syncthreads();
+  const int n = __popcll(m);
+  if (lane == 0) nt[ce] = (uint8_t)((n + 15) >> 4);
+  for (int j = 0; j < kMMTiles; ++j) {
+    const int slot = 16 * j + (lane & 15);
+    const bool valid = slot < n;
+    const uint32_t en = valid ? lst[slot] : 0u;
+    const uint32_t t = en >> 8;
+    const size_t tile = (size_t)ce * kMMTiles + j;
+    if (lane < 16) ent[tile * 16 + lane] = en;
+    uint64_t cw = 0;
+    for (int q = 0; q < 4; ++q) {
+      const int i = (lane >> 4) + 4 * q;
+      uint32_t cq = kMMNone;
+      if (valid && i < M && (i == e || !((t >> i) & 1u))) {
+        const uint32_t s2 = (i == e) ? t : t ^ (1u << e) ^ (1u << i);
+        const uint32_t r = (uint32_t)(arank->lo[s2 & 255u] + arank->hi[(s2 >> 8) & 255u]);
+        uint32_t sab = 0u, ssg = 0u;
+        if (i != e) {
+          const int pid = pair_id(min(i, e), max(i, e));
+          sab = __popc(abJa[pid] & s2) & 1u;
+          ssg = __popc(sJ[pid] & s2) & 1u;
+        }
+        cq = r | (sab << 14) | (ssg << 15);
+      }
+      cw |= (uint64_t)cq << (16 * q);
+    }
+    code[tile * 64 + lane] = cw;
+  }
+}
+
+template <typename T>
 struct MixedMMLds {
-  double P[65][kMMCols];      // rows < 64: kept beta-single sources (zero past them); row 64: own row
-  uint32_t lst[16][kMMCols];  // per wave: chunk column | alpha string << 8, columns with the wave's orbital occupied
-  int32_t rlo[256], rhi[256]; // alpha rank tables
+  T P[2][65][kMMCols];  // rows < 64: kept beta-single sources (zero past them); row 64: own row
   int2 stage[64];
   int nstage;
   int own;
 };
 constexpr size_t kMMLdsMax = 160 * 1024;  // LDS per workgroup
 
-template <typename T>
-__global__ void __launch_bounds__(1024) k_mixed_m(MixedArgs a) {
+// qr: columns per region (a multiple of kMMSeg), nch = qr / kMMSeg chunks;
+// kVec: rows start 16-byte aligned (16-byte copies, else 4-byte)
+template <typename T, int kVec>
+__global__ void __launch_bounds__(1024) k_mixed_m(MixedArgs a, const uint32_t* __restrict__ ment,
+                                                  const uint64_t* __restrict__ mcode, const uint8_t* __restrict__ mnt,
+                                                  int qr, int nch) {
   typedef double f64x4 __attribute__((ext_vector_type(4)));
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ MixedMMLds L;
+  __shared__ __align__(16) MixedMMLds<T> L;
   double* sig = (double*)smem;  // [da]: the row's alpha-beta part
   const int M = a.M, da = a.da;
   const uint32_t amask = (1u << M) - 1u;
@@ -1420,15 +1485,11 @@ __global__ void __launch_bounds__(1024) k_mixed_m(MixedArgs a) {
     return;
   }
   for (int c = tid; c < da; c += 1024) sig[c] = 0.0;
-  if (tid < 256) {
-    L.rlo[tid] = a.arank->lo[tid];
-    L.rhi[tid] = a.arank->hi[tid];
-  }
-  // source rows past the kept ones stay zero, and so does the own row when
-  // it is not taken
-  for (int x = tid; x < 65 * kMMCols; x += 1024) {
-    const int r = x / kMMCols;
-    if ((r >= nst && r < 64) || (r == 64 && !own)) L.P[r][x % kMMCols] = 0.0;
+  // source rows past the kept ones stay zero in both buffers, and so does
+  // the own row when it is not taken
+  for (int x = tid; x < 2 * 65 * kMMCols; x += 1024) {
+    const int r = (x / kMMCols) % 65;
+    if ((r >= nst && r < 64) || (r == 64 && !own)) (&L.P[0][0][0])[x] = T(0);
   }
   const int nks = (nst + 3) >> 2;  // MFMA steps of 4 stages
 
@@ -1458,146 +1519,197 @@ __global__ void __launch_bounds__(1024) k_mixed_m(MixedArgs a) {
       areg[st] = v;
     }
   }
-  // per output element q of a lane (row i = (l >> 4) + 4q of Z_e): the
-  // target is s = t ^ flip, kept where t & excl == 0 (i empty in t; never for
-  // i >= M); the alpha-beta and single-dressing sign masks of the pair (i, e)
-  // and the own row's coefficient (the alpha single's beta dressing, or for
-  // i = e, where flip = 0 and the masks are 0, the alpha-beta diagonal of e)
-  uint32_t mab[4], msg[4], flip[4], excl[4];
+  // the own row's coefficient per output element q of a lane (row
+  // i = (l >> 4) + 4q of Z_e): the alpha single's beta dressing of the pair
+  // (i, e), for i = e the alpha-beta diagonal of e
   double cown[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int i = (lane >> 4) + 4 * q;
-    mab[q] = 0u;
-    msg[q] = 0u;
-    cown[q] = 0.0;
-    flip[q] = (i < M && i != e) ? (1u << e) ^ (1u << i) : 0u;
-    excl[q] = (!ew || i >= M) ? ~0u : (i == e ? 0u : 1u << i);
-    if (ew && i < M && i != e) {
-      const int pid = pair_id(min(i, e), max(i, e));
-      mab[q] = H.abJa[pid];
-      msg[q] = H.sJ[pid];
-      if (own) {
-        const double* B = H.sB + (size_t)(pid * 2 + (i > e ? 1 : 0)) * 32;
-        double v = 0.0;
-        uint32_t o = bs;
+    double v = 0.0;
+    if (ew && own && i < M) {
+      uint32_t o = bs;
+      if (i == e) {
+        while (o) {
+          const int l = __ffs(o) - 1;
+          o &= o - 1;
+          v += H.dC[e * 32 + (l + M)];
+        }
+      } else {
+        const double* B = H.sB + (size_t)(pair_id(min(i, e), max(i, e)) * 2 + (i > e ? 1 : 0)) * 32;
         while (o) {
           const int l = __ffs(o) - 1;
           o &= o - 1;
           v += B[l + M];
         }
-        cown[q] = v;
       }
     }
+    cown[q] = v;
   }
-  double dmix_e = 0.0;
-  if (ew && own) {
-    uint32_t o = bs;
-    while (o) {
-      const int l = __ffs(o) - 1;
-      o &= o - 1;
-      dmix_e += H.dC[e * 32 + (l + M)];
-    }
-  }
+  // the set-up loads complete here, not behind the chunk loop's copies
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if ((lane >> 4) + 4 * q == e) cown[q] = dmix_e;
-  // the set-up loads complete here, not behind the chunk loop's prefetches
-#pragma unroll
-  for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(mab[q]), "+v"(msg[q]), "+v"(cown[q]));
+  for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(cown[q]));
 #pragma unroll
   for (int st = 0; st < 16; ++st) asm volatile("" : "+v"(areg[st]));
 
-  // prefetch into registers: thread -> source row tid >> 4, columns
-  // 4 (tid & 15) .. + 3; threads < 16 also the own row; every wave the
-  // chunk's alpha strings
+  // chunk c into buffer bf: piece p (kPB bytes) of the 65 x kMMCols buffer
+  // from row p / kPPR; lane l of a wave writes its piece at the wave's base +
+  // kPB l.  A thread's pieces are p = 1024 it + 64 w + lane; their source
+  // addresses at chunk 0, set once, advance by kMMSeg columns per chunk.
+  constexpr int kPB = kVec ? 16 : 4;
+  constexpr int kPPR = kMMCols * (int)sizeof(T) / kPB;  // pieces per row
+  constexpr int kNP = 65 * kPPR;                       // pieces per buffer
+  constexpr int kIt = (kNP + 1023) / 1024;
+  // (with more than 4 pieces per thread, the FP64 4-byte form, the
+  // addresses are formed per chunk instead)
+  constexpr int kPre = kIt <= 4 ? kIt : 0;
   const T* psi = (const T*)a.psi;
-  const int pr = tid >> 4, pc = (tid & 15) * 4;
-  const T* srow = psi + (pr < nst ? (int64_t)L.stage[pr].x * da : 0);
-  const T* orow = psi + (int64_t)brow * da;
-  double pv[4], po[4];
-  uint32_t tv = 0u;
-  auto fetch = [&](int c) {
-    const int c0 = c * kMMCols;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int col = c0 + pc + u;
-      pv[u] = (pr < nst && col < da) ? (double)srow[col] : 0.0;
-      po[u] = (own && tid < 16 && col < da) ? (double)orow[col] : 0.0;
-    }
-    tv = (c0 + lane < da) ? a.astr[c0 + lane] : 0u;
+  auto piece = [&](int it, int& g, uint32_t& off) {
+    const int p = it * 1024 + w * 64 + lane;
+    const int row = p / kPPR;
+    const int lb = (p % kPPR) * kPB;  // byte in the row
+    g = mm_column(0, lb / (int)sizeof(T), qr);
+    const bool ok = p < kNP && (row < nst || (row == 64 && own));
+    const int src = row == 64 ? brow : (row < nst ? L.stage[row].x : 0);
+    off = (uint32_t)((int64_t)src * da + g);
+    if (!ok) g = -1;
   };
-  // registers into LDS; the wave's list of columns with its orbital occupied
-  auto put = [&](int c) -> int {
-    if (pr < nst) {
+  uint32_t off0[kPre > 0 ? kPre : 1];  // source element at chunk 0 (the state has < 2^32 elements wherever the row fits LDS)
+  int g0[kPre > 0 ? kPre : 1];         // column of the piece at chunk 0, -1 when it is not copied
 #pragma unroll
-      for (int u = 0; u < 4; ++u) L.P[pr][pc + u] = pv[u];
+  for (int it = 0; it < kPre; ++it) piece(it, g0[it], off0[it]);
+  auto copy = [&](uint32_t dst, int base, int c, int g, uint32_t off) {
+    if (g >= 0 && g + c * kMMSeg < da) {
+      const int lb = ((base + lane) % kPPR) * kPB;
+      const char* gp = (const char*)(psi + off + (uint32_t)c * kMMSeg) + lb % (int)sizeof(T);
+      if (kVec)
+        dma16(dst, gp);
+      else
+        dma4(dst, gp);
     }
-    if (own && tid < 16) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) L.P[64][pc + u] = po[u];
-    }
-    const bool bit = ew && (c * kMMCols + lane < da) && ((tv >> e) & 1u);
-    const uint64_t m = __ballot(bit);
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (bit) L.lst[w][__popcll(m & below)] = (uint32_t)lane | (tv << 8);
-    return __popcll(m);
   };
-
-  const int nch = (da + kMMCols - 1) / kMMCols;
-  const uint32_t pbase0 = lds_addr(&L.P[lane >> 4][0]);
-  fetch(0);
-  for (int c = 0; c < nch; ++c) {
-    const int n = put(c);
-    __syncthreads();  // chunk c and the lists in LDS
-    if (c + 1 < nch) fetch(c + 1);
-    if (ew) {
-      const int c0 = c * kMMCols;
-      const int ntile = (n + 15) >> 4;
-      for (int j = 0; j < ntile; ++j) {
-        const int slot = 16 * j + (lane & 15);
-        const bool valid = slot < n;
-        const uint32_t ent = L.lst[w][valid ? slot : 0];
-        const int col = (int)(ent & 63u);
-        const uint32_t t = ent >> 8;
-        const uint32_t pb = pbase0 + (uint32_t)col * 8u;
-        f64x4 z0 = {0.0, 0.0, 0.0, 0.0}, z1 = {0.0, 0.0, 0.0, 0.0};
-        if (nks == 16) {
-          // every stage kept: B operands read ahead of the products
-          double bv[16];
+  auto issue = [&](int c, int bf) {
+    const uint32_t buf = lds_addr(&L.P[bf][0][0]);
+    if constexpr (kPre > 0) {
 #pragma unroll
-          for (int st = 0; st < 16; ++st) bv[st] = lds_load<double>(pb + st * 4 * kMMCols * 8);
-#pragma unroll
-          for (int st = 0; st < 16; st += 2) {
-            z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st], bv[st], z0, 0, 0, 0);
-            z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st + 1], bv[st + 1], z1, 0, 0, 0);
-          }
-        } else {
-#pragma unroll
-          for (int st = 0; st < 16; st += 2) {
-            if (st < nks)
-              z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st], lds_load<double>(pb + st * 4 * kMMCols * 8), z0,
-                                                        0, 0, 0);
-            if (st + 1 < nks)
-              z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                  areg[st + 1], lds_load<double>(pb + (st + 1) * 4 * kMMCols * 8), z1, 0, 0, 0);
-          }
-        }
-        const f64x4 z = z0 + z1;
-        const double pown = L.P[64][col];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t s2 = t ^ flip[q];
-          const int r = L.rlo[s2 & 255u] + L.rhi[(s2 >> 8) & 255u];
-          const double zz = (__popc(mab[q] & s2) & 1) ? -z[q] : z[q];
-          const double cc = (__popc(msg[q] & s2) & 1) ? -cown[q] : cown[q];
-          const double v = zz + cc * pown;
-          if (valid && (t & excl[q]) == 0u) atomicAdd(&sig[r], v);
+      for (int it = 0; it < kPre; ++it) {
+        const int base = it * 1024 + w * 64;  // wave-uniform
+        if (base < kNP)
+          copy((uint32_t)__builtin_amdgcn_readfirstlane(buf + (uint32_t)base * (uint32_t)kPB), base, c, g0[it],
+               off0[it]);
+      }
+    } else {
+#pragma unroll 1
+      for (int it = 0; it < kIt; ++it) {
+        const int base = it * 1024 + w * 64;
+        if (base < kNP) {
+          int g;
+          uint32_t off;
+          piece(it, g, off);
+          copy((uint32_t)__builtin_amdgcn_readfirstlane(buf + (uint32_t)base * (uint32_t)kPB), base, c, g, off);
         }
       }
     }
-    __syncthreads();  // chunk c's reads done before chunk c + 1 overwrites it
+  };
+  // the wave's tables of chunk c
+  int ntn = 0;
+  uint32_t entn[kMMTiles];
+  uint64_t coden[kMMTiles];
+  auto tables = [&](int c) {
+    const size_t ce = (size_t)c * 16 + e;
+    ntn = ew ? __builtin_amdgcn_readfirstlane((int)mnt[ce]) : 0;
+#pragma unroll
+    for (int j = 0; j < kMMTiles; ++j) {
+      entn[j] = 0u;
+      coden[j] = ~0ull;
+      if (j < ntn) {
+        entn[j] = ment[(ce * kMMTiles + j) * 16 + (lane & 15)];
+        coden[j] = mcode[(ce * kMMTiles + j) * 64 + lane];
+      }
+    }
+  };
+
+  const uint32_t pbase0 = lds_addr(&L.P[0][lane >> 4][0]);
+  constexpr uint32_t kBufBytes = 65u * kMMCols * sizeof(T);
+  constexpr uint32_t kStep = 4u * kMMCols * sizeof(T);  // 4 stages
+  // Z_e of one tile (column col of buffer pbc)
+  auto products = [&](uint32_t pbc, uint32_t col) -> f64x4 {
+    const uint32_t pb = pbc + col * (uint32_t)sizeof(T);
+    f64x4 z0 = {0.0, 0.0, 0.0, 0.0}, z1 = {0.0, 0.0, 0.0, 0.0};
+    if (nks == 16) {
+      // every stage kept: all B operands read, then the products
+#pragma unroll
+      for (int h = 0; h < 16; h += 8) {
+        // eight B operands read, then their products
+        double bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bv[u] = (double)lds_load<T>(pb + (h + u) * kStep);
+        asm volatile("" ::"v"(bv[0]), "v"(bv[1]), "v"(bv[2]), "v"(bv[3]), "v"(bv[4]), "v"(bv[5]), "v"(bv[6]),
+                     "v"(bv[7]));
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[h + u], bv[u], z0, 0, 0, 0);
+          z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[h + u + 1], bv[u + 1], z1, 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int st = 0; st < 16; st += 2) {
+        if (st < nks)
+          z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st], (double)lds_load<T>(pb + st * kStep), z0, 0, 0, 0);
+        if (st + 1 < nks)
+          z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st + 1], (double)lds_load<T>(pb + (st + 1) * kStep), z1, 0,
+                                                    0, 0);
+      }
+    }
+    return z0 + z1;
+  };
+  // each element of the tile to its target in the row
+  auto scatter = [&](uint32_t obase, uint32_t col, uint64_t cw, const f64x4& z) {
+    const double pown = (double)lds_load<T>(obase + col * (uint32_t)sizeof(T));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t cq = (uint32_t)(cw >> (16 * q)) & 0xffffu;
+      const uint32_t r = cq & 0x3fffu;
+      const double zz = (cq & 0x4000u) ? -z[q] : z[q];
+      const double cc = (cq & 0x8000u) ? -cown[q] : cown[q];
+      if (r != kMMNone) atomicAdd(&sig[r], zz + cc * pown);
+    }
+  };
+
+  tables(0);
+  issue(0, 0);
+  for (int c = 0; c < nch; ++c) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();  // chunk c in its buffer; every wave done with chunk c - 1
+    const int ntile = ntn;
+    uint32_t ent[kMMTiles];
+    uint64_t code[kMMTiles];
+#pragma unroll
+    for (int j = 0; j < kMMTiles; ++j) {
+      ent[j] = entn[j];
+      code[j] = coden[j];
+    }
+    const uint32_t pbc = pbase0 + (uint32_t)(c & 1) * kBufBytes;
+    const uint32_t obase = lds_addr(&L.P[c & 1][64][0]);
+    // the first tile's products run while the next chunk's tables and
+    // copies go out
+    f64x4 z = {0.0, 0.0, 0.0, 0.0};
+    if (ntile > 0) z = products(pbc, ent[0] & 63u);
+    if (c + 1 < nch) {
+      tables(c + 1);
+      issue(c + 1, (c + 1) & 1);
+    }
+    if (ntile > 0) scatter(obase, ent[0] & 63u, code[0], z);
+#pragma unroll
+    for (int j = 1; j < kMMTiles; ++j) {
+      if (j < ntile) {
+        const f64x4 zj = products(pbc, ent[j] & 63u);
+        scatter(obase, ent[j] & 63u, code[j], zj);
+      }
+    }
   }
+  __syncthreads();  // every addition into the row done
   for (int c = tid; c < da; c += 1024) {
     const double v = sig[c] + a.pb[(int64_t)brow * da + c] + a.pa_t[(int64_t)c * a.db + brow];
     ((T*)a.sigma)[(int64_t)brow * da + c] = (T)v;
@@ -1652,7 +1764,7 @@ static int g_ss_cores = 2;      // process-wide: FP64 same-spin doubles through 
                                 // built, 2 where built and the FP64 state exceeds kCoreAutoBytes
 static int g_mixed_mm = 2;      // process-wide: mixed pass on the matrix cores (k_mixed_m): 0 off, 1 where
                                 // the row fits LDS, 2 where it fits and the state exceeds kMMAutoBytes
-constexpr size_t kMMAutoBytes = size_t(256) << 20;
+constexpr size_t kMMAutoBytes = size_t(64) << 20;
 static int g_ss_groups = 2;     // process-wide: FP64 same-spin pass over grouped lists with this many
                                 // 64-column tiles per four-wave workgroup (1, 2 or 4); 0: per-row lists
 
@@ -1756,6 +1868,25 @@ constexpr size_t kCoreYBytes = size_t(20) << 30;
 // products (measured: 10.3 against 11.2 ms at 28 qubits, 0.73 against 0.77
 // at 24; 255 against 235 ms at 32 qubits).
 constexpr size_t kCoreAutoBytes = size_t(256) << 20;
+
+// Tables of the mixed pass on the matrix cores, where its output row fits
+// LDS (M <= 16).
+static hyp_status build_mixed_mm(Ham* Hm, HamWork* W, hipStream_t st) {
+  Sector* S = Hm->sec;
+  const int da = (int)S->da;
+  if (S->M > kMaxOrb || da <= 0 || S->db <= 0 || (size_t)da * 8 + sizeof(MixedMMLds<double>) > kMMLdsMax) return HYP_OK;
+  const int qr = (da + kMMCols - 1) / kMMCols * kMMSeg;  // columns per region
+  const int nce = qr / kMMSeg * 16;                       // (chunk, orbital) pairs
+  HYP_HIP(hipMalloc(&W->m_ent, (size_t)nce * kMMTiles * 16 * sizeof(uint32_t)));
+  HYP_HIP(hipMalloc(&W->m_code, (size_t)nce * kMMTiles * 64 * sizeof(uint64_t)));
+  HYP_HIP(hipMalloc(&W->m_nt, (size_t)nce));
+  HYP_LAUNCH("k_mm_tables", k_mm_tables, dim3((unsigned)nce), dim3(64), 0, st, S->M, da, qr, S->d_astr, S->d_arank,
+             Hm->dev.abJa, Hm->dev.sJ, W->m_ent, W->m_code, W->m_nt);
+  HYP_HIP(hipGetLastError());
+  W->m_qr = qr;
+  W->m_ok = true;
+  return HYP_OK;
+}
 
 static hyp_status build_core_path(Ham* Hm, HamWork* W, hipStream_t st) {
   Sector* S = Hm->sec;
@@ -2068,10 +2199,17 @@ static hyp_status run_mixed(Ham* Hm, HamWork* W, const void* psi, void* sigma, u
   const int nt = Hm->threads[sizeof(T) == 4 ? 1 : 0];
   ma.nchunk = (da + nt - 1) / nt;
   const size_t mshm = (size_t)da * 8;  // the output row in FP64
-  if (g_mixed_mm != 0 && da > 0 && db > 0 && S->M <= kMaxOrb && mshm + sizeof(MixedMMLds) <= kMMLdsMax &&
+  if (g_mixed_mm != 0 && W->m_ok && mshm + sizeof(MixedMMLds<T>) <= kMMLdsMax &&
       (g_mixed_mm == 1 || (size_t)S->dim * 8 > kMMAutoBytes)) {
-    HYP_HIP(hipFuncSetAttribute((const void*)k_mixed_m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mshm));
-    HYP_LAUNCH("k_mixed", k_mixed_m<T>, dim3((unsigned)db), dim3(1024), mshm, st, ma);
+    const bool vec = ((uintptr_t)psi & 15u) == 0 && ((size_t)da * sizeof(T)) % 16 == 0;
+    const void* kf = vec ? (const void*)k_mixed_m<T, 1> : (const void*)k_mixed_m<T, 0>;
+    HYP_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mshm));
+    if (vec)
+      HYP_LAUNCH("k_mixed", (k_mixed_m<T, 1>), dim3((unsigned)db), dim3(1024), mshm, st, ma, W->m_ent, W->m_code,
+                 W->m_nt, W->m_qr, W->m_qr / kMMSeg);
+    else
+      HYP_LAUNCH("k_mixed", (k_mixed_m<T, 0>), dim3((unsigned)db), dim3(1024), mshm, st, ma, W->m_ent, W->m_code,
+                 W->m_nt, W->m_qr, W->m_qr / kMMSeg);
     HYP_HIP(hipGetLastError());
     return HYP_OK;
   }
@@ -2431,6 +2569,7 @@ hyp_status hyp_build_hamiltonian(hyp_sector sh, const uint32_t* x_mask, const ui
     if (e != hipSuccess) return cleanup_fail(e, "hyp_build_hamiltonian: workspace");
     hyp_status rb = build_same_spin(&H, &hh->w, st);
     if (rb == HYP_OK) rb = build_core_path(&H, &hh->w, st);
+    if (rb == HYP_OK) rb = build_mixed_mm(&H, &hh->w, st);
     if (rb != HYP_OK) {
       hyp_ham_destroy(hh);
       return rb;
@@ -2494,6 +2633,9 @@ hyp_status hyp_ham_destroy(hyp_ham hh) {
     (void)hipFree(hh->w.k_rowany[sp]);
   }
   (void)hipFree(hh->w.k_Y);
+  (void)hipFree(hh->w.m_ent);
+  (void)hipFree(hh->w.m_code);
+  (void)hipFree(hh->w.m_nt);
   (void)hipFree(hh->w.k_sel);
   (void)hipFree(hh->w.c_bpos);
   (void)hipFree(hh->w.c_blist);

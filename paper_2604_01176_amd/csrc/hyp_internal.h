@@ -231,6 +231,15 @@ __device__ inline void dma16(uint32_t lds_wave, const void* src) {
       : "memory");
 }
 
+// 4 bytes per lane, as dma16.
+__device__ inline void dma4(uint32_t lds_wave, const void* src) {
+  uint32_t save;
+  asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %2, off\n\ts_mov_b32 m0, %0"
+               : "=&s"(save)
+               : "s"(lds_wave), "v"(src)
+               : "memory");
+}
+
 // Stage chunk blocks blk[k] (k-th group of nt blocks) of one FP64 row.
 __device__ inline void stage_blocks(uint32_t buf, const double* row, const int (&blk)[kCPerThread], int nb, int tid,
                                     int nt) {
@@ -300,6 +309,17 @@ struct HamWork {
   int k_band[2] = {0, 0};
   double* k_Y = nullptr;
   bool k_ok = false;
+  // mixed pass on the matrix cores (row-independent tables, per chunk c,
+  // alpha orbital e and 16-column tile j): m_ent[((c*16 + e)*3 + j)*16 + u]
+  // the source column of slot u (chunk column | alpha string << 8),
+  // m_code[((c*16 + e)*3 + j)*64 + lane] the lane's four targets (16 bits
+  // each: target rank | alpha-beta sign << 14 | single-dressing sign << 15;
+  // 0x3fff: none), m_nt[c*16 + e] the tile count
+  uint32_t* m_ent = nullptr;
+  uint64_t* m_code = nullptr;
+  uint8_t* m_nt = nullptr;
+  int m_qr = 0;
+  bool m_ok = false;
   // compact staging tables of the mixed pass (768-column chunks); c_ok when
   // every chunk fits a buffer
   uint16_t* c_bpos = nullptr;
