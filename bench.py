@@ -50,6 +50,8 @@ def kernel_flops(name, m):
     dim, sa, sb = m["dim"], m["sa"], m["sb"]
     if name == "k_mixed":
         return 2.0 * dim * (sa * sb + sa + sb + 1), "alu"
+    if name == "k_mixed_m":  # the same products on the FP64 matrix cores
+        return 2.0 * dim * (sa * sb + sa + sb + 1), "mfma"
     if name == "k_ss_apply":  # mean of the alpha- and the beta-row launch
         return 2.0 * dim * (1 + (sa + m["dda"] + sb + m["ddb"]) / 2), "alu"
     if name in ("k_tdens", "k_tdens_rows"):
@@ -89,7 +91,7 @@ def roofline(name, ms, m):
 
 
 # source file of each kernel whose counters are committed
-KERNEL_SOURCES = {"k_mixed": "hamiltonian.hip", "k_ss_apply": "hamiltonian.hip", "k_transpose": "hamiltonian.hip",
+KERNEL_SOURCES = {"k_mixed": "hamiltonian.hip", "k_mixed_m": "hamiltonian.hip", "k_ss_apply": "hamiltonian.hip", "k_transpose": "hamiltonian.hip",
                   "k_ss_core": "hamiltonian.hip", "k_ss_apply_sparse": "hamiltonian.hip",
                   "k_ssg_compact": "hamiltonian.hip", "k_tdens_rows": "sweep.hip", "k_tdens_rows_final": "sweep.hip",
                   "k_gram_grad": "sweep.hip", "k_core_gram_a": "core_gram.hip", "k_core_gram_b": "core_gram.hip",
@@ -319,7 +321,7 @@ def main():
     # is missing or stale)
     # (bytes per launch of each H psi kernel x its launches per product; the
     # same-spin pass runs in column bands, several launches per product)
-    hk = [k for k in ("k_mixed", "k_ss_core", "k_ss_apply", "k_ss_apply_sparse", "k_transpose") if k in prof]
+    hk = [k for k in ("k_mixed", "k_mixed_m", "k_ss_core", "k_ss_apply", "k_ss_apply_sparse", "k_transpose") if k in prof]
     hb = {k: measured_traffic(w.name, k) for k in hk}
     hpsi_hbm = None
     if hk and all(v is not None for v in hb.values()):

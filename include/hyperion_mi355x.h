@@ -133,7 +133,9 @@ int hyp_ham_is_structured(hyp_ham h);
  * the fastest for later hyp_apply_h calls on h in that storage type (FP64
  * and FP32 keep separate widths) and returns it.  In FP64 the 768-thread
  * candidate is the compact, double-buffered mixed pass wherever its staging
- * tables exist (see hyp_set_row_staging).  Overwrites sigma_dev.  A
+ * tables exist (see hyp_set_row_staging).  Where the mixed pass runs on the
+ * matrix cores (hyp_set_mixed_matrix_cores) it has no width to tune: the
+ * call times that form and returns 1024.  Overwrites sigma_dev.  A
  * generic (non-structured) Hamiltonian returns 0 threads. */
 hyp_status hyp_tune_apply_h(hyp_ham h, hyp_dtype dtype, const void* psi_dev, void* sigma_dev,
                             int reps, void* stream, int* best_threads, double* best_ms);

@@ -2176,6 +2176,13 @@ static hyp_status run_structured(Ham* Hm, HamWork* W, const void* psi, void* sig
 }
 
 // The mixed pass (adds the two same-spin partials).
+// The matrix-core form serves this Hamiltonian and storage size.
+static bool mixed_mm_applies(const Sector* S, const HamWork* W, size_t tsize) {
+  const size_t lds = (size_t)S->da * 8 + (tsize == 8 ? sizeof(MixedMMLds<double>) : sizeof(MixedMMLds<float>));
+  return g_mixed_mm != 0 && W->m_ok && lds <= kMMLdsMax &&
+         (g_mixed_mm == 1 || (size_t)S->dim * 8 > kMMAutoBytes);
+}
+
 template <typename T>
 static hyp_status run_mixed(Ham* Hm, HamWork* W, const void* psi, void* sigma, uint32_t* nz_b, hipStream_t st) {
   Sector* S = Hm->sec;
@@ -2199,16 +2206,15 @@ static hyp_status run_mixed(Ham* Hm, HamWork* W, const void* psi, void* sigma, u
   const int nt = Hm->threads[sizeof(T) == 4 ? 1 : 0];
   ma.nchunk = (da + nt - 1) / nt;
   const size_t mshm = (size_t)da * 8;  // the output row in FP64
-  if (g_mixed_mm != 0 && W->m_ok && mshm + sizeof(MixedMMLds<T>) <= kMMLdsMax &&
-      (g_mixed_mm == 1 || (size_t)S->dim * 8 > kMMAutoBytes)) {
+  if (mixed_mm_applies(S, W, sizeof(T))) {
     const bool vec = ((uintptr_t)psi & 15u) == 0 && ((size_t)da * sizeof(T)) % 16 == 0;
     const void* kf = vec ? (const void*)k_mixed_m<T, 1> : (const void*)k_mixed_m<T, 0>;
     HYP_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mshm));
     if (vec)
-      HYP_LAUNCH("k_mixed", (k_mixed_m<T, 1>), dim3((unsigned)db), dim3(1024), mshm, st, ma, W->m_ent, W->m_code,
+      HYP_LAUNCH("k_mixed_m", (k_mixed_m<T, 1>), dim3((unsigned)db), dim3(1024), mshm, st, ma, W->m_ent, W->m_code,
                  W->m_nt, W->m_qr, W->m_qr / kMMSeg);
     else
-      HYP_LAUNCH("k_mixed", (k_mixed_m<T, 0>), dim3((unsigned)db), dim3(1024), mshm, st, ma, W->m_ent, W->m_code,
+      HYP_LAUNCH("k_mixed_m", (k_mixed_m<T, 0>), dim3((unsigned)db), dim3(1024), mshm, st, ma, W->m_ent, W->m_code,
                  W->m_nt, W->m_qr, W->m_qr / kMMSeg);
     HYP_HIP(hipGetLastError());
     return HYP_OK;
@@ -2663,6 +2669,27 @@ hyp_status hyp_tune_apply_h(hyp_ham hh, hyp_dtype dtype, const void* psi, void* 
   hipStream_t st = (hipStream_t)stream;
   const int da = (int)H->sec->da;
   static const int cand[] = {128, 256, 384, 512, 640, 768, 896, 1024};
+  if (mixed_mm_applies(H->sec, &hh->w, dtype == HYP_F32 ? 4 : 8)) {
+    // the matrix-core form (1024 threads per beta row) takes no width: time it
+    hipEvent_t e0, e1;
+    HYP_HIP(hipEventCreate(&e0));
+    HYP_HIP(hipEventCreate(&e1));
+    hyp_status r = apply_h_internal(hh, dtype, psi, sigma, st);
+    if (r == HYP_OK) HYP_HIP(hipEventRecord(e0, st));
+    for (int i = 0; i < reps && r == HYP_OK; ++i) r = apply_h_internal(hh, dtype, psi, sigma, st);
+    float ms = 0.f;
+    if (r == HYP_OK) {
+      HYP_HIP(hipEventRecord(e1, st));
+      HYP_HIP(hipEventSynchronize(e1));
+      HYP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != HYP_OK) return r;
+    *best_threads = 1024;
+    *best_ms = ms / reps;
+    return HYP_OK;
+  }
   hipEvent_t e0, e1;
   HYP_HIP(hipEventCreate(&e0));
   HYP_HIP(hipEventCreate(&e1));

@@ -29,3 +29,9 @@ def test_models_at_32_qubits():
     assert abs(r["frac"] - r["achieved"] / 78.6) < 1e-3
     assert abs(r["lds"]["achieved"] - flops / 2 * 16 / 0.218 / 1e12) < 0.05
     assert abs(bench.LDS_PEAK_TBS - 78.6432) < 1e-3
+    # the same products on the FP64 matrix cores: same flops, bound by the
+    # matrix peak (equal to the vector peak on this chip), no LDS-per-product figure
+    f_m, b_m = bench.kernel_flops("k_mixed_m", m)
+    assert b_m == "mfma" and f_m == flops
+    r = bench.roofline("k_mixed_m", 76.8, m)
+    assert r["bound"] == "mfma" and "lds" not in r and abs(r["achieved"] - flops / 0.0768 / 1e12) < 0.01
