@@ -56,6 +56,8 @@ def kernel_flops(name, m):
         return 2.0 * dim * (1 + (sa + m["dda"] + sb + m["ddb"]) / 2), "alu"
     if name in ("k_tdens", "k_tdens_rows"):
         return 2.0 * dim * (sa + sb * (sa + 1)), "alu"
+    if name == "k_tdens_m":  # the same products on the FP64 matrix cores
+        return 2.0 * dim * (sa + sb * (sa + 1)), "mfma"
     if name in ("k_core_gram_a", "k_core_gram_b"):
         # 2 flops per (core, slot i, slot j, column): the S x S block of every
         # (N-2)-electron core over the other spin's strings
@@ -93,7 +95,8 @@ def roofline(name, ms, m):
 # source file of each kernel whose counters are committed
 KERNEL_SOURCES = {"k_mixed": "hamiltonian.hip", "k_mixed_m": "hamiltonian.hip", "k_ss_apply": "hamiltonian.hip", "k_transpose": "hamiltonian.hip",
                   "k_ss_core": "hamiltonian.hip", "k_ss_apply_sparse": "hamiltonian.hip",
-                  "k_ssg_compact": "hamiltonian.hip", "k_tdens_rows": "sweep.hip", "k_tdens_rows_final": "sweep.hip",
+                  "k_ssg_compact": "hamiltonian.hip", "k_tdens_rows": "sweep.hip", "k_tdens_m": "sweep.hip",
+                  "k_tm_final": "sweep.hip", "k_tdens_rows_final": "sweep.hip",
                   "k_gram_grad": "sweep.hip", "k_core_gram_a": "core_gram.hip", "k_core_gram_b": "core_gram.hip",
                   "k_gram_transpose": "core_gram.hip", "k_rotate": "pool.hip", "k_dot_partial_f64": "sector.hip"}
 
@@ -300,7 +303,7 @@ def main():
     sweep_kernels = ("k_pool_grad", "k_sum_chunks", "k_tdens", "k_tdens_reduce_ab", "k_tdens_reduce_a",
                      "k_tdens_final", "k_tdens_rows", "k_tdens_rows_final", "k_eb_rows", "k_gram_grad",
                      "k_tdens_grad", "k_core_gram_a", "k_core_gram_b", "k_gram_transpose", "k_gram_widen",
-                     "k_zero_u32", "k_support", "k_list_nz", "k_rows_compact")
+                     "k_zero_u32", "k_support", "k_list_nz", "k_rows_compact", "k_tdens_m", "k_tm_final")
     sweep_ms = sum(prof.get(k, (0.0, 0))[0] for k in sweep_kernels) / args.steps
 
     # the learned screen's gradient phase on the same state (network trained

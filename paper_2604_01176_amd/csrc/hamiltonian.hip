@@ -1764,7 +1764,6 @@ static int g_ss_cores = 2;      // process-wide: FP64 same-spin doubles through 
                                 // built, 2 where built and the FP64 state exceeds kCoreAutoBytes
 static int g_mixed_mm = 2;      // process-wide: mixed pass on the matrix cores (k_mixed_m): 0 off, 1 where
                                 // the row fits LDS, 2 where it fits and the state exceeds kMMAutoBytes
-constexpr size_t kMMAutoBytes = size_t(64) << 20;
 static int g_ss_groups = 2;     // process-wide: FP64 same-spin pass over grouped lists with this many
                                 // 64-column tiles per four-wave workgroup (1, 2 or 4); 0: per-row lists
 
@@ -2760,6 +2759,7 @@ namespace hyp {
 Ham* ham_of(hyp_ham h) { return h ? &h->h : nullptr; }
 HamWork* work_of(hyp_ham h) { return h ? &h->w : nullptr; }
 bool support_skip() { return g_support_skip != 0; }
+int mixed_mm_mode() { return g_mixed_mm; }
 
 hyp_status apply_h_internal(hyp_ham hh, hyp_dtype dtype, const void* psi, void* sigma,
                             hipStream_t st) {

@@ -367,6 +367,11 @@ hyp_status apply_h_internal(hyp_ham h, hyp_dtype dt, const void* psi, void* sigm
 bool prefer_full_sweep(const Sector* S, int64_t n_ops);
 // process-wide support-skipping switch (hyp_set_support_skip)
 bool support_skip();
+// Process-wide switch of the alpha-beta products on the matrix cores
+// (hyp_set_mixed_matrix_cores): 0 off, 1 where they fit, 2 where they fit and
+// the FP64 state exceeds kMMAutoBytes.
+int mixed_mm_mode();
+constexpr size_t kMMAutoBytes = size_t(64) << 20;
 // psi's support flags ([db] beta rows, then [da] alpha columns), device
 // scratch of the sweep valid until its next use on this device
 hyp_status support_flags(Sector* S, hyp_dtype dt, const void* psi, const uint32_t** flags, hipStream_t st);

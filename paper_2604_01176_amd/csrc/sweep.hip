@@ -630,6 +630,276 @@ __global__ void k_tdens_rows_final(const double* part, int n_eb, int n_id, int n
   }
 }
 
+// ------------------------------------------ transition values on matrix cores
+//
+// The singles and alpha-beta doubles of the sweep per target beta row I_b
+// as dense products.  Stage the row's kept beta-single sources J_k (k < 64,
+// ordered beta excitation eb_k from J_k to I_b, pool sign s_k) as
+// P[k][t] = psi[J_k][t] and the target row sigma[I_b][.] whole in LDS.  For
+// alpha orbital e (wave e) and source strings t holding e,
+//   X_e[i][k] = sum_t A_e[i][t] P[k][t],
+//   A_e[i][t] = (alpha pool sign of (i, e) at s) sigma[I_b][s],  s = t - e + i,
+// is a (16 x n) x (n x 64) product on v_mfma_f64_16x16x4_f64 (A operand:
+// lane l row i = l & 15, column t of step slot l >> 4; B operand: stage
+// k = 16 b + (l & 15) of the same column), and
+//   Tab[(i, e)][eb_k] += s_k X_e[i][k]  (i empty in t),
+//   Tb[eb_k] += s_k X_e[e][k]  (row i = e: A = sigma[I_b][t], counted at the
+//               lowest occupied orbital of t only, so each t once; the empty
+//               string, which has none, at orbital 0),
+//   Ta[(i, e)] += sum_t A_e[i][t] psi[I_b][t]  (the row's own amplitudes).
+// Each of kTMWG persistent workgroups adds its rows into a partial table of
+// its own, every entry of which only one wave touches, rows in a fixed
+// order, a row's additions complete before the next row's; a fixed-order
+// pass sums the partials: the results are reproducible bit for bit.
+constexpr int kTMSeg = 16;                 // columns per segment
+constexpr int kTMSegs = 3;                 // segments per chunk, from three regions of the alpha space
+constexpr int kTMCols = kTMSeg * kTMSegs;  // columns per chunk
+constexpr int kTMLd = kTMCols + 1;         // staged row stride: a column read by 16 stages hits 16 bank pairs
+constexpr int kTMWG = 256;                 // persistent workgroups
+constexpr int kTMPart = kBins * kBins + kBins + 16 * kBins;  // partial: Tab | Ta | Tb per orbital
+__host__ __device__ inline int tm_column(int c, int l, int qr) {
+  return (l / kTMSeg) * qr + c * kTMSeg + l % kTMSeg;
+}
+
+template <typename T>
+struct TMLds {
+  T P[2][65][kTMLd];          // rows < 64: kept beta-single sources (zero past them); row 64: the own row
+  uint32_t lst[16][kTMCols];  // per wave: chunk column | alpha string << 8, columns with its orbital occupied
+  int32_t rlo[256], rhi[256]; // alpha rank tables
+  int2 stage[64];             // (source rank, eb | pool sign << 16)
+  int nstage;
+  int own;
+};
+
+struct TMArgs {
+  const void* psi;
+  const void* sig;
+  int M, nb, da, db, qr, nch;
+  const uint32_t* astr;
+  const RankTables* arank;
+  const uint32_t* bstr;
+  const RankTables* brank;
+  const uint32_t* row_nz;  // support flags of psi's beta rows, or null
+  double* part;            // [gridDim][kTMPart]
+  int fsign;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_tdens_m(TMArgs a) {
+  typedef double f64x4 __attribute__((ext_vector_type(4)));
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ __align__(16) TMLds<T> L;
+  T* srow = (T*)smem;  // [da]: the target row of sigma
+  const int M = a.M, da = a.da;
+  const uint32_t bmask = (1u << M) - 1u;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int e = w;
+  const bool ew = e < M;
+  double* part = a.part + (size_t)blockIdx.x * kTMPart;
+  double* pTa = part + kBins * kBins;
+  double* pTb = pTa + kBins;
+  for (int x = tid; x < kTMPart; x += 1024) part[x] = 0.0;
+  if (tid < 256) {
+    L.rlo[tid] = a.arank->lo[tid];
+    L.rhi[tid] = a.arank->hi[tid];
+  }
+  const T* psi = (const T*)a.psi;
+  const T* sig = (const T*)a.sig;
+  // staging pieces: 4 bytes, kPPR per row, 64 per copy, kIPR copies per row
+  constexpr int kPPR = kTMCols * (int)sizeof(T) / 4;
+  constexpr int kIPR = (kPPR + 63) / 64;
+  constexpr int kNI = 65 * kIPR;  // copies per buffer
+  int gpart[kIPR];                // chunk-0 column of the lane's piece in part j of a row, -1 past the row
+  int wpart[kIPR];                // byte within the element
+#pragma unroll
+  for (int j = 0; j < kIPR; ++j) {
+    const int piece = j * 64 + lane;
+    const int lb = piece * 4;
+    gpart[j] = piece < kPPR ? tm_column(0, lb / (int)sizeof(T), a.qr) : -1;
+    wpart[j] = lb % (int)sizeof(T);
+  }
+  const int i_a = lane & 15;  // A-operand row
+  // pair bin of (i_a, e), and the orbitals strictly between them
+  const int pbin = (max(i_a, e) * (max(i_a, e) - 1) / 2 + min(i_a, e)) * 2 + (i_a > e ? 1 : 0);
+  const uint32_t btw = (i_a < M && i_a != e && ew) ? betw(min(i_a, e), max(i_a, e)) : 0u;
+  // target of (i_a, e) from t: t ^ flip (t itself for i_a = e)
+  const uint32_t flip = (i_a == e) ? 0u : (1u << e) ^ (1u << i_a);
+  // alpha string of chunk column `lane` | 1 << 31 (0 past the columns)
+  auto string_of = [&](int c) -> uint32_t {
+    const int g = tm_column(c, lane, a.qr);
+    return (lane < kTMCols && g < da) ? (a.astr[g] | 0x80000000u) : 0u;
+  };
+  for (int brow = blockIdx.x; brow < a.db; brow += gridDim.x) {
+    __syncthreads();  // the previous row is done with the staging buffers and the sigma row
+    const uint32_t bs = a.bstr[brow];
+    const int nbemp = M - a.nb, nbs = a.nb * nbemp;
+    if (tid < 64) {
+      const int jb = tid;
+      bool keep = false;
+      int2 ent = make_int2(0, 0);
+      if (jb < nbs) {
+        const int io = jb / nbemp, ie = jb % nbemp;
+        uint32_t occ = bs, emp = ~bs & bmask;
+        for (int j = 0; j < io; ++j) occ &= occ - 1;
+        for (int j = 0; j < ie; ++j) emp &= emp - 1;
+        const int i = __ffs(occ) - 1, ee = __ffs(emp) - 1;
+        const int p = min(i, ee), q = max(i, ee);
+        const uint32_t src = bs ^ (1u << i) ^ (1u << ee);
+        const int eb = (q * (q - 1) / 2 + p) * 2 + (i == q ? 1 : 0);
+        const uint32_t sg = __popc(betw(p, q) & src) & (uint32_t)a.fsign;
+        const int r2 = a.brank->lo[src & 255u] + a.brank->hi[(src >> 8) & 255u];
+        ent = make_int2(r2, eb | (int)(sg << 16));
+        keep = !a.row_nz || a.row_nz[r2] != 0u;
+      }
+      const uint64_t m = __ballot(keep);
+      const uint64_t below = (jb == 0) ? 0ull : (~0ull >> (64 - jb));
+      if (keep) L.stage[__popcll(m & below)] = ent;
+      if (jb == 0) {
+        L.nstage = __popcll(m);
+        L.own = (!a.row_nz || a.row_nz[brow] != 0u) ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    const int nst = L.nstage;
+    const bool own = L.own != 0;
+    if (nst == 0 && !own) continue;
+    const int nblk = (nst + 15) >> 4;  // 16-stage MFMA blocks
+    for (int x = tid; x < 2 * 65 * kTMLd; x += 1024) {
+      const int r = (x / kTMLd) % 65;
+      if ((r >= nst && r < 64) || (r == 64 && !own)) (&L.P[0][0][0])[x] = T(0);
+    }
+    // the sigma row (its copies complete before the barrier of chunk 0)
+    stage_row_lds(srow, sig + (int64_t)brow * da, da * (int)sizeof(T), tid, 1024);
+    auto issue = [&](int c, int bf) {
+      for (int ins = w; ins < kNI; ins += 16) {
+        const int row = ins / kIPR, j = ins % kIPR;
+        if (row < nst || (row == 64 && own)) {
+          const int src = row == 64 ? brow : L.stage[row].x;
+          const uint32_t dst =
+              (uint32_t)__builtin_amdgcn_readfirstlane(lds_addr(&L.P[bf][row][0]) + (uint32_t)j * 256u);
+          int gp = -1;
+          int wp = 0;
+#pragma unroll
+          for (int jj = 0; jj < kIPR; ++jj)
+            if (jj == j) {
+              gp = gpart[jj];
+              wp = wpart[jj];
+            }
+          const int g = gp + c * kTMSeg;
+          if (gp >= 0 && g < da) dma4(dst, (const char*)(psi + (int64_t)src * da + g) + wp);
+        }
+      }
+    };
+    f64x4 acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double oacc = 0.0;
+    const uint32_t srow_a = lds_addr(srow);
+    uint32_t tv = string_of(0);
+    issue(0, 0);
+    for (int c = 0; c < a.nch; ++c) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();  // chunk c in its buffer; every wave done with chunk c - 1
+      uint32_t tvn = 0u;
+      if (c + 1 < a.nch) {
+        tvn = string_of(c + 1);
+        issue(c + 1, (c + 1) & 1);
+      }
+      // the wave's columns with its orbital occupied (wave 0 also takes the
+      // empty string)
+      const uint32_t tc = tv & 0xffffu;
+      const bool bit = ew && (tv >> 31) && (((tc >> e) & 1u) || (tc == 0u && e == 0));
+      const uint64_t m = __ballot(bit);
+      const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+      if (bit) L.lst[w][__popcll(m & below)] = (uint32_t)lane | (tc << 8);
+      const int n = __popcll(m);
+      tv = tvn;
+      const uint32_t pb = lds_addr(&L.P[c & 1][i_a][0]);  // stage i_a of block 0
+      const uint32_t po = lds_addr(&L.P[c & 1][64][0]);   // the own row
+      const int nsteps = (n + 3) >> 2;
+      // one step: the A element (sigma at the target of (i_a, e) from the
+      // column's string t, with its sign; zero where there is none) and the
+      // B operands of the column, all of whose reads wait only for the list
+      auto a_elem = [&](int st, uint32_t& cl) -> double {
+        const int slot = 4 * st + (lane >> 4);
+        const bool sv_ok = slot < n;
+        const uint32_t ent = L.lst[w][sv_ok ? slot : 0];
+        cl = ent & 63u;
+        const uint32_t t = ent >> 8;
+        const uint32_t s2 = t ^ flip;
+        const int low = t ? __ffs(t) - 1 : 0;  // lowest occupied orbital (0 for the empty string)
+        const bool ok = sv_ok && i_a < M && (i_a == e ? low == e : (((t >> e) & 1u) && !((t >> i_a) & 1u)));
+        const int r0 = L.rlo[s2 & 255u] + L.rhi[(s2 >> 8) & 255u];  // any byte indexes the tables
+        const double v = (double)lds_load<T>(srow_a + (uint32_t)(ok ? r0 : 0) * (uint32_t)sizeof(T));
+        return ok ? (((__popc(btw & s2) & a.fsign) != 0) ? -v : v) : 0.0;
+      };
+      // (rows past the kept stages are zero: their reads are harmless; the
+      // products of whole blocks past them are skipped)
+#pragma unroll 1
+      for (int st = 0; st < nsteps; ++st) {
+        uint32_t cl;
+        const double av = a_elem(st, cl);
+        double bv[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          bv[b] = (double)lds_load<T>(pb + (uint32_t)(16 * b * kTMLd + (int)cl) * (uint32_t)sizeof(T));
+        if (own) oacc += av * (double)lds_load<T>(po + cl * (uint32_t)sizeof(T));
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (b < nblk) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[b], acc[b], 0, 0, 0);
+      }
+    }
+    // the row's values into the partial (element q of lane l: row
+    // (l >> 4) + 4q, stage 16 b + (l & 15))
+    oacc += __shfl_xor(oacc, 16, 64);
+    oacc += __shfl_xor(oacc, 32, 64);
+    if (ew) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int k = 16 * b + (lane & 15);
+        if (b < nblk && k < nst) {
+          const int info = L.stage[k].y;
+          const int eb = info & 0xffff;
+          const bool neg = (info >> 16) & 1;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = (lane >> 4) + 4 * q;
+            const double v = neg ? -acc[b][q] : acc[b][q];
+            if (i == e)
+              unsafeAtomicAdd(pTb + e * kBins + eb, v);
+            else if (i < M)
+              unsafeAtomicAdd(part + (size_t)((max(i, e) * (max(i, e) - 1) / 2 + min(i, e)) * 2 + (i > e ? 1 : 0)) *
+                                         kBins + eb,
+                              v);
+          }
+        }
+      }
+      if (own && lane < M && lane != e) unsafeAtomicAdd(pTa + pbin, oacc);
+    }
+  }
+}
+
+// Fixed-order sums of the workgroups' partials.
+__global__ void k_tm_final(const double* __restrict__ part, int nwg, double* Ta, double* Tb, double* Tab) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < kBins * kBins) {
+    double t = 0.0;
+    for (int g = 0; g < nwg; ++g) t += part[(size_t)g * kTMPart + x];
+    Tab[x] = t;
+  } else if (x < kBins * kBins + kBins) {
+    const int ea = x - kBins * kBins;
+    double t = 0.0;
+    for (int g = 0; g < nwg; ++g) t += part[(size_t)g * kTMPart + kBins * kBins + ea];
+    Ta[ea] = t;
+  } else if (x < kBins * kBins + 2 * kBins) {
+    const int eb = x - kBins * kBins - kBins;
+    double t = 0.0;
+    for (int g = 0; g < nwg; ++g)
+      for (int e = 0; e < 16; ++e) t += part[(size_t)g * kTMPart + kBins * kBins + kBins + e * kBins + eb];
+    Tb[eb] = t;
+  }
+}
+
 // (source row, target row | sign << 31) of every ordered beta single
 // excitation eb = (created ci, annihilated ae): source rows hold ae and not
 // ci, in colex order over the other orbitals.  One thread per (eb, k).
@@ -1006,6 +1276,8 @@ struct TScratch {
   };
   CTab ctab[8];
   int ctab_next = 0;
+  // matrix-core transition values: the workgroups' partials
+  double* tm_part = nullptr;
 };
 TScratch g_ts[64];
 }  // namespace
@@ -1094,6 +1366,53 @@ static int64_t binom64(int m, int k) {
   int64_t r = 1;
   for (int i = 1; i <= k; ++i) r = r * (m - k + i) / i;
   return r;
+}
+
+// The singles and alpha-beta doubles on the matrix cores (k_tdens_m) where
+// the target row fits LDS and the mode switch takes them; *done false
+// otherwise.
+static hyp_status tdens_mm(Sector* S, hyp_dtype dt, TScratch& ts, const void* psi, const void* sig, double* Ta,
+                           double* Tb, double* Tab, bool skip, hipStream_t st, bool* done) {
+  *done = false;
+  const int mode = mixed_mm_mode();
+  const int M = S->M, na = S->na, da = (int)S->da, db = (int)S->db;
+  const size_t tsz = dt == HYP_F64 ? 8 : 4;
+  const size_t lds = (size_t)da * tsz + (tsz == 8 ? sizeof(TMLds<double>) : sizeof(TMLds<float>));
+  if (mode == 0 || M > kMaxOrb || da <= 0 || db <= 0 || lds > 160 * 1024 ||
+      (mode == 2 && (size_t)S->dim * 8 <= kMMAutoBytes))
+    return HYP_OK;
+  const int qr = (da + kTMCols - 1) / kTMCols * kTMSeg;  // columns per region
+  if (!ts.tm_part) HYP_HIP(hipMalloc(&ts.tm_part, (size_t)kTMWG * kTMPart * sizeof(double)));
+  TMArgs a;
+  a.psi = psi;
+  a.sig = sig;
+  a.M = M;
+  a.nb = S->nb;
+  a.da = da;
+  a.db = db;
+  a.qr = qr;
+  a.nch = qr / kTMSeg;
+  a.astr = S->d_astr;
+  a.arank = S->d_arank;
+  a.bstr = S->d_bstr;
+  a.brank = S->d_brank;
+  a.row_nz = skip ? ts.nz : nullptr;
+  a.part = ts.tm_part;
+  a.fsign = pool_kind() == 0 ? 1 : 0;
+  const int nwg = std::min(kTMWG, db);
+  const size_t shm = (size_t)da * tsz;
+  if (dt == HYP_F64) {
+    HYP_HIP(hipFuncSetAttribute((const void*)k_tdens_m<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    HYP_LAUNCH("k_tdens_m", k_tdens_m<double>, dim3((unsigned)nwg), dim3(1024), shm, st, a);
+  } else {
+    HYP_HIP(hipFuncSetAttribute((const void*)k_tdens_m<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    HYP_LAUNCH("k_tdens_m", k_tdens_m<float>, dim3((unsigned)nwg), dim3(1024), shm, st, a);
+  }
+  HYP_LAUNCH("k_tm_final", k_tm_final, dim3((kBins * kBins + 2 * kBins + 255) / 256), dim3(256), 0, st, ts.tm_part,
+             nwg, Ta, Tb, Tab);
+  HYP_HIP(hipGetLastError());
+  *done = true;
+  return HYP_OK;
 }
 
 // Transition values of singles and alpha-beta doubles (Ta, Tb, Tab) by the
@@ -1284,7 +1603,9 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
     HYP_LAUNCH("k_list_nz", k_list_nz, dim3(1), dim3(1024), 0, st, ts.nz + db, (int)da, ts.lists + db, ts.cnt + 1);
   }
   if (!bins) {
-    hyp_status r = tdens_rows(S, dt, ts, psi, sig, Ta, Tb, Tab, skip, st);
+    bool done = false;
+    hyp_status r = tdens_mm(S, dt, ts, psi, sig, Ta, Tb, Tab, skip, st, &done);
+    if (r == HYP_OK && !done) r = tdens_rows(S, dt, ts, psi, sig, Ta, Tb, Tab, skip, st);
     if (r != HYP_OK) return r;
   } else {
   const size_t need = tdens_bytes(S);

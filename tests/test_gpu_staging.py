@@ -30,13 +30,17 @@ def _dev(v, dtype=torch.float64):
 
 
 def _grads(hyp, S, ops, psi, sig, staging):
+    # the two staging forms of the row-batched kernel (the matrix-core form
+    # switched off)
     try:
+        hyp.set_mixed_matrix_cores(False)
         hyp.set_sweep_mode("tdens")
         hyp.set_row_staging(staging)
         return hyp.hyp_pool_gradients(S, ops, psi, sig).cpu().numpy()
     finally:
         hyp.set_row_staging("compact")
         hyp.set_sweep_mode("auto")
+        hyp.set_mixed_matrix_cores()
 
 
 # (11,5), (12,6), (12,5), (13,6), (14,7): even alpha dimension above 448,
