@@ -820,30 +820,35 @@ __global__ void __launch_bounds__(1024) k_tdens_m(TMArgs a) {
       // one step: the A element (sigma at the target of (i_a, e) from the
       // column's string t, with its sign; zero where there is none) and the
       // B operands of the column, all of whose reads wait only for the list
-      auto a_elem = [&](int st, uint32_t& cl) -> double {
+      // one step: the A element (sigma at the target of (i_a, e) from the
+      // column's string t, with its sign; zero where there is none) and the
+      // B operands of the column, all of whose reads wait only for the list
+      // entry, which is read a step ahead
+      auto entry = [&](int st) -> uint32_t {
         const int slot = 4 * st + (lane >> 4);
-        const bool sv_ok = slot < n;
-        const uint32_t ent = L.lst[w][sv_ok ? slot : 0];
-        cl = ent & 63u;
-        const uint32_t t = ent >> 8;
-        const uint32_t s2 = t ^ flip;
-        const int low = t ? __ffs(t) - 1 : 0;  // lowest occupied orbital (0 for the empty string)
-        const bool ok = sv_ok && i_a < M && (i_a == e ? low == e : (((t >> e) & 1u) && !((t >> i_a) & 1u)));
-        const int r0 = L.rlo[s2 & 255u] + L.rhi[(s2 >> 8) & 255u];  // any byte indexes the tables
-        const double v = (double)lds_load<T>(srow_a + (uint32_t)(ok ? r0 : 0) * (uint32_t)sizeof(T));
-        return ok ? (((__popc(btw & s2) & a.fsign) != 0) ? -v : v) : 0.0;
+        return L.lst[w][slot < n ? slot : 0] | (slot < n ? 0x80000000u : 0u);
       };
+      uint32_t ent = entry(0);
       // (rows past the kept stages are zero: their reads are harmless; the
       // products of whole blocks past them are skipped)
 #pragma unroll 1
       for (int st = 0; st < nsteps; ++st) {
-        uint32_t cl;
-        const double av = a_elem(st, cl);
+        const uint32_t cur = ent;
+        ent = entry(st + 1);
+        const uint32_t cl = cur & 63u;
+        const uint32_t t = (cur >> 8) & 0xffffu;
+        const uint32_t s2 = t ^ flip;
+        const int low = t ? __ffs(t) - 1 : 0;  // lowest occupied orbital (0 for the empty string)
+        const bool ok = (cur >> 31) && i_a < M && (i_a == e ? low == e : (((t >> e) & 1u) && !((t >> i_a) & 1u)));
+        const int r0 = L.rlo[s2 & 255u] + L.rhi[(s2 >> 8) & 255u];  // any byte indexes the tables
         double bv[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b)
           bv[b] = (double)lds_load<T>(pb + (uint32_t)(16 * b * kTMLd + (int)cl) * (uint32_t)sizeof(T));
-        if (own) oacc += av * (double)lds_load<T>(po + cl * (uint32_t)sizeof(T));
+        const double pw = own ? (double)lds_load<T>(po + cl * (uint32_t)sizeof(T)) : 0.0;
+        const double v = (double)lds_load<T>(srow_a + (uint32_t)(ok ? r0 : 0) * (uint32_t)sizeof(T));
+        const double av = ok ? (((__popc(btw & s2) & a.fsign) != 0) ? -v : v) : 0.0;
+        oacc += av * pw;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
           if (b < nblk) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[b], acc[b], 0, 0, 0);
