@@ -208,21 +208,25 @@ hyp_status hyp_set_same_spin_groups(int tiles);
  * order.  Process-wide; HYP_ERR_ARG unless mode is 0, 1 or 2. */
 hyp_status hyp_set_same_spin_cores(int mode);
 
-/* Mixed alpha-beta part of hyp_apply_h (the paper's "Sparse State-Vector
- * Emulation" product; both storage types) as dense products on FP64 MFMA.
- * For one beta row, with its beta-single source rows staged as the K x D_a
- * matrix P (K <= 64), the doubles and the beta singles' alpha dressing that
- * empty alpha orbital e of a source string are Z_e = A_e P over the source
- * strings with e occupied (A_e: 16 x K, the row's alpha-beta coefficients
- * for the pairs (i, e) and the dressing of e), each element added to its
- * output string s = t - e + i of the row held in LDS.  mode = 2 (default)
- * takes it where the output row fits LDS (D_a <= 14,000 at M <= 16) and the
- * FP64 state exceeds 64 MiB (28 qubits and up); 1 wherever the row fits; 0
- * never (k_mixed /
- * k_mixed_c of hyp_set_row_staging).  The additions into the row land in no
- * fixed order, so this form reproduces sigma to rounding, not bit for bit;
- * mode 0 restores bitwise reproducibility.  Process-wide; HYP_ERR_ARG
- * unless mode is 0, 1 or 2. */
+/* The alpha-beta products of hyp_apply_h and of hyp_pool_gradients on FP64
+ * MFMA (the paper's "Sparse State-Vector Emulation" product and its pool
+ * gradients; both storage types).  H psi: for one beta row, with its
+ * beta-single source rows staged as the K x D_a matrix P (K <= 64), the
+ * doubles and the beta singles' alpha dressing that empty alpha orbital e of
+ * a source string are Z_e = A_e P over the source strings with e occupied
+ * (A_e: 16 x K, the row's alpha-beta coefficients for the pairs (i, e) and
+ * the dressing of e), each element added to its output string s = t - e + i
+ * of the row held in LDS; the additions land in no fixed order, so sigma is
+ * reproducible to rounding, not bit for bit.  Sweep: per target beta row,
+ * X_e = A_e P^T with A_e the signed sigma values gathered at the targets,
+ * added into per-workgroup partials that are summed in a fixed order
+ * (reproducible bit for bit).  mode = 2 (default) takes the H psi form where
+ * the output row fits LDS (D_a <= 14,000 at M <= 16) and the FP64 state
+ * exceeds 64 MiB (28 qubits and up), the sweep form where its target row
+ * fits and the state exceeds 256 MiB (32 qubits); 1 both wherever they fit;
+ * 0 never (k_mixed / k_mixed_c and k_tdens_rows of hyp_set_row_staging,
+ * bitwise reproducible).  Process-wide; HYP_ERR_ARG unless mode is 0, 1 or
+ * 2. */
 hyp_status hyp_set_mixed_matrix_cores(int mode);
 
 /* Materialised sector Hamiltonian in CSR form, the paper's storage of H

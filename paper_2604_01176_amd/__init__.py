@@ -326,10 +326,11 @@ def set_same_spin_cores(mode="auto"):
 
 
 def set_mixed_matrix_cores(mode="auto"):
-    """hyp_set_mixed_matrix_cores: the mixed alpha-beta pass as dense
-    products on the matrix cores: "auto" (default; where the output row fits
-    LDS and the FP64 state exceeds 64 MiB), True (wherever the row fits) or
-    False (the bitwise-reproducible k_mixed / k_mixed_c)."""
+    """hyp_set_mixed_matrix_cores: the alpha-beta products of H psi and of
+    the sweep as dense products on the matrix cores: "auto" (default; H psi
+    from 64 MiB FP64 states, the sweep from 256 MiB, where the row fits LDS),
+    True (wherever the row fits) or False (the bitwise-reproducible
+    k_mixed / k_mixed_c and k_tdens_rows)."""
     m = 2 if mode == "auto" else (1 if mode else 0)
     check(_lib.load().hyp_set_mixed_matrix_cores(m))
 

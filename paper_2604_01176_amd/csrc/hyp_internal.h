@@ -369,9 +369,10 @@ bool prefer_full_sweep(const Sector* S, int64_t n_ops);
 bool support_skip();
 // Process-wide switch of the alpha-beta products on the matrix cores
 // (hyp_set_mixed_matrix_cores): 0 off, 1 where they fit, 2 where they fit and
-// the FP64 state exceeds kMMAutoBytes.
+// the FP64 state exceeds kMMAutoBytes (H psi) or kTMAutoBytes (the sweep).
 int mixed_mm_mode();
 constexpr size_t kMMAutoBytes = size_t(64) << 20;
+constexpr size_t kTMAutoBytes = size_t(256) << 20;
 // psi's support flags ([db] beta rows, then [da] alpha columns), device
 // scratch of the sweep valid until its next use on this device
 hyp_status support_flags(Sector* S, hyp_dtype dt, const void* psi, const uint32_t** flags, hipStream_t st);

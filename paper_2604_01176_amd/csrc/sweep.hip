@@ -1374,8 +1374,10 @@ static int64_t binom64(int m, int k) {
 }
 
 // The singles and alpha-beta doubles on the matrix cores (k_tdens_m) where
-// the target row fits LDS and the mode switch takes them; *done false
-// otherwise.
+// the target row fits LDS and the mode switch takes them (in auto mode above
+// kTMAutoBytes: below, the state stays in the Infinity Cache and the
+// row-batched kernel is faster, 5.3 against 7.8 ms at 28 qubits); *done
+// false otherwise.
 static hyp_status tdens_mm(Sector* S, hyp_dtype dt, TScratch& ts, const void* psi, const void* sig, double* Ta,
                            double* Tb, double* Tab, bool skip, hipStream_t st, bool* done) {
   *done = false;
@@ -1384,7 +1386,7 @@ static hyp_status tdens_mm(Sector* S, hyp_dtype dt, TScratch& ts, const void* ps
   const size_t tsz = dt == HYP_F64 ? 8 : 4;
   const size_t lds = (size_t)da * tsz + (tsz == 8 ? sizeof(TMLds<double>) : sizeof(TMLds<float>));
   if (mode == 0 || M > kMaxOrb || da <= 0 || db <= 0 || lds > 160 * 1024 ||
-      (mode == 2 && (size_t)S->dim * 8 <= kMMAutoBytes))
+      (mode == 2 && (size_t)S->dim * 8 <= kTMAutoBytes))
     return HYP_OK;
   const int qr = (da + kTMCols - 1) / kTMCols * kTMSeg;  // columns per region
   if (!ts.tm_part) HYP_HIP(hipMalloc(&ts.tm_part, (size_t)kTMWG * kTMPart * sizeof(double)));

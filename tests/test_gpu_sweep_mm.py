@@ -135,7 +135,7 @@ def test_matrix_core_sweep_28q(hyp):
     psi_h = synth.random_state(S.dim, 4)
     psi = torch.from_numpy(psi_h).cuda()
     sig = H.apply(psi)
-    got = _grads(hyp, S, ops, psi, sig, "auto").cpu().numpy()
+    got = _grads(hyp, S, ops, psi, sig, True).cpu().numpy()  # (auto takes the row-batched kernel below 256 MiB)
     rows = _grads(hyp, S, ops, psi, sig, False).cpu().numpy()
     scale = max(1.0, np.abs(rows).max())
     print(f"[sweep-mm] 28q: max difference {np.abs(got - rows).max() / scale:.2e} of the largest gradient", flush=True)
