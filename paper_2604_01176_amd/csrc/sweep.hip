@@ -182,6 +182,7 @@ __global__ void __launch_bounds__(768) k_tdens(TArgs a) {
 struct TRArgs {
   const void* psi;
   const void* sig;
+  const int* sel;     // device-side choice under support skipping: these kernels run where *sel == 0 (null: always)
   int M, da, db;
   const uint32_t* astr;
   const RankTables* arank;
@@ -258,6 +259,7 @@ __global__ void __launch_bounds__(512) k_tdens_rows(TRArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* s_row = (T*)smem;
   __shared__ double s_red[8];
+  if (a.sel && *a.sel != 0) return;
   const int M = a.M;
   const uint32_t amask = (1u << M) - 1u;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -451,6 +453,7 @@ __global__ void __launch_bounds__(512) k_tdens_rows_c(TRArgs a, const uint16_t* 
                                                       const uint16_t* __restrict__ blist,
                                                       const int* __restrict__ nblk_c, int nblk,
                                                       uint32_t pairs_off) {
+  if (a.sel && *a.sel != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_red[8];
   const int M = a.M;
@@ -612,7 +615,8 @@ __global__ void __launch_bounds__(512) k_tdens_rows_c(TRArgs a, const uint16_t* 
 //   Tab[ea][eb] = sum over chunks of slot eb's bin ea,  Tb[eb] = the same of
 //   its identity bin,  Ta[ea] = sum over the identity slices and chunks.
 __global__ void k_tdens_rows_final(const double* part, int n_eb, int n_id, int nchunk, double* Ta, double* Tb,
-                                   double* Tab) {
+                                   double* Tab, const int* sel) {
+  if (sel && *sel != 0) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < kBins * kStageW) {
     const int eb = i / kStageW, x = i % kStageW;
@@ -674,6 +678,7 @@ struct TMLds {
 struct TMArgs {
   const void* psi;
   const void* sig;
+  const int* sel;          // device-side choice under support skipping: runs where *sel == 1 (null: always)
   int M, nb, da, db, qr, nch;
   const uint32_t* astr;
   const RankTables* arank;
@@ -695,6 +700,7 @@ __global__ void __launch_bounds__(1024) k_tdens_m(TMArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int e = w;
   const bool ew = e < M;
+  if (a.sel && *a.sel != 1) return;
   double* part = a.part + (size_t)blockIdx.x * kTMPart;
   double* pTa = part + kBins * kBins;
   double* pTb = pTa + kBins;
@@ -885,7 +891,9 @@ __global__ void __launch_bounds__(1024) k_tdens_m(TMArgs a) {
 }
 
 // Fixed-order sums of the workgroups' partials.
-__global__ void k_tm_final(const double* __restrict__ part, int nwg, double* Ta, double* Tb, double* Tab) {
+__global__ void k_tm_final(const double* __restrict__ part, int nwg, double* Ta, double* Tb, double* Tab,
+                           const int* sel) {
+  if (sel && *sel != 1) return;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x < kBins * kBins) {
     double t = 0.0;
@@ -902,6 +910,23 @@ __global__ void k_tm_final(const double* __restrict__ part, int nwg, double* Ta,
     for (int g = 0; g < nwg; ++g)
       for (int e = 0; e < 16; ++e) t += part[(size_t)g * kTMPart + kBins * kBins + kBins + e * kBins + eb];
     Tb[eb] = t;
+  }
+}
+
+// Under support skipping: the matrix-core form where at least a quarter of
+// the beta rows hold amplitude (*sel = 1), else the row-batched kernel,
+// whose work follows the kept row pairs (*sel = 0).
+__global__ void __launch_bounds__(1024) k_tm_select(const uint32_t* __restrict__ flags, int nrow, int* __restrict__ sel) {
+  __shared__ int s_n[16];
+  int n = 0;
+  for (int r = threadIdx.x; r < nrow; r += blockDim.x) n += flags[r] != 0u ? 1 : 0;
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_down(n, o, 64);
+  if ((threadIdx.x & 63) == 0) s_n[threadIdx.x >> 6] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_n[w];
+    *sel = 4 * t >= nrow ? 1 : 0;
   }
 }
 
@@ -1281,8 +1306,10 @@ struct TScratch {
   };
   CTab ctab[8];
   int ctab_next = 0;
-  // matrix-core transition values: the workgroups' partials
+  // matrix-core transition values: the workgroups' partials and the
+  // device-side choice of form under support skipping
   double* tm_part = nullptr;
+  int* tm_sel = nullptr;
 };
 TScratch g_ts[64];
 }  // namespace
@@ -1379,8 +1406,9 @@ static int64_t binom64(int m, int k) {
 // row-batched kernel is faster, 5.3 against 7.8 ms at 28 qubits); *done
 // false otherwise.
 static hyp_status tdens_mm(Sector* S, hyp_dtype dt, TScratch& ts, const void* psi, const void* sig, double* Ta,
-                           double* Tb, double* Tab, bool skip, hipStream_t st, bool* done) {
+                           double* Tb, double* Tab, bool skip, hipStream_t st, bool* done, const int** sel) {
   *done = false;
+  *sel = nullptr;
   const int mode = mixed_mm_mode();
   const int M = S->M, na = S->na, da = (int)S->da, db = (int)S->db;
   const size_t tsz = dt == HYP_F64 ? 8 : 4;
@@ -1390,9 +1418,17 @@ static hyp_status tdens_mm(Sector* S, hyp_dtype dt, TScratch& ts, const void* ps
     return HYP_OK;
   const int qr = (da + kTMCols - 1) / kTMCols * kTMSeg;  // columns per region
   if (!ts.tm_part) HYP_HIP(hipMalloc(&ts.tm_part, (size_t)kTMWG * kTMPart * sizeof(double)));
+  if (!ts.tm_sel) HYP_HIP(hipMalloc(&ts.tm_sel, sizeof(int)));
   TMArgs a;
   a.psi = psi;
   a.sig = sig;
+  a.sel = nullptr;
+  if (skip) {
+    // a sparse support takes the row-batched kernel (chosen on the device)
+    HYP_LAUNCH("k_tm_select", k_tm_select, dim3(1), dim3(1024), 0, st, ts.nz, db, ts.tm_sel);
+    a.sel = ts.tm_sel;
+    *sel = ts.tm_sel;
+  }
   a.M = M;
   a.nb = S->nb;
   a.da = da;
@@ -1416,7 +1452,7 @@ static hyp_status tdens_mm(Sector* S, hyp_dtype dt, TScratch& ts, const void* ps
     HYP_LAUNCH("k_tdens_m", k_tdens_m<float>, dim3((unsigned)nwg), dim3(1024), shm, st, a);
   }
   HYP_LAUNCH("k_tm_final", k_tm_final, dim3((kBins * kBins + 2 * kBins + 255) / 256), dim3(256), 0, st, ts.tm_part,
-             nwg, Ta, Tb, Tab);
+             nwg, Ta, Tb, Tab, a.sel);
   HYP_HIP(hipGetLastError());
   *done = true;
   return HYP_OK;
@@ -1425,10 +1461,11 @@ static hyp_status tdens_mm(Sector* S, hyp_dtype dt, TScratch& ts, const void* ps
 // Transition values of singles and alpha-beta doubles (Ta, Tb, Tab) by the
 // row-batched kernel.
 static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* psi, const void* sig,
-                             double* Ta, double* Tb, double* Tab, bool skip, hipStream_t st) {
+                             double* Ta, double* Tb, double* Tab, bool skip, hipStream_t st, const int* sel) {
   TRArgs a;
   a.psi = psi;
   a.sig = sig;
+  a.sel = sel;
   a.M = S->M;
   a.da = (int)S->da;
   a.db = (int)S->db;
@@ -1515,7 +1552,7 @@ static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* 
       HYP_LAUNCH("k_tdens_rows", k_tdens_rows_c, dim3((unsigned)nblk), dim3(nt), cshm, st, a, ct->bpos, ct->blist,
                  ct->nb, (a.da + 1) / 2, (uint32_t)pairs_off);
       HYP_LAUNCH("k_tdens_rows_final", k_tdens_rows_final, dim3((kBins * kStageW + kBins + 255) / 256), dim3(256),
-                 0, st, ts.rpart, a.n_eb, a.n_id, a.nchunk, Ta, Tb, Tab);
+                 0, st, ts.rpart, a.n_eb, a.n_id, a.nchunk, Ta, Tb, Tab, sel);
       return HYP_OK;
     }
   }
@@ -1531,7 +1568,7 @@ static hyp_status tdens_rows(Sector* S, hyp_dtype dt, TScratch& ts, const void* 
     HYP_LAUNCH("k_tdens_rows", k_tdens_rows<float>, dim3((unsigned)nblk), dim3(nt), shm, st, a);
   }
   HYP_LAUNCH("k_tdens_rows_final", k_tdens_rows_final, dim3((kBins * kStageW + kBins + 255) / 256), dim3(256), 0,
-             st, ts.rpart, a.n_eb, a.n_id, a.nchunk, Ta, Tb, Tab);
+             st, ts.rpart, a.n_eb, a.n_id, a.nchunk, Ta, Tb, Tab, sel);
   return HYP_OK;
 }
 
@@ -1611,8 +1648,10 @@ hyp_status launch_tdens(Sector* S, hyp_dtype dt, const hyp_exc* ops, int64_t n_o
   }
   if (!bins) {
     bool done = false;
-    hyp_status r = tdens_mm(S, dt, ts, psi, sig, Ta, Tb, Tab, skip, st, &done);
-    if (r == HYP_OK && !done) r = tdens_rows(S, dt, ts, psi, sig, Ta, Tb, Tab, skip, st);
+    const int* sel = nullptr;
+    hyp_status r = tdens_mm(S, dt, ts, psi, sig, Ta, Tb, Tab, skip, st, &done, &sel);
+    // with a device-side choice both forms are launched; the other exits at once
+    if (r == HYP_OK && (!done || sel)) r = tdens_rows(S, dt, ts, psi, sig, Ta, Tb, Tab, skip, st, sel);
     if (r != HYP_OK) return r;
   } else {
   const size_t need = tdens_bytes(S);

@@ -148,3 +148,32 @@ def test_matrix_core_sweep_28q(hyp):
     pick = np.array(sorted(pick))
     ref = oracle.pool_gradients(w.n_orb, w.n_alpha, w.n_beta, cre[pick], ann[pick], psi_h, sig.cpu().numpy())
     assert np.abs(got[pick] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("frac", [0.2, 0.3])
+def test_device_choice_under_support_skipping(hyp, frac):
+    """With support skipping the form is chosen on the device: the
+    matrix-core kernel where at least a quarter of the beta rows hold
+    amplitude, the row-batched one below (both launched, the other exits).
+    States just under and over the quarter give the oracle's gradients."""
+    M, na, nb = 9, 4, 5
+    S, H, cre, ann = _problem(hyp, M, na, nb, 977)
+    ops = hyp.exc_tensor(cre, ann)
+    rng = np.random.default_rng(31)
+    rows = rng.choice(S.db, max(1, int(round(frac * S.db))), replace=False)
+    psi_h = np.zeros(S.dim)
+    for r in rows:
+        psi_h[r * S.da:(r + 1) * S.da] = rng.standard_normal(S.da)
+    psi_h /= np.linalg.norm(psi_h)
+    psi = torch.from_numpy(psi_h).cuda()
+    sig = H.apply(psi)
+    hyp.set_support_skip(True)
+    got = _grads(hyp, S, ops, psi, sig, True).cpu().numpy()
+    ref = oracle.pool_gradients(M, na, nb, cre, ann, psi_h, sig.cpu().numpy())
+    assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    hyp.set_support_skip(False)
+    try:
+        full = _grads(hyp, S, ops, psi, sig, True).cpu().numpy()  # every row: the matrix-core kernel
+    finally:
+        hyp.set_support_skip(True)
+    assert np.abs(got - full).max() <= 1e-13 * max(1.0, np.abs(full).max())
