@@ -789,6 +789,9 @@ struct MixedArgs {
   const RankTables* brank;
   int nchunk;             // column chunks per beta row
   const uint32_t* row_nz; // support flags of psi's beta rows, or null (every row taken)
+  // device-side choice under support skipping: k_mixed_m runs where
+  // *sel == 1, k_mixed / k_mixed_c where *sel == 0 (null: no choice)
+  const int* sel;
   HamDev H;
 };
 
@@ -828,6 +831,7 @@ template <typename T>
 __global__ void __launch_bounds__(1024) k_mixed(MixedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* s_row = (T*)smem;  // [da + 1]: the staged row and a zero slot
+  if (a.sel && *a.sel != 0) return;
   __shared__ MixedLds<T> L;
   T* const s_fab = L.fab;
   double* const s_srow = L.srow;
@@ -1089,6 +1093,7 @@ __global__ void __launch_bounds__(768) k_mixed_c(MixedArgs a, const uint16_t* __
                                                  int nblk) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ MixedLdsC L;
+  if (a.sel && *a.sel != 0) return;
   const int M = a.M;
   const uint32_t amask = (1u << M) - 1u;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -1435,6 +1440,7 @@ __global__ void __launch_bounds__(1024) k_mixed_m(MixedArgs a, const uint32_t* _
   typedef double f64x4 __attribute__((ext_vector_type(4)));
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ __align__(16) MixedMMLds<T> L;
+  if (a.sel && *a.sel != 1) return;
   double* sig = (double*)smem;  // [da]: the row's alpha-beta part
   const int M = a.M, da = a.da;
   const uint32_t amask = (1u << M) - 1u;
@@ -1879,6 +1885,7 @@ static hyp_status build_mixed_mm(Ham* Hm, HamWork* W, hipStream_t st) {
   HYP_HIP(hipMalloc(&W->m_ent, (size_t)nce * kMMTiles * 16 * sizeof(uint32_t)));
   HYP_HIP(hipMalloc(&W->m_code, (size_t)nce * kMMTiles * 64 * sizeof(uint64_t)));
   HYP_HIP(hipMalloc(&W->m_nt, (size_t)nce));
+  HYP_HIP(hipMalloc(&W->m_sel, sizeof(int)));
   HYP_LAUNCH("k_mm_tables", k_mm_tables, dim3((unsigned)nce), dim3(64), 0, st, S->M, da, qr, S->d_astr, S->d_arank,
              Hm->dev.abJa, Hm->dev.sJ, W->m_ent, W->m_code, W->m_nt);
   HYP_HIP(hipGetLastError());
@@ -2202,10 +2209,17 @@ static hyp_status run_mixed(Ham* Hm, HamWork* W, const void* psi, void* sigma, u
   ma.brank = S->d_brank;
   ma.H = Hm->dev;
   ma.row_nz = nz_b;
+  ma.sel = nullptr;
   const int nt = Hm->threads[sizeof(T) == 4 ? 1 : 0];
   ma.nchunk = (da + nt - 1) / nt;
   const size_t mshm = (size_t)da * 8;  // the output row in FP64
   if (mixed_mm_applies(S, W, sizeof(T))) {
+    // under support skipping a sparse support takes the vector forms, whose
+    // work follows the kept stages (chosen on the device; both launched)
+    if (nz_b) {
+      HYP_LAUNCH("k_ss_select", k_ss_select, dim3(1), dim3(1024), 0, st, nz_b, db, W->m_sel);
+      ma.sel = W->m_sel;
+    }
     const bool vec = ((uintptr_t)psi & 15u) == 0 && ((size_t)da * sizeof(T)) % 16 == 0;
     const void* kf = vec ? (const void*)k_mixed_m<T, 1> : (const void*)k_mixed_m<T, 0>;
     HYP_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mshm));
@@ -2216,7 +2230,7 @@ static hyp_status run_mixed(Ham* Hm, HamWork* W, const void* psi, void* sigma, u
       HYP_LAUNCH("k_mixed_m", (k_mixed_m<T, 0>), dim3((unsigned)db), dim3(1024), mshm, st, ma, W->m_ent, W->m_code,
                  W->m_nt, W->m_qr, W->m_qr / kMMSeg);
     HYP_HIP(hipGetLastError());
-    return HYP_OK;
+    if (!ma.sel) return HYP_OK;
   }
   if (sizeof(T) == 8 && nt == kCMixedThreads && row_staging_compact() && W->c_ok && (da % 2) == 0 &&
       ((uintptr_t)psi & 15u) == 0) {
@@ -2641,6 +2655,7 @@ hyp_status hyp_ham_destroy(hyp_ham hh) {
   (void)hipFree(hh->w.m_ent);
   (void)hipFree(hh->w.m_code);
   (void)hipFree(hh->w.m_nt);
+  (void)hipFree(hh->w.m_sel);
   (void)hipFree(hh->w.k_sel);
   (void)hipFree(hh->w.c_bpos);
   (void)hipFree(hh->w.c_blist);

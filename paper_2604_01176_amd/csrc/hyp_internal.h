@@ -318,6 +318,7 @@ struct HamWork {
   uint32_t* m_ent = nullptr;
   uint64_t* m_code = nullptr;
   uint8_t* m_nt = nullptr;
+  int* m_sel = nullptr;  // support skipping: 1 matrix-core form, 0 k_mixed / k_mixed_c
   int m_qr = 0;
   bool m_ok = false;
   // compact staging tables of the mixed pass (768-column chunks); c_ok when

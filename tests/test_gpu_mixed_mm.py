@@ -159,3 +159,30 @@ def test_matrix_core_mixed_pass_workloads(hyp, name):
     assert np.abs(g_rows - ref_rows).max() <= 1e-12 * np.abs(ref_rows).max()
     del dp, got, det
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("frac", [0.2, 0.3])
+def test_device_choice_under_support_skipping(hyp, frac):
+    """With support skipping the mixed pass's form is chosen on the device:
+    the matrix-core kernel where at least a quarter of the beta rows hold
+    amplitude, k_mixed / k_mixed_c below (both launched, the other exits).
+    States just under and over the quarter give the oracle's sigma."""
+    M, na, nb = 10, 5, 4
+    S, H, (x, z, c) = _ham(hyp, M, na, nb, 955)
+    rng = np.random.default_rng(17)
+    rows = rng.choice(S.db, max(1, int(round(frac * S.db))), replace=False)
+    psi_h = np.zeros(S.dim)
+    for r in rows:
+        psi_h[r * S.da:(r + 1) * S.da] = rng.standard_normal(S.da)
+    psi_h /= np.linalg.norm(psi_h)
+    d = torch.from_numpy(psi_h).cuda()
+    ref = oracle.apply_h(M, na, nb, x, z, c, psi_h)
+    hyp.set_support_skip(True)
+    got = _apply(hyp, H, d, True).cpu().numpy()
+    hyp.set_support_skip(False)
+    try:
+        full = _apply(hyp, H, d, True).cpu().numpy()  # every row: the matrix-core kernel
+    finally:
+        hyp.set_support_skip(True)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.linalg.norm(got - full) <= 1e-14 * np.linalg.norm(full)
