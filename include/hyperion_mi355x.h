@@ -225,8 +225,12 @@ hyp_status hyp_set_same_spin_cores(int mode);
  * exceeds 64 MiB (28 qubits and up), the sweep form where its target row
  * fits and the state exceeds 256 MiB (32 qubits); 1 both wherever they fit;
  * 0 never (k_mixed / k_mixed_c and k_tdens_rows of hyp_set_row_staging,
- * bitwise reproducible).  Process-wide; HYP_ERR_ARG unless mode is 0, 1 or
- * 2. */
+ * bitwise reproducible).  With support skipping (hyp_set_support_skip) the
+ * form is chosen per call on the device: the matrix-core one where at least
+ * a quarter of psi's beta rows carry amplitude, the other below (both are
+ * launched and the unchosen one exits at once; no host synchronisation, so
+ * the calls stay capturable).  Process-wide; HYP_ERR_ARG unless mode is 0, 1
+ * or 2. */
 hyp_status hyp_set_mixed_matrix_cores(int mode);
 
 /* Materialised sector Hamiltonian in CSR form, the paper's storage of H
