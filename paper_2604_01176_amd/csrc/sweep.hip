@@ -730,6 +730,9 @@ __global__ void __launch_bounds__(1024) k_tdens_m(TMArgs a) {
   const uint32_t btw = (i_a < M && i_a != e && ew) ? betw(min(i_a, e), max(i_a, e)) : 0u;
   // target of (i_a, e) from t: t ^ flip (t itself for i_a = e)
   const uint32_t flip = (i_a == e) ? 0u : (1u << e) ^ (1u << i_a);
+  const uint32_t diag = (i_a == e) ? 1u : 0u;
+  const uint32_t lane_ok = (ew && i_a < M) ? 1u : 0u;
+  const uint32_t ebit = 1u << e, ibit = 1u << i_a;
   // alpha string of chunk column `lane` | 1 << 31 (0 past the columns)
   auto string_of = [&](int c) -> uint32_t {
     const int g = tm_column(c, lane, a.qr);
@@ -829,10 +832,34 @@ __global__ void __launch_bounds__(1024) k_tdens_m(TMArgs a) {
       // one step: the A element (sigma at the target of (i_a, e) from the
       // column's string t, with its sign; zero where there is none) and the
       // B operands of the column, all of whose reads wait only for the list
-      // entry, which is read a step ahead
+      // entry, which is read a step ahead.  The element's validity is formed
+      // without branches from the lane's masks.
       auto entry = [&](int st) -> uint32_t {
         const int slot = 4 * st + (lane >> 4);
         return L.lst[w][slot < n ? slot : 0] | (slot < n ? 0x80000000u : 0u);
+      };
+      auto step = [&](uint32_t cur, auto full) {
+        constexpr bool kFull = decltype(full)::value;
+        const uint32_t cl = cur & 63u;
+        const uint32_t t = (cur >> 8) & 0xffffu;
+        const uint32_t s2 = t ^ flip;
+        const uint32_t low = t ? (uint32_t)(__ffs(t) - 1) : 0u;  // lowest occupied orbital (0 for the empty string)
+        const uint32_t ok = (cur >> 31) & lane_ok &
+                            ((diag & (uint32_t)(low == (uint32_t)e)) |
+                             ((diag ^ 1u) & (uint32_t)((t & ebit) != 0u) & (uint32_t)((t & ibit) == 0u)));
+        const int r0 = L.rlo[s2 & 255u] + L.rhi[(s2 >> 8) & 255u];  // any byte indexes the tables
+        double bv[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          bv[b] = (double)lds_load<T>(pb + (uint32_t)(16 * b * kTMLd + (int)cl) * (uint32_t)sizeof(T));
+        const double pw = own ? (double)lds_load<T>(po + cl * (uint32_t)sizeof(T)) : 0.0;
+        const double v = (double)lds_load<T>(srow_a + (uint32_t)(ok ? r0 : 0) * (uint32_t)sizeof(T));
+        const double sv = ((__popc(btw & s2) & a.fsign) != 0) ? -v : v;
+        const double av = ok ? sv : 0.0;
+        oacc += av * pw;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (kFull || b < nblk) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[b], acc[b], 0, 0, 0);
       };
       uint32_t ent = entry(0);
       // (rows past the kept stages are zero: their reads are harmless; the
@@ -841,23 +868,7 @@ __global__ void __launch_bounds__(1024) k_tdens_m(TMArgs a) {
       for (int st = 0; st < nsteps; ++st) {
         const uint32_t cur = ent;
         ent = entry(st + 1);
-        const uint32_t cl = cur & 63u;
-        const uint32_t t = (cur >> 8) & 0xffffu;
-        const uint32_t s2 = t ^ flip;
-        const int low = t ? __ffs(t) - 1 : 0;  // lowest occupied orbital (0 for the empty string)
-        const bool ok = (cur >> 31) && i_a < M && (i_a == e ? low == e : (((t >> e) & 1u) && !((t >> i_a) & 1u)));
-        const int r0 = L.rlo[s2 & 255u] + L.rhi[(s2 >> 8) & 255u];  // any byte indexes the tables
-        double bv[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          bv[b] = (double)lds_load<T>(pb + (uint32_t)(16 * b * kTMLd + (int)cl) * (uint32_t)sizeof(T));
-        const double pw = own ? (double)lds_load<T>(po + cl * (uint32_t)sizeof(T)) : 0.0;
-        const double v = (double)lds_load<T>(srow_a + (uint32_t)(ok ? r0 : 0) * (uint32_t)sizeof(T));
-        const double av = ok ? (((__popc(btw & s2) & a.fsign) != 0) ? -v : v) : 0.0;
-        oacc += av * pw;
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          if (b < nblk) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[b], acc[b], 0, 0, 0);
+        step(cur, std::integral_constant<bool, false>());
       }
     }
     // the row's values into the partial (element q of lane l: row
