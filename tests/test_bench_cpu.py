@@ -35,3 +35,9 @@ def test_models_at_32_qubits():
     assert b_m == "mfma" and f_m == flops
     r = bench.roofline("k_mixed_m", 76.8, m)
     assert r["bound"] == "mfma" and "lds" not in r and abs(r["achieved"] - flops / 0.0768 / 1e12) < 0.01
+    # the transition values: 2 flops per (target, source) product, s_a + s_b (s_a + 1) per amplitude,
+    # on the matrix cores or the vector ALU (1.40 TFLOP at 32 qubits either way)
+    f_t, b_t = bench.kernel_flops("k_tdens_m", m)
+    f_r, b_r = bench.kernel_flops("k_tdens_rows", m)
+    assert b_t == "mfma" and b_r == "alu" and f_t == f_r
+    assert abs(f_t - 2 * m["dim"] * (64 + 64 * 65)) < 1 and abs(f_t / 1e12 - 1.40) < 0.01
